@@ -1,0 +1,209 @@
+"""ctypes front end of the FP64 CPU oracle (test infrastructure only).
+
+Only the test suite, the package smoke check and the benchmark's CPU-baseline leg may
+import this module.  It never touches the GPU library and the GPU library never calls it.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+from .build import LIB, build
+
+MU = 4.0 / 27.0
+
+
+class OrcView(C.Structure):
+    _fields_ = [("r_s", C.c_double), ("cam_pos", C.c_double * 3), ("cam_vel", C.c_double * 3),
+                ("cam_rot", C.c_double * 9), ("fov_y", C.c_double),
+                ("width", C.c_int32), ("height", C.c_int32),
+                ("disc_r_in", C.c_double), ("disc_r_out", C.c_double),
+                ("disc_T_law", C.c_int32), ("pad0", C.c_int32),
+                ("disc_T0", C.c_double), ("disc_T_exp", C.c_double),
+                ("disc_opacity", C.c_double), ("k_disc", C.c_double), ("k_star", C.c_double)]
+
+
+class OrcRay(C.Structure):
+    _fields_ = [("delta_prime", C.c_double), ("captured", C.c_int32), ("n_cross", C.c_int32),
+                ("u_cross", C.c_double * 4), ("phi_cross", C.c_double * 4),
+                ("branch", C.c_int32 * 4), ("steps", C.c_int32), ("pad0", C.c_int32)]
+
+
+PIXEL_DTYPE = np.dtype([
+    ("rgb", "<f8", 3), ("disc_rgb", "<f8", 3), ("star_rgb", "<f8", 3),
+    ("delta_prime", "<f8"), ("u_cross", "<f8", 2), ("e2_over_mu", "<f8"),
+    ("omega_ratio", "<f8"), ("d_cam", "<f8"), ("star_A", "<f8"), ("star_T", "<f8"),
+    ("delta", "<f8"), ("alpha", "<f8"), ("zeta", "<f8"),
+    ("x", "<i4"), ("y", "<i4"), ("n_cross", "<i4"), ("branch_bits", "<i4"),
+    ("captured", "<i4"), ("star_zeroed", "<i4"), ("degenerate", "<i4"), ("mip_level", "<i4"),
+])
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = C.CDLL(LIB)
+        dp = C.POINTER(C.c_double)
+        L.orc_apsis.restype = C.c_double
+        L.orc_apsis.argtypes = [C.c_double]
+        L.orc_deflection.restype = C.c_double
+        L.orc_deflection.argtypes = [C.c_double]
+        L.orc_u_at_phi.restype = C.c_double
+        L.orc_u_at_phi.argtypes = [C.c_double] * 4
+        L.orc_trace_exact.argtypes = [C.c_double] * 6 + [C.POINTER(OrcRay)]
+        L.orc_trace_table.argtypes = [dp, C.c_int32, dp, C.c_int32, C.c_int32] + \
+            [C.c_double] * 5 + [C.POINTER(OrcRay)]
+        L.orc_tables.argtypes = [C.c_int32, C.c_int32, C.c_int32, dp, dp, C.c_int]
+        L.orc_table_entry_D.argtypes = [C.c_int32, C.c_int32, C.c_int32, dp, dp, dp]
+        L.orc_table_entry_U.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, dp, dp, dp]
+        L.orc_band_radiance.argtypes = [C.c_double, dp]
+        L.orc_planck.restype = C.c_double
+        L.orc_planck.argtypes = [C.c_double, C.c_double]
+        L.orc_cubemap_texels.restype = C.c_int64
+        L.orc_cubemap_texels.argtypes = [C.c_int32]
+        fp = C.POINTER(C.c_float)
+        L.orc_cubemap_build.argtypes = [fp, fp, fp, C.c_int64, C.c_int32, dp]
+        L.orc_render_quads.argtypes = [C.POINTER(OrcView), dp, C.c_int32, dp, C.c_int32, dp,
+                                       C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.c_int64,
+                                       C.c_void_p, C.c_int]
+        L.orc_quad_poly_check.restype = C.c_double
+        L.orc_quad_poly_check.argtypes = [C.c_int]
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double)) if a is not None else None
+
+
+def threads() -> int:
+    return os.cpu_count() or 1
+
+
+def apsis(e2: float) -> float:
+    return lib().orc_apsis(e2)
+
+
+def deflection(e: float) -> float:
+    return lib().orc_deflection(e)
+
+
+def u_at_phi(u0: float, w0: float, phi: float, gr: float = 1.0) -> float:
+    return lib().orc_u_at_phi(u0, w0, phi, gr)
+
+
+def _ray_dict(r: OrcRay):
+    n = r.n_cross
+    return {"delta_prime": r.delta_prime, "captured": bool(r.captured), "n_cross": n,
+            "u": [r.u_cross[k] for k in range(n)], "phi": [r.phi_cross[k] for k in range(n)],
+            "branch": [r.branch[k] for k in range(n)], "steps": r.steps}
+
+
+def trace_exact(u_c, delta, alpha, u_ic, u_oc, gr=1.0):
+    r = OrcRay()
+    lib().orc_trace_exact(u_c, delta, alpha, u_ic, u_oc, gr, C.byref(r))
+    return _ray_dict(r)
+
+
+class Tables:
+    def __init__(self, d_n=512, u_ne=64, u_nphi=32, nthreads=None):
+        self.d_n, self.u_ne, self.u_nphi = d_n, u_ne, u_nphi
+        self.D = np.zeros((d_n, d_n), np.float64)
+        self.U = np.zeros((u_nphi, u_ne), np.float64)
+        rc = lib().orc_tables(d_n, u_ne, u_nphi, _dp(self.D), _dp(self.U), nthreads or threads())
+        if rc:
+            raise ValueError("orc_tables failed")
+
+    def trace(self, u_c, delta, alpha, u_ic, u_oc):
+        r = OrcRay()
+        lib().orc_trace_table(_dp(self.D), self.d_n, _dp(self.U), self.u_ne, self.u_nphi,
+                              u_c, delta, alpha, u_ic, u_oc, C.byref(r))
+        return _ray_dict(r)
+
+
+def table_entry_D(n, i, j):
+    v, e2, u = C.c_double(), C.c_double(), C.c_double()
+    if lib().orc_table_entry_D(n, i, j, C.byref(v), C.byref(e2), C.byref(u)):
+        raise ValueError("bad entry")
+    return v.value, e2.value, u.value
+
+
+def table_entry_U(ne, nphi, i, j):
+    v, e2, phi = C.c_double(), C.c_double(), C.c_double()
+    if lib().orc_table_entry_U(ne, nphi, i, j, C.byref(v), C.byref(e2), C.byref(phi)):
+        raise ValueError("bad entry")
+    return v.value, e2.value, phi.value
+
+
+def band_radiance(T: float) -> np.ndarray:
+    out = np.zeros(3, np.float64)
+    lib().orc_band_radiance(float(T), _dp(out))
+    return out
+
+
+def planck(lam: float, T: float) -> float:
+    return lib().orc_planck(lam, T)
+
+
+def cubemap(field, n0: int) -> np.ndarray:
+    """FP64 cubemap texels (all mip levels concatenated), shape (texels, 4)."""
+    n = len(field)
+    tex = np.zeros((lib().orc_cubemap_texels(n0), 4), np.float64)
+    dirs = np.ascontiguousarray(field.dirs, np.float32)
+    inten = np.ascontiguousarray(field.intensity, np.float32)
+    temp = np.ascontiguousarray(field.temperature, np.float32)
+    fp = C.POINTER(C.c_float)
+    rc = lib().orc_cubemap_build(dirs.ctypes.data_as(fp), inten.ctypes.data_as(fp),
+                                 temp.ctypes.data_as(fp), n, n0, _dp(tex))
+    if rc:
+        raise ValueError("orc_cubemap_build failed")
+    return tex
+
+
+def cubemap_level(tex: np.ndarray, n0: int, level: int) -> np.ndarray:
+    """View of one mip level as (6, nL, nL, 4)."""
+    off = sum(6 * (n0 >> l) ** 2 for l in range(level))
+    nl = n0 >> level
+    return tex[off:off + 6 * nl * nl].reshape(6, nl, nl, 4)
+
+
+def to_orc_view(v) -> OrcView:
+    o = OrcView()
+    o.r_s = v.r_s
+    o.cam_pos[:] = list(v.cam_pos)
+    o.cam_vel[:] = list(v.cam_vel)
+    o.cam_rot[:] = list(v.cam_rot)
+    o.fov_y = v.fov_y
+    o.width, o.height = v.width, v.height
+    o.disc_r_in, o.disc_r_out = v.disc_r_in, v.disc_r_out
+    o.disc_T_law = v.disc_T_law
+    o.disc_T0, o.disc_T_exp = v.disc_T0, v.disc_T_exp
+    o.disc_opacity, o.k_disc, o.k_star = v.disc_opacity, v.k_disc, v.k_star
+    return o
+
+
+def render_quads(view, quads: np.ndarray, cube: np.ndarray = None, n0: int = 0,
+                 tables: Tables = None, nthreads: int = None) -> np.ndarray:
+    """Render the 4 pixels of every quad (x0, y0); returns a PIXEL_DTYPE array (4 per quad)."""
+    q = np.ascontiguousarray(quads, np.int32)
+    nq = q.shape[0]
+    out = np.zeros(4 * nq, PIXEL_DTYPE)
+    ov = to_orc_view(view)
+    D = U = None
+    dn = une = unphi = 0
+    if tables is not None:
+        D, U, dn, une, unphi = tables.D, tables.U, tables.d_n, tables.u_ne, tables.u_nphi
+    rc = lib().orc_render_quads(C.byref(ov), _dp(cube) if cube is not None else None, n0,
+                                _dp(D), dn, _dp(U), une, unphi,
+                                q.ctypes.data_as(C.POINTER(C.c_int32)), nq,
+                                out.ctypes.data, nthreads or threads())
+    if rc:
+        raise ValueError("orc_render_quads rejected the view")
+    return out

@@ -1,0 +1,122 @@
+/*
+ * FP64 CPU oracle for the per-pixel black-hole beam tracer of Bruneton,
+ * "Real-time High-Quality Rendering of Non-Rotating Black Holes" (arXiv 2010.08735).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the slow, plain reference that the GPU
+ * library is checked against.  Only the test suite, the package smoke check and the
+ * benchmark's CPU-baseline leg may load it.  It shares no code, header, table or
+ * constant generator with the GPU library, and the GPU library never calls it.
+ *
+ * Units: Schwarzschild radius r_s = 1 and c = 1 (Section 3.1), u = 1/r.
+ *
+ * Two ways to trace a ray:
+ *   exact mode  -- the orbit equation u'' = 3/2 u^2 - u (Section 3.3, eq. rayequation) is
+ *                  integrated per ray with an adaptive Dormand-Prince 5(4) method and
+ *                  event location (escape, capture, disc-plane crossings);
+ *   table mode  -- deflection and intersection tables are filled by quadrature of the
+ *                  first integral at the texel centres (Section 3.3.2, Appendix A) and the
+ *                  paper's TraceRay procedure (Algorithm 1) reads them in FP64.
+ * Shading follows Sections 3.3.2 (stars, filtering), 3.3.3 (disc) and 3.4 (lensing,
+ * Doppler, beaming).  Parity status of every function is listed in its comment; every
+ * function here is pinned by a test that does not reuse this code.
+ */
+#ifndef BH_ORACLE_H
+#define BH_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC_MU (4.0 / 27.0)
+
+/* Camera + disc description, mirrors the GPU library's view record field by field. */
+typedef struct {
+  double r_s;
+  double cam_pos[3];
+  double cam_vel[3];
+  double cam_rot[9];      /* rows e_w, e_h, e_d; the camera looks along -e_d */
+  double fov_y;
+  int32_t width, height;
+  double disc_r_in, disc_r_out;
+  int32_t disc_T_law;     /* 0: T0 (r/3)^T_exp ; 1: T^4 ~ u^3 (1 - sqrt(3u)), peak T0 */
+  int32_t pad0;
+  double disc_T0, disc_T_exp;
+  double disc_opacity, k_disc, k_star;
+} orc_view;
+
+/* Result of tracing one ray in its orbital plane. */
+typedef struct {
+  double delta_prime;     /* escape angle from e_x' (INFINITY if captured)            */
+  int32_t captured;
+  int32_t n_cross;        /* crossings of the disc annulus, in order along the beam     */
+  double u_cross[4];
+  double phi_cross[4];    /* rotated azimuth of each crossing                           */
+  int32_t branch[4];      /* 0: before the apsis of the backward ray, 1: after it       */
+  int32_t steps;          /* accepted integrator steps (exact mode), 0 in table mode    */
+  int32_t pad0;
+} orc_ray;
+
+/* One rendered pixel with the diagnostics the parity mask needs. */
+typedef struct {
+  double rgb[3];
+  double disc_rgb[3];
+  double star_rgb[3];
+  double delta_prime;     /* INFINITY if captured */
+  double u_cross[2];      /* first and second crossing in beam order (0 if absent) */
+  double e2_over_mu;
+  double omega_ratio;     /* lensing amplification Omega/Omega' (0 if undefined) */
+  double d_cam;           /* frequency ratio received/emitted for static stars */
+  double star_A;          /* filtered intensity sum */
+  double star_T;          /* intensity-weighted temperature of the footprint */
+  double delta, alpha, zeta;
+  int32_t x, y;
+  int32_t n_cross;
+  int32_t branch_bits;    /* bit k set: a crossing on branch k was found */
+  int32_t captured;
+  int32_t star_zeroed;    /* a member of the 2x2 quad is captured */
+  int32_t degenerate;     /* ray radial or ray plane == disc plane */
+  int32_t mip_level;      /* -1 if no gather happened */
+} orc_pixel;
+
+/* ---- geometry of rays (Section 3.3.1) --------------------------------------------- */
+double orc_apsis(double e2);                         /* eq. uapsis, e2 < mu */
+int orc_trace_exact(double u_c, double delta, double alpha, double u_ic, double u_oc,
+                    double gr, orc_ray* out);        /* gr = 1: Schwarzschild, 0: flat */
+double orc_deflection(double e);                     /* 2 phi_a - pi for a ray from infinity */
+double orc_u_at_phi(double u0, double w0, double phi, double gr); /* u(phi) along a ray */
+
+/* ---- tables by quadrature (table mode) ---------------------------------------------- */
+int orc_tables(int32_t d_n, int32_t u_ne, int32_t u_nphi, double* D, double* U, int nthreads);
+int orc_table_entry_D(int32_t d_n, int32_t i, int32_t j, double* value, double* e2, double* u);
+int orc_table_entry_U(int32_t u_ne, int32_t u_nphi, int32_t i, int32_t j, double* value,
+                      double* e2, double* phi);
+int orc_trace_table(const double* D, int32_t d_n, const double* U, int32_t u_ne, int32_t u_nphi,
+                    double u_c, double delta, double alpha, double u_ic, double u_oc, orc_ray* out);
+
+/* ---- emission (Sections 3.3.3, 3.4.2) ----------------------------------------------- */
+void orc_band_radiance(double T, double out[3]);     /* R, G, B box bands, W m^-2 sr^-1 */
+double orc_planck(double lambda, double T);          /* spectral radiance B_lambda(T) */
+
+/* ---- star cubemap (Section 3.3.2 "Emitted light") ------------------------------------ */
+int64_t orc_cubemap_texels(int32_t n0);              /* texel count over all mip levels */
+int orc_cubemap_build(const float* dirs, const float* inten, const float* temp, int64_t n,
+                      int32_t n0, double* texels);   /* texels: orc_cubemap_texels * 4 */
+
+/* ---- whole pixels --------------------------------------------------------------------- */
+/* quads: (x0, y0) pairs with even coordinates; out: 4 pixels per quad in the order
+ * (x0,y0), (x0+1,y0), (x0,y0+1), (x0+1,y0+1).  D == NULL selects exact mode.
+ * cubemap == NULL means a black sky. */
+int orc_render_quads(const orc_view* v, const double* cubemap, int32_t n0,
+                     const double* D, int32_t d_n, const double* U, int32_t u_ne,
+                     int32_t u_nphi, const int32_t* quads, int64_t nq, orc_pixel* out,
+                     int nthreads);
+
+/* quadrature helper exposed for its own pin (Gauss-Legendre exactness) */
+double orc_quad_poly_check(int degree);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

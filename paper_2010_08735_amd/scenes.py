@@ -1,0 +1,244 @@
+"""Seeded synthetic inputs for the black-hole beam tracer.
+
+Both the HIP library and the FP64 oracle consume the arrays produced here; this module
+only draws random numbers and lays out input records.  It contains none of the
+renderer's arithmetic (no geodesics, tables, Doppler factors, shading or filtering).
+
+Units: lengths in Schwarzschild radii (r_s = 1) unless a view says otherwise, speeds in
+units of c, angles in radians, temperatures in kelvin.
+
+Input recipes (all RNG draws use numpy's PCG64 ``default_rng(seed)`` in the order listed):
+
+* star field: z ~ U(-1, 1), azimuth ~ U(0, 2 pi), intensity = 10**U(-4, 0),
+  temperature ~ U(3000, 12000) K, each drawn as a whole array in that order;
+* camera orientation: the camera looks at the apparent direction of the hole centre
+  (the hole direction carried from the static frame into the moving camera's frame), with
+  the image "up" axis the projection of +z (or +x when the camera looks along z).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Sequence, Tuple
+
+import numpy as np
+
+T_LAW_POWER = 0   # T' = T0 * (r' / (3 r_s)) ** T_exp
+T_LAW_PAPER = 1   # T'^4 proportional to u^3 (1 - sqrt(3u)), peak value T0
+
+
+@dataclasses.dataclass
+class View:
+    """One camera + disc configuration (mirrors ``bh_view`` of include/bh.h)."""
+    cam_pos: Tuple[float, float, float]
+    cam_vel: Tuple[float, float, float]
+    cam_rot: Tuple[float, ...]          # 9 values, rows e_w, e_h, e_d (camera looks along -e_d)
+    width: int
+    height: int
+    fov_y: float = math.radians(60.0)
+    r_s: float = 1.0
+    disc_r_in: float = 3.0
+    disc_r_out: float = 12.0
+    disc_T_law: int = T_LAW_POWER
+    disc_T0: float = 1.0e4
+    disc_T_exp: float = -0.75
+    disc_opacity: float = 1.0
+    k_disc: float = 1.0e-7
+    k_star: float = 1.0
+
+    def pixels(self) -> int:
+        return self.width * self.height
+
+
+@dataclasses.dataclass
+class StarField:
+    """Point stars: unit directions (n,3), intensities (n,) and temperatures (n,), float32."""
+    dirs: np.ndarray
+    intensity: np.ndarray
+    temperature: np.ndarray
+    seed: int
+
+    def __len__(self) -> int:
+        return int(self.intensity.shape[0])
+
+
+def star_field(n: int, seed: int) -> StarField:
+    rng = np.random.default_rng(seed)
+    z = rng.uniform(-1.0, 1.0, n)
+    az = rng.uniform(0.0, 2.0 * math.pi, n)
+    inten = 10.0 ** rng.uniform(-4.0, 0.0, n)
+    temp = rng.uniform(3000.0, 12000.0, n)
+    s = np.sqrt(np.maximum(0.0, 1.0 - z * z))
+    dirs = np.stack([s * np.cos(az), s * np.sin(az), z], axis=1)
+    return StarField(dirs.astype(np.float32), inten.astype(np.float32),
+                     temp.astype(np.float32), seed)
+
+
+# ----------------------------------------------------------------------------------------
+# camera placement helpers (input recipe only)
+
+def spherical_position(r: float, theta: float, phi: float) -> np.ndarray:
+    return r * np.array([math.sin(theta) * math.cos(phi),
+                         math.sin(theta) * math.sin(phi),
+                         math.cos(theta)])
+
+
+def _unit(v: np.ndarray) -> np.ndarray:
+    return v / np.linalg.norm(v)
+
+
+def azimuthal_direction(pos: np.ndarray) -> np.ndarray:
+    """Unit vector along increasing azimuth at ``pos`` (z-axis positions fall back to +y)."""
+    t = np.array([-pos[1], pos[0], 0.0])
+    n = np.linalg.norm(t)
+    return t / n if n > 1e-12 else np.array([0.0, 1.0, 0.0])
+
+
+def apparent_hole_direction(pos: np.ndarray, vel: np.ndarray) -> np.ndarray:
+    """Direction of the hole centre as seen in the frame of a camera moving at ``vel``.
+
+    Recipe for aiming views; the renderer and the oracle do their own frame changes."""
+    n_s = -_unit(pos)
+    v2 = float(vel @ vel)
+    if v2 < 1e-30:
+        return n_s
+    v = math.sqrt(v2)
+    vh = vel / v
+    g = 1.0 / math.sqrt(1.0 - v2)
+    nv = float(n_s @ vh)
+    n_c = (n_s + ((g - 1.0) * nv + g * v) * vh) / (g * (1.0 + v * nv))
+    return _unit(n_c)
+
+
+def look_rotation(look: np.ndarray) -> Tuple[float, ...]:
+    """Rows e_w, e_h, e_d for a camera looking along ``look`` with +z (else +x) as up."""
+    e_d = -_unit(look)
+    up = np.array([0.0, 0.0, 1.0])
+    if abs(float(up @ e_d)) > 0.999:
+        up = np.array([1.0, 0.0, 0.0])
+    e_h = _unit(up - (up @ e_d) * e_d)
+    e_w = np.cross(e_h, e_d)
+    return tuple(float(x) for x in np.concatenate([e_w, e_h, e_d]))
+
+
+def aimed_view(pos, vel, width, height, **kw) -> View:
+    pos = np.asarray(pos, dtype=np.float64)
+    vel = np.asarray(vel, dtype=np.float64)
+    rot = look_rotation(apparent_hole_direction(pos, vel))
+    return View(cam_pos=tuple(float(x) for x in pos), cam_vel=tuple(float(x) for x in vel),
+                cam_rot=rot, width=int(width), height=int(height), **kw)
+
+
+# ----------------------------------------------------------------------------------------
+# the workloads
+
+def small_static_view() -> View:
+    """128x128, static camera at r = 15, 80 deg from the disc normal, disc [3, 12]."""
+    pos = spherical_position(15.0, math.radians(80.0), 0.0)
+    return aimed_view(pos, np.zeros(3), 128, 128, disc_r_in=3.0, disc_r_out=12.0)
+
+
+def boosted_orbit_view(width: int = 1920, height: int = 1080) -> View:
+    """Camera at r = 6, 85 deg from the disc normal, moving at 0.9c along +azimuth."""
+    pos = spherical_position(6.0, math.radians(85.0), 0.0)
+    vel = 0.9 * azimuthal_direction(pos)
+    return aimed_view(pos, vel, width, height, disc_r_in=3.0, disc_r_out=20.0)
+
+
+BATCH_RESOLUTIONS = ((256, 256), (512, 512), (1024, 1024), (1920, 1080), (2048, 2048))
+
+
+def batch_views(n: int = 64, seed: int = 3) -> List[View]:
+    """Uneven views: r ~ U(2.5, 50), inclination ~ U(0, 90 deg), speed ~ U(0, 0.95)."""
+    rng = np.random.default_rng(seed)
+    res = rng.integers(0, len(BATCH_RESOLUTIONS), n)
+    r = rng.uniform(2.5, 50.0, n)
+    th = rng.uniform(0.0, math.pi / 2, n)
+    ph = rng.uniform(0.0, 2 * math.pi, n)
+    sp = rng.uniform(0.0, 0.95, n)
+    vz = rng.uniform(-1.0, 1.0, n)
+    vaz = rng.uniform(0.0, 2 * math.pi, n)
+    r_in = rng.uniform(3.0, 6.0, n)
+    r_out = rng.uniform(10.0, 30.0, n)
+    views = []
+    for k in range(n):
+        s = math.sqrt(max(0.0, 1.0 - vz[k] ** 2))
+        vdir = np.array([s * math.cos(vaz[k]), s * math.sin(vaz[k]), vz[k]])
+        pos = spherical_position(r[k], th[k], ph[k])
+        w, h = BATCH_RESOLUTIONS[res[k]]
+        views.append(aimed_view(pos, sp[k] * vdir, w, h,
+                                disc_r_in=float(r_in[k]), disc_r_out=float(r_out[k])))
+    return views
+
+
+SERVE_RESOLUTIONS = ((512, 512), (1920, 1080), (3840, 2160), (7680, 4320))
+SERVE_WEIGHTS = (0.4, 0.3, 0.2, 0.1)
+SERVE_FIELDS = ((100_000, 40), (1_000_000, 41), (4_000_000, 42))
+
+
+@dataclasses.dataclass
+class Request:
+    arrival: float        # seconds since the start of the stream
+    view: View
+    field: int            # index into SERVE_FIELDS
+
+
+def serve_requests(rate: float = 200.0, duration: float = 60.0, seed: int = 4,
+                   time_scale: float = 1000.0) -> List[Request]:
+    """Poisson arrivals; each request is a frame on a circular orbit of radius U(3, 30).
+
+    The orbit plane normal is uniform on the sphere, the phase advances with the arrival
+    time (``time_scale`` r_s/c per second) at the Keplerian rate, and the camera moves
+    along the orbit at the local circular-orbit speed sqrt(u / (2 (1 - u)))."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    arrivals = []
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= duration:
+            break
+        arrivals.append(t)
+    n = len(arrivals)
+    res = rng.choice(len(SERVE_RESOLUTIONS), size=n, p=SERVE_WEIGHTS)
+    r = rng.uniform(3.0, 30.0, n)
+    nz = rng.uniform(-1.0, 1.0, n)
+    naz = rng.uniform(0.0, 2 * math.pi, n)
+    psi0 = rng.uniform(0.0, 2 * math.pi, n)
+    r_in = rng.uniform(3.0, 6.0, n)
+    r_out = rng.uniform(10.0, 30.0, n)
+    field = rng.integers(0, len(SERVE_FIELDS), n)
+    out = []
+    for k in range(n):
+        s = math.sqrt(max(0.0, 1.0 - nz[k] ** 2))
+        nrm = np.array([s * math.cos(naz[k]), s * math.sin(naz[k]), nz[k]])
+        a = _unit(np.cross(nrm, [1.0, 0.0, 0.0]) if abs(nrm[0]) < 0.9
+                  else np.cross(nrm, [0.0, 1.0, 0.0]))
+        b = np.cross(nrm, a)
+        u = 1.0 / r[k]
+        psi = psi0[k] + math.sqrt(u ** 3 / 2.0) * arrivals[k] * time_scale
+        rhat = math.cos(psi) * a + math.sin(psi) * b
+        tang = -math.sin(psi) * a + math.cos(psi) * b
+        speed = math.sqrt(u / (2.0 * (1.0 - u)))
+        w, h = SERVE_RESOLUTIONS[res[k]]
+        v = aimed_view(r[k] * rhat, speed * tang, w, h,
+                       disc_r_in=float(r_in[k]), disc_r_out=float(r_out[k]))
+        out.append(Request(arrivals[k], v, int(field[k])))
+    return out
+
+
+def sample_quads(width: int, height: int, frac: float, seed: int) -> np.ndarray:
+    """Sorted unique 2x2-quad origins (even x, even y) covering about ``frac`` of pixels.
+
+    Returns int32 array (m, 2) of (x0, y0)."""
+    qw, qh = (width + 1) // 2, (height + 1) // 2
+    nq = qw * qh
+    m = max(1, int(round(frac * width * height / 4.0)))
+    rng = np.random.default_rng(seed)
+    idx = np.sort(rng.choice(nq, size=min(m, nq), replace=False))
+    return np.stack([2 * (idx % qw), 2 * (idx // qw)], axis=1).astype(np.int32)
+
+
+def all_quads(width: int, height: int) -> np.ndarray:
+    qw, qh = (width + 1) // 2, (height + 1) // 2
+    idx = np.arange(qw * qh)
+    return np.stack([2 * (idx % qw), 2 * (idx // qw)], axis=1).astype(np.int32)
