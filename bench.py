@@ -1,0 +1,265 @@
+"""Benchmark of the MI355X beam tracer (one JSON line on stdout).
+
+Workload (the headline metric's configuration): one 1920x1080 frame seen from a camera at
+r = 6 r_s, 85 deg from the disc normal, moving at 0.9c along +azimuth; disc r in [3, 20];
+1,000,000 seeded stars in a 6x2048x2048 RGBA16F star map; 512x512 / 64x32 tables
+integrated on the GPU with the FP64 photon-sphere band; FP32 trace.  A step is one frame of
+the whole per-pixel path (beam init, TraceRay, disc, derivatives, star gather, compose) on
+device-resident inputs; tables and star map are built once, before timing.
+
+Also reported: the batched form (64 uneven views in one persistent launch) and the served
+form (Poisson arrivals, continuous batching) against one launch per frame, the roofline of
+the render kernel (algorithmic HBM bytes from a footprint-counting pass, kernel duration
+from HIP events on the launch stream) and the FP64 CPU oracle on one full frame.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def star_map(bh, ctx, field, n0, key):
+    import torch
+    d = torch.from_numpy(field.dirs).cuda()
+    i = torch.from_numpy(field.intensity).cuda()
+    t = torch.from_numpy(field.temperature).cuda()
+    h = bh.bh_build_stars(ctx, d.data_ptr(), i.data_ptr(), t.data_ptr(), len(field), n0,
+                          bh.BH_TEXEL_FP16, key, bh.current_stream())
+    torch.cuda.synchronize()
+    return h
+
+
+def plain_leg(bh, ctx, tables, view, steps, warmup):
+    import torch
+    out = torch.empty((view.height, view.width, 4), dtype=torch.float32, device="cuda")
+    st = bh.current_stream()
+    for _ in range(warmup):
+        bh.bh_render(ctx, tables, view, out.data_ptr(), None, st)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    t0 = time.perf_counter()
+    for e0, e1 in evs:
+        e0.record()
+        bh.bh_render(ctx, tables, view, out.data_ptr(), None, st)
+        e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kms = [e0.elapsed_time(e1) for e0, e1 in evs]
+    return wall, kms, out
+
+
+def batch_leg(bh, ctx, tables, views, reps):
+    """64 uneven views: one launch per frame against one persistent launch (HIP graph)."""
+    import torch
+    outs = [torch.empty((v.height, v.width, 4), dtype=torch.float32, device="cuda")
+            for v in views]
+    ptrs = [o.data_ptr() for o in outs]
+    st = bh.current_stream()
+    px = sum(v.width * v.height for v in views)
+    res = {}
+    for name in ("plain", "batched"):
+        if name == "batched":
+            best, ms = bh.bh_autotune(ctx, tables, views, ptrs, reps=2)
+            cfg = bh.bh_tile_config_get(best // 2)
+            res["autotune"] = {"tile": [cfg.tile_w, cfg.tile_h], "ppt": cfg.ppt,
+                               "persistent": best % 2, "ms_per_config": [round(m, 4) for m in ms]}
+        def once():
+            if name == "plain":
+                for v, p in zip(views, ptrs):
+                    bh.bh_render(ctx, tables, v, p, None, st)
+            else:
+                bh.bh_render_batch(ctx, tables, views, ptrs, st)
+        once()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            once()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        res[name] = {"ms_per_batch": dt * 1e3, "mpx_per_s": px / dt / 1e6}
+    res["pixels_per_batch"] = px
+    del outs
+    return res
+
+
+def serve_leg(bh, scenes, tables_of, fields, duration, rate, seed, budget):
+    """Poisson arrivals for `duration` seconds through bh_submit/bh_poll (library-allocated
+    images inside the HBM budget), then the same requests submitted all at once."""
+    import torch
+    reqs = scenes.serve_requests(rate=rate, duration=duration, seed=seed)
+    out = {"requests": len(reqs), "rate_per_s": rate, "duration_s": duration}
+    for mode in ("poisson", "saturated"):
+        ctx = bh.bh_create(0, budget)
+        try:
+            tables = tables_of(ctx)
+            smaps = [star_map(bh, ctx, f, 2048, 40 + k) for k, f in enumerate(fields)]
+            bh.bh_serve_start(ctx, 0, 3, 8192)
+            tickets, lat = [], []
+            t_start = time.perf_counter()
+            px = 0
+            for r in reqs:
+                if mode == "poisson":
+                    wait = t_start + r.arrival - time.perf_counter()
+                    if wait > 0:
+                        time.sleep(wait)
+                v = bh.make_view(r.view, smaps[r.field])
+                tickets.append(bh.bh_submit(ctx, tables, v, None))
+                px += r.view.width * r.view.height
+                # free finished images as we go so the budget admits new frames
+                while len(tickets) > 64:
+                    done, l = bh.bh_poll(ctx, tickets[0])
+                    if not done:
+                        break
+                    lat.append(l)
+                    bh.bh_ticket_free(ctx, tickets.pop(0))
+            for t in tickets:
+                while True:
+                    done, l = bh.bh_poll(ctx, t)
+                    if done:
+                        break
+                    time.sleep(1e-4)
+                lat.append(l)
+                bh.bh_ticket_free(ctx, t)
+            span = time.perf_counter() - t_start
+        finally:
+            bh.bh_destroy(ctx)
+        lat.sort()
+        out[mode] = {"mpx_per_s": px / span / 1e6, "makespan_s": span,
+                     "latency_p50_ms": 1e3 * lat[len(lat) // 2],
+                     "latency_p99_ms": 1e3 * lat[min(len(lat) - 1, int(0.99 * len(lat)))]}
+    return out
+
+
+def cpu_baseline(view_obj, field, n0):
+    """The FP64 oracle on one full frame of the same workload, all host cores."""
+    import oracle
+    from paper_2010_08735_amd import scenes
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    cube = oracle.cubemap(field, n0)
+    quads = scenes.all_quads(view_obj.width, view_obj.height)
+    t0 = time.perf_counter()
+    px = oracle.render_quads(view_obj, quads, cube=cube, n0=n0, nthreads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": len(px) / dt / 1e6, "unit": "Mpixels/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "one full %dx%d frame (%d pixels), exact geodesic integration, FP64, "
+                      "star map built before timing" % (view_obj.width, view_obj.height, len(px)),
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--legs", default="plain,batch,serve,cpu",
+                    help="comma list of plain, batch, serve, cpu")
+    ap.add_argument("--serve-seconds", type=float, default=5.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the beam tracer runs on a single MI355X here "
+              "(--gpus %d is not supported)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    legs = set(args.legs.split(","))
+
+    import numpy as np
+    import torch
+    from paper_2010_08735_amd import bh, scenes
+
+    bh.lib()
+    ctx = bh.bh_create(0, 0)
+    t0 = time.perf_counter()
+    tables = bh.bh_precompute_tables(ctx, 512, 64, 32, bh.BH_TAB_FP64_BAND, 0.05)
+    t_tab = time.perf_counter() - t0
+    field = scenes.star_field(1_000_000, 1)
+    t0 = time.perf_counter()
+    stars = star_map(bh, ctx, field, 2048, 1)
+    t_star = time.perf_counter() - t0
+    sv = scenes.boosted_orbit_view()
+    view = bh.make_view(sv, stars)
+    W, H = sv.width, sv.height
+    log("tables %.3f s, star map %.3f s" % (t_tab, t_star))
+
+    wall, kms, out = plain_leg(bh, ctx, tables, view, args.steps, args.warmup)
+    img = out.cpu().numpy()
+    assert np.isfinite(img).all(), "non-finite pixels"
+    ms_step = 1e3 * wall / args.steps
+    mpx = W * H * args.steps / wall / 1e6
+    kernel_ms = float(np.mean(kms))
+    log("plain: %.4f ms/frame wall, kernel %.4f ms (events), %.0f Mpx/s" % (ms_step, kernel_ms, mpx))
+
+    # roofline of the render kernel: algorithmic HBM bytes per launch
+    texels = bh.bh_footprint_texels(ctx, tables, view, out.data_ptr())
+    bytes_out = 16 * W * H
+    bytes_tex = 8 * texels
+    bytes_tab = 4 * (512 * 512 + 64 * 32) + 16 * 4096
+    alg = bytes_out + bytes_tex + bytes_tab
+    achieved = alg / (kernel_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "kernel": "k_render<16,16,1>", "kernel_ms": kernel_ms,
+            "algorithmic_bytes": alg, "bytes_image": bytes_out, "bytes_star_texels": bytes_tex,
+            "star_texels_touched": texels, "bytes_tables_lut": bytes_tab}
+    log("roofline: %.1f MB algorithmic, %.1f GB/s, frac %.4f" % (alg / 1e6, achieved, achieved / HBM_PEAK_GBS))
+
+    extra = {}
+    if "batch" in legs:
+        views = [bh.make_view(v, stars) for v in scenes.batch_views(64, 3)]
+        extra["batched"] = batch_leg(bh, ctx, tables, views, reps=3)
+        log("batch:", json.dumps(extra["batched"]))
+    bh.bh_destroy(ctx)
+    torch.cuda.synchronize()
+
+    if "serve" in legs:
+        fields = [scenes.star_field(n, s) for n, s in scenes.SERVE_FIELDS]
+        tab = lambda c: bh.bh_precompute_tables(c, 512, 64, 32, bh.BH_TAB_FP64_BAND, 0.05)
+        extra["served"] = serve_leg(bh, scenes, tab, fields, args.serve_seconds, 200.0, 4,
+                                    64 << 30)
+        log("serve:", json.dumps(extra["served"]))
+
+    if "calib" in legs:
+        # a plain device copy of known size, for scaling FETCH_SIZE / WRITE_SIZE counters
+        a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        extra["calib_copy_bytes"] = 4 * (64 << 20)
+
+    cpu = None
+    if "cpu" in legs:
+        cpu = cpu_baseline(sv, field, 2048)
+        log("cpu baseline: %.3f Mpx/s on %d cores (%.1f s)" % (cpu["value"], cpu["cores"], cpu["seconds"]))
+
+    line = {
+        "metric": "Mpixels/s at 1080p (plain vs batched/served); p50/p99 frame latency",
+        "value": mpx, "unit": "Mpixels/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "fp32",
+        "data": "synthetic (seeded star field and camera, no catalog data)",
+        "config": {"workload": "1920x1080 frame, camera r=6 at 0.9c tangential, disc [3,20], "
+                               "1M stars 6x2048^2 RGBA16F, tables 512^2 + 64x32 (FP64 band)",
+                   "width": W, "height": H, "stars": 1_000_000, "star_map": "6x2048x2048 RGBA16F",
+                   "tables": "D 512x512, U 64x32, FP32 storage", "parallelism": "single GPU"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "setup_s": {"tables": t_tab, "star_map": t_star},
+    }
+    line.update(extra)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

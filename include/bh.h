@@ -1,0 +1,229 @@
+/*
+ * libbh -- per-pixel constant-time beam tracer for non-rotating black holes on AMD
+ * Instinct MI355X (gfx950), after E. Bruneton, "Real-time High-Quality Rendering of
+ * Non-Rotating Black Holes" (arXiv 2010.08735).
+ *
+ * Units follow Section 3.1: every length is given in the same unit as r_s (the horizon
+ * radius) and is divided by r_s inside the library; the speed of light is 1.
+ *
+ * Conventions shared by every entry point
+ *   - Return value: a bh_status.  Arguments are validated before any device work; on error
+ *     nothing is launched and bh_last_error() describes the problem (thread-local string,
+ *     owned by the library, valid until the next failing call on the same thread).
+ *   - Pointers named *_dev are device pointers (HIP global memory); the caller owns them
+ *     and must keep them alive until the work that uses them has completed on the stream.
+ *   - Pointers named host_* are host pointers.
+ *   - hip_stream is a hipStream_t (may be NULL for the null stream).  Work is enqueued on
+ *     that stream and the call returns without waiting, unless stated otherwise.
+ *   - Handles (bh_ctx, bh_tables, bh_stars) are owned by the library.  Tables and star
+ *     maps are reference counted and shared by key: a second request with the same key
+ *     returns the resident handle with its count incremented; bh_release_* drops it.
+ *   - Thread safety: every call is safe to make concurrently on one context.
+ */
+#ifndef BH_H
+#define BH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BH_OK = 0,
+  BH_EINVAL = 1,     /* invalid argument (geometry, sizes, NaN, null pointer)          */
+  BH_ENOMEM = 2,     /* HBM budget exceeded or a device allocation failed              */
+  BH_EDEVICE = 3,    /* HIP runtime error                                               */
+  BH_EAGAIN = 4,     /* serving queue full; retry later                                 */
+  BH_ENOTFOUND = 5,  /* unknown ticket                                                  */
+  BH_ECANCELED = 6   /* request cancelled (context destroyed before completion)         */
+} bh_status;
+
+typedef struct bh_ctx bh_ctx;
+typedef struct bh_tables bh_tables;
+typedef struct bh_stars bh_stars;
+
+/* ---- context ----------------------------------------------------------------------- */
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes caps the device memory the
+ * library itself allocates (tables, star maps, band table, serving outputs); 0 = no cap.
+ * Builds the blackbody band table on the device before returning. */
+bh_status bh_create(int device, uint64_t hbm_budget_bytes, bh_ctx** out);
+/* Wait for outstanding work, cancel queued requests, free every resource. */
+void bh_destroy(bh_ctx* ctx);
+const char* bh_last_error(void);
+/* Device bytes currently allocated by the library on this context. */
+uint64_t bh_bytes_in_use(const bh_ctx* ctx);
+
+/* ---- precomputed tables (Section 3.3.2 "Escape angle", 3.3.3 "Intersections",
+ *      Algorithm 1 Precompute, Appendix A) -------------------------------------------- */
+
+#define BH_TAB_FP32 0       /* integrate in FP32 everywhere                              */
+#define BH_TAB_FP64_BAND 1  /* FP64 while |u - 2/3| < fp64_band, FP32 elsewhere           */
+#define BH_TAB_FP64_ALL 2   /* FP64 everywhere                                           */
+
+typedef struct {
+  int32_t d_n;        /* deflection table is d_n x d_n (even, >= 8; paper: 512)          */
+  int32_t u_ne;       /* intersection table columns along e (paper: 64)                  */
+  int32_t u_nphi;     /* intersection table rows along phi (paper: 32)                   */
+  int32_t precision;  /* BH_TAB_*                                                        */
+  double fp64_band;   /* half-width of the FP64 band around u = 2/3 (0.05)               */
+  double step;        /* integration step in phi (RK4; 0 selects 2e-3)                   */
+} bh_table_params;
+
+/* Integrate the orbit equation u'' = 3/2 u^2 - u on the device for every table column
+ * and fill the deflection table D(e,u) = phi - atan2(u, du/dphi) (incoming branch) and
+ * the intersection table U(e,phi) = u (phi < pi, 1 after the ray falls in), both FP32,
+ * at the texel centres k/(N-1) of the Appendix A mappings.  Shared by parameter key.
+ * Synchronises hip_stream before returning (the tables are then ready for any stream). */
+bh_status bh_precompute_tables(bh_ctx* ctx, const bh_table_params* p, void* hip_stream,
+                               bh_tables** out);
+/* Copy the tables to the host: host_D d_n*d_n floats, row j (u coordinate) major, column
+ * i (e coordinate) minor; host_U u_nphi*u_ne floats, row (phi) major.  Either may be NULL.
+ * Blocking. */
+bh_status bh_tables_download(const bh_tables* t, float* host_D, float* host_U);
+bh_status bh_release_tables(bh_tables* t);
+
+/* ---- star map (Section 3.3.2 "Emitted light") -------------------------------------- */
+
+#define BH_TEXEL_FP16 0     /* RGBA16F texels: I (per-level power-of-two scale), T, p_u, p_v */
+#define BH_TEXEL_FP32 1     /* RGBA32F texels                                             */
+
+typedef struct {
+  const float* dir_xyz_dev;     /* n x 3 directions (any length > 0), device               */
+  const float* intensity_dev;   /* n, emitted intensity summed over the three bands, >= 0  */
+  const float* temperature_dev; /* n, blackbody temperature in K                           */
+  int64_t n;
+  int32_t face_size;            /* level-0 texels per cube face edge, power of two         */
+  int32_t texel_format;         /* BH_TEXEL_*                                              */
+  uint64_t key;                 /* non-zero: share the resident map built with this key,
+                                   face size and format                                    */
+} bh_star_field;
+
+/* Splat the stars into a cube map (one texel holds the intensity sum, the
+ * intensity-weighted mean temperature and the intensity-weighted mean position of the
+ * stars inside it) and build every mip level with the same rule.  Deterministic.
+ * Synchronises hip_stream before returning. */
+bh_status bh_build_stars(bh_ctx* ctx, const bh_star_field* f, void* hip_stream, bh_stars** out);
+/* Copy mip level `level` as float (face, y, x, [I, T, p_u, p_v]) to host_texels
+ * (6 * (face_size >> level)^2 * 4 floats).  Blocking. */
+bh_status bh_stars_download(const bh_stars* s, int32_t level, float* host_texels);
+bh_status bh_release_stars(bh_stars* s);
+
+/* ---- rendering (Sections 3.2-3.4) ---------------------------------------------------- */
+
+#define BH_T_POWER 0  /* T' = T0 (r' / 3 r_s)^T_exp                                        */
+#define BH_T_PAPER 1  /* T'^4 proportional to u^3 (1 - sqrt(3u)) (Section 3.3.3), peak T0  */
+
+typedef struct {
+  double r_s;           /* > 0                                                            */
+  double cam_pos[3];    /* Cartesian camera position, |cam_pos| > r_s (Section 5)         */
+  double cam_vel[3];    /* camera velocity seen by the static observer at cam_pos, along
+                           the Cartesian axes, |v| < 1                                     */
+  double cam_rot[9];    /* rows e_w, e_h, e_d (orthonormal) of the camera in its own
+                           (boosted) frame; the camera looks along -e_d                    */
+  double fov_y;         /* vertical field of view, radians, (0, pi)                       */
+  int32_t width, height;
+  double disc_r_in;     /* >= 3 r_s (innermost stable circular orbit, Section 3.3.3)       */
+  double disc_r_out;    /* > disc_r_in                                                     */
+  int32_t disc_T_law;   /* BH_T_*                                                          */
+  int32_t pad0;
+  double disc_T0;       /* K                                                               */
+  double disc_T_exp;    /* exponent of the power law (-0.75)                              */
+  double disc_opacity;  /* front-to-back opacity of each disc crossing, [0, 1]             */
+  double k_disc;        /* exposure applied to disc band radiances (W m^-2 sr^-1)         */
+  double k_star;        /* exposure applied to star intensities                           */
+  const bh_stars* stars;/* NULL: black sky                                                 */
+} bh_view;
+
+/* AOV record written per pixel when aov_dev is not NULL (4 floats):
+ *   [0] escape angle delta' (radians, +inf if the beam falls into the hole)
+ *   [1] u of the first disc crossing along the beam (0 if none)
+ *   [2] u of the second disc crossing (0 if none)
+ *   [3] bit pattern (reinterpret as uint32): bit0 captured, bit1 crossing before the
+ *       apsis, bit2 crossing after the apsis, bit3 star term zeroed (a member of the 2x2
+ *       quad is captured), bit4 degenerate beam plane, bits 8-15 mip level (255: none). */
+#define BH_AOV_CAPTURED 1u
+#define BH_AOV_CROSS0 2u
+#define BH_AOV_CROSS1 4u
+#define BH_AOV_STAR_ZEROED 8u
+#define BH_AOV_DEGENERATE 16u
+
+/* Render one view: out_rgba_dev receives width*height float4 (R, G, B, 1) in row-major
+ * order, row 0 at the top; colour = k_disc x disc band radiances composited front to back
+ * over k_star x lensed, Doppler-shifted star light.  aov_dev may be NULL. */
+bh_status bh_render(bh_ctx* ctx, const bh_tables* t, const bh_view* v, float* out_rgba_dev,
+                    float* aov_dev, void* hip_stream);
+
+/* Render n views of any sizes in one persistent launch (work list of tiles, replayed as
+ * a HIP graph when the same shapes repeat).  outs_dev[i] has views[i].width*height float4.
+ * Per pixel the result is bitwise identical to bh_render. */
+bh_status bh_render_batch(bh_ctx* ctx, const bh_tables* t, const bh_view* views, int32_t n,
+                          float* const* outs_dev, void* hip_stream);
+
+/* Tile configuration of the render kernels (the autotuner chooses among these). */
+typedef struct {
+  int32_t tile_w, tile_h;  /* pixels per workgroup tile (multiples of 8)                  */
+  int32_t waves;           /* wavefronts per workgroup                                    */
+  int32_t ppt;             /* pixels per thread                                           */
+} bh_tile_config;
+int32_t bh_tile_config_count(void);
+bh_status bh_tile_config_get(int32_t index, bh_tile_config* out);
+/* Select the tile configuration used by bh_render / bh_render_batch (-1: built-in default) */
+bh_status bh_set_tile_config(bh_ctx* ctx, int32_t index);
+/* Time every tile configuration with both batched launch forms (persistent workgroups
+ * pulling tiles from an atomic counter, or one workgroup per tile) on the given views and
+ * keep the fastest.  best_index = 2 * config + persistent; ms_per_config receives
+ * 2 * bh_tile_config_count() timings in the same order (or NULL). */
+bh_status bh_autotune(bh_ctx* ctx, const bh_tables* t, const bh_view* views, int32_t n,
+                      float* const* outs_dev, int32_t reps, int32_t* best_index,
+                      float* ms_per_config);
+
+/* ---- serving: continuous batching -------------------------------------------------- */
+
+typedef struct {
+  int32_t max_queue;          /* submissions beyond this return BH_EAGAIN                */
+  int32_t max_inflight_launches; /* launches kept in flight on the serving stream (2)    */
+  int64_t max_tiles_per_launch;  /* tiles per launch; bigger requests are split (16384)  */
+} bh_serve_params;
+
+/* Start the serving scheduler thread on its own stream (call once per context). */
+bh_status bh_serve_start(bh_ctx* ctx, const bh_serve_params* p);
+/* Queue a frame; returns at once with a ticket.  out_rgba_dev may be NULL, in which case
+ * the library allocates the image inside the HBM budget (admission waits for room) and
+ * bh_poll returns it; it is freed by bh_ticket_free. */
+bh_status bh_submit(bh_ctx* ctx, const bh_tables* t, const bh_view* v, float* out_rgba_dev,
+                    uint64_t* ticket);
+/* done = 1 when the frame is complete on the device; latency_s = completion - submit. */
+bh_status bh_poll(bh_ctx* ctx, uint64_t ticket, int32_t* done, double* latency_s);
+/* Image of a finished ticket that was submitted with out_rgba_dev = NULL. */
+bh_status bh_ticket_image(bh_ctx* ctx, uint64_t ticket, float** out_rgba_dev);
+/* Forget a finished ticket (and free a library-allocated image). */
+bh_status bh_ticket_free(bh_ctx* ctx, uint64_t ticket);
+/* Block until every submitted request is complete. */
+bh_status bh_serve_drain(bh_ctx* ctx);
+
+/* ---- unit-level entry points used by the tests ------------------------------------------ */
+
+/* TraceRay (Algorithm 1) alone for n rays given as 5 floats each
+ * [u = 1/p^r, delta, alpha, u_ic, u_oc]; writes 4 floats per ray in the AOV layout. */
+bh_status bh_trace_rays(bh_ctx* ctx, const bh_tables* t, const float* rays_dev, int64_t n,
+                        float* out_dev, void* hip_stream);
+/* Measurement: render v once (into out_rgba_dev) with a variant of the render kernel that
+ * marks every star-map texel the footprints visit, and return how many distinct texels were
+ * visited (the star-map bytes one frame must read at least once).  Blocking. */
+bh_status bh_footprint_texels(bh_ctx* ctx, const bh_tables* t, const bh_view* v,
+                              float* out_rgba_dev, uint64_t* texels);
+/* Blackbody band table: n entries of 4 floats [log2 L_R, log2 L_G, log2 L_B,
+ * log2 (L_R + L_G + L_B)] at log2 T = x0 + k dx.  Blocking. */
+bh_status bh_band_table_info(const bh_ctx* ctx, int32_t* n, float* x0, float* dx);
+bh_status bh_band_table_download(const bh_ctx* ctx, float* host_lut);
+/* Band radiances (W m^-2 sr^-1) through the band table for n temperatures, 3 floats each. */
+bh_status bh_band_eval(bh_ctx* ctx, const float* temps_dev, int64_t n, float* out_dev,
+                       void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

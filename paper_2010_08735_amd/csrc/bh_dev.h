@@ -1,0 +1,138 @@
+// Device-side records and helpers shared by the libbh HIP kernels (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "bh.h"
+
+// AOV flag bits (see include/bh.h)
+#define BH_CAPTURED_BIT BH_AOV_CAPTURED
+#define BH_CROSS0_BIT BH_AOV_CROSS0
+#define BH_CROSS1_BIT BH_AOV_CROSS1
+#define BH_STAR_ZEROED_BIT BH_AOV_STAR_ZEROED
+#define BH_DEGENERATE_BIT BH_AOV_DEGENERATE
+
+namespace bh {
+
+// mu = 4/27: maximum of u^2 (1 - u), reached at the photon sphere u = 2/3 (Section 3.3.1)
+constexpr float kMu = 4.0f / 27.0f;
+constexpr double kMuD = 4.0 / 27.0;
+constexpr float kPi = 3.14159265358979323846f;
+
+// ---- tables -------------------------------------------------------------------------
+struct TablesDev {
+  const float* D;  // d_n x d_n, row j (u coordinate) major
+  const float* U;  // u_nphi x u_ne, row j (phi coordinate) major
+  int d_n, u_ne, u_nphi, pad;
+};
+
+// ---- blackbody band table -----------------------------------------------------------
+// lut[k] = (log2 L_R, log2 L_G, log2 L_B, log2(L_R + L_G + L_B)) at log2 T = x0 + k dx
+struct LutDev {
+  const float4* lut;
+  int n;
+  float x0, inv_dx, pad;
+};
+
+// ---- star map -------------------------------------------------------------------------
+struct StarsDev {
+  const void* tex;        // all levels, level L at element offset level_off[L]
+  const float* scale;     // per-level intensity scale (FP16 format), 1 for FP32
+  const uint32_t* level_off;  // texel offset of each level (<= 2^32 texels)
+  const uint32_t* occ;    // occupancy bits, level L at word offset occ_off[L]
+  const uint32_t* occ_off;
+  int n0, levels, fp16, pad;
+};
+
+// ---- per-view constant block (host computes it in FP64 from bh_view) -----------------
+struct ViewDev {
+  float rhat[3], sq1mu;   // e_x' = radial unit vector at the camera, sqrt(1 - u_c)
+  float ew[3], f;         // camera axes in world coordinates, focal length in pixels
+  float eh[3], u_c;
+  float ed[3], gamma;
+  float vhat[3], vmag;    // camera velocity direction and speed (static frame)
+  float half_w, half_h, u_ic, u_oc;
+  float inv_sq1mu, T0, T_exp, rho;
+  float k_disc, k_star, T_norm, pad0;
+  int width, height, T_law, has_stars;
+  StarsDev stars;
+  float4* out;
+  float4* aov;
+};
+
+// tile work item for the batched kernel: view index and tile origin
+struct WorkItem {
+  int view, x0, y0, pad;
+};
+
+__device__ __forceinline__ float clampf(float x, float lo, float hi) {
+  return fminf(fmaxf(x, lo), hi);
+}
+
+// bilinear fetch of a row-major table with texel k of n at unit coordinate k/(n-1),
+// columns clamped to [lo, hi] (so the two halves of D are never mixed)
+__device__ __forceinline__ float bilinear(const float* __restrict__ t, int nx, int ny, int lo,
+                                          int hi, float x, float y) {
+  float tx = clampf(x * (float)(nx - 1), (float)lo, (float)hi);
+  float ty = clampf(y * (float)(ny - 1), 0.0f, (float)(ny - 1));
+  int i0 = min((int)tx, hi - 1);
+  int j0 = min((int)ty, ny - 2);
+  float fx = tx - (float)i0, fy = ty - (float)j0;
+  const float* r0 = t + (size_t)j0 * nx + i0;
+  const float* r1 = r0 + nx;
+  float a = r0[0] + fx * (r0[1] - r0[0]);
+  float b = r1[0] + fx * (r1[1] - r1[0]);
+  return a + fy * (b - a);
+}
+
+// apsis of a ray with e^2 < mu (Section 3.3.1, eq. uapsis)
+__device__ __forceinline__ float apsis_f(float e2) {
+  float a = clampf(e2 * (2.0f / kMu) - 1.0f, -1.0f, 1.0f);
+  return 1.0f / 3.0f + 2.0f / 3.0f * sinf(asinf(a) * (1.0f / 3.0f));
+}
+
+// D(e, u) through the Appendix A mapping.  udot = du/dphi at (e, u) on the ray.  For
+// e^2 < mu the row coordinate y = 1 - sqrt(1 - u/u_a) is evaluated as
+// 1 - sqrt(udot^2 / (e^2 + u u_a (1 - u_a - u))): the two are equal because
+// udot^2 = (u_a - u)(u_2 - u)(u - u_3) with u_2 + u_3 = 1 - u_a and u_2 u_3 = -e^2 / u_a,
+// and the second form has no cancellation when the camera sits near the apsis.
+__device__ __forceinline__ float lookup_D(const TablesDev& T, float e2, float u, float ua,
+                                          float udot) {
+  const int n = T.d_n;
+  if (e2 < kMu) {
+    float x = 0.5f - sqrtf(-log1pf(-e2 * (1.0f / kMu)) * (1.0f / 50.0f));
+    float den = e2 + u * ua * (1.0f - ua - u);
+    float s2 = den > 0.0f ? fminf(__fdividef(udot * udot, den), 1.0f) : 0.0f;
+    float y = 1.0f - sqrtf(s2);
+    return bilinear(T.D, n, n, 0, n / 2 - 1, x, y);
+  }
+  float x = 0.5f + sqrtf(-log1pf(-kMu / e2) * (1.0f / 50.0f));
+  float dz = u - 2.0f / 3.0f;
+  const float s23 = 0.816496580927726f, s13 = 0.577350269189626f;
+  float y = (s23 + copysignf(sqrtf(fabsf(dz)), dz)) * (1.0f / (s23 + s13));
+  return bilinear(T.D, n, n, n / 2, n - 1, x, y);
+}
+
+// U(e, phi) through the Appendix A mapping
+__device__ __forceinline__ float lookup_U(const TablesDev& T, float e2, float e, float phi) {
+  float x = __fdividef(1.0f, 1.0f + 6.0f * e2);
+  // (1 + 6 e^3) / (1 + e^2) written so that it cannot overflow for nearly radial rays
+  float y = phi * (1.0f / 3.0f) * (6.0f * e + __fdividef(1.0f - 6.0f * e, 1.0f + e2));
+  return bilinear(T.U, T.u_ne, T.u_nphi, 0, T.u_ne - 1, x, y);
+}
+
+// band radiances (R, G, B, sum) at temperature T from the log-log band table
+__device__ __forceinline__ float4 band_lookup(const LutDev& L, float T) {
+  if (!(T > 0.0f)) return make_float4(0.f, 0.f, 0.f, 0.f);
+  float x = (__log2f(T) - L.x0) * L.inv_dx;
+  if (x < 0.0f) return make_float4(0.f, 0.f, 0.f, 0.f);
+  x = fminf(x, (float)L.n + 1024.0f);  // keeps the index conversion defined for T = inf
+  int k = min((int)x, L.n - 2);
+  float fr = x - (float)k;  // > 1 above the table: linear extrapolation in log-log
+  float4 a = L.lut[k], b = L.lut[k + 1];
+  return make_float4(exp2f(a.x + fr * (b.x - a.x)), exp2f(a.y + fr * (b.y - a.y)),
+                     exp2f(a.z + fr * (b.z - a.z)), exp2f(a.w + fr * (b.w - a.w)));
+}
+
+}  // namespace bh

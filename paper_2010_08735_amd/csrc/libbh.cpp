@@ -1,0 +1,1151 @@
+// libbh host side: contexts, resident resources, argument validation, per-view setup in
+// FP64, kernel launches, batched launches under HIP graphs, autotuning and the serving
+// scheduler.  Public API: include/bh.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <tuple>
+#include <unordered_map>
+#include <vector>
+
+#include "bh.h"
+#include "bh_dev.h"
+
+namespace bh {
+hipError_t launch_precompute(float* D, int d_n, float* U, int u_ne, int u_nphi, int mode,
+                             double band, double step, hipStream_t s);
+hipError_t launch_band_lut(float4* lut, int n, float x0, float dx, hipStream_t s);
+hipError_t launch_band_eval(const LutDev& L, const float* temps, int64_t n, float* out,
+                            hipStream_t s);
+hipError_t launch_star_build(const float* dirs, const float* inten, const float* temp, int64_t n,
+                             int n0, int levels, const uint32_t* level_off_host, int* head,
+                             int* next, float2* pos, float4* master, unsigned* maxbits,
+                             float* scale, int fp16, void* out, hipStream_t s);
+hipError_t launch_fill_int(int* p, int64_t n, int v, hipStream_t s);
+hipError_t launch_star_occupancy(const void* tex, int n0, int levels, const uint32_t* level_off,
+                                 const uint32_t* occ_off, int fp16, uint32_t* occ,
+                                 hipStream_t s);
+hipError_t launch_star_unpack(const void* in, int64_t count, float scale, int fp16, float4* out,
+                              hipStream_t s);
+hipError_t launch_render(int cfg, const ViewDev& v, const TablesDev& T, const LutDev& L,
+                         hipStream_t s);
+hipError_t launch_render_batch(int cfg, int persistent, const ViewDev* views,
+                               const WorkItem* items, int nitems, int* counter,
+                               const TablesDev& T, const LutDev& L, int grid, hipStream_t s);
+hipError_t launch_trace_rays(const TablesDev& T, const float* rays, int64_t n, float4* out,
+                             hipStream_t s);
+hipError_t launch_render_count(const ViewDev& v, const TablesDev& T, const LutDev& L,
+                               uint32_t* touched, int64_t words, unsigned long long* total,
+                               hipStream_t s);
+int tile_config_count();
+void tile_config(int i, int* tw, int* th, int* waves, int* ppt);
+}  // namespace bh
+
+using namespace bh;
+
+// ---- errors ------------------------------------------------------------------------------
+
+static thread_local std::string g_err;
+
+static bh_status fail(bh_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIPCHK(expr)                                                                        \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return fail(BH_EDEVICE, std::string(#expr) + " failed: " + hipGetErrorString(e_));    \
+  } while (0)
+
+extern "C" const char* bh_last_error(void) { return g_err.c_str(); }
+
+// ---- resources -----------------------------------------------------------------------------
+
+struct bh_tables {
+  bh_ctx* ctx;
+  bh_table_params p;
+  std::string key;
+  float* D = nullptr;
+  float* U = nullptr;
+  size_t bytes = 0;
+  int refs = 1;
+};
+
+struct bh_stars {
+  bh_ctx* ctx;
+  uint64_t key;
+  int n0, levels, fp16;
+  void* tex = nullptr;
+  float* scale = nullptr;
+  uint32_t* level_off_dev = nullptr;
+  uint32_t* occ = nullptr;        // occupancy bits (see k_star_occupancy)
+  uint32_t* occ_off_dev = nullptr;
+  size_t occ_bytes = 0;
+  std::vector<uint32_t> level_off, occ_off;
+  size_t bytes = 0;
+  int refs = 1;
+};
+
+struct Staging {
+  void* host = nullptr;   // pinned
+  size_t cap = 0;
+  hipEvent_t done = nullptr;  // last copy out of this buffer
+  bool used = false;
+};
+
+struct ServeReq {
+  uint64_t ticket;
+  bh_view view;
+  const bh_tables* tables;
+  float* out;
+  bool owned = false;         // out allocated by the library
+  size_t out_bytes = 0;
+  int tiles_total = 0, tiles_next = 0;
+  int tiles_x = 0;
+  double t_submit = 0, t_done = 0;
+  bool admitted = false, done = false;
+  bh_status status = BH_OK;
+};
+
+struct Launch {
+  hipEvent_t ev = nullptr;
+  std::vector<uint64_t> finishing;  // tickets whose last tile is in this launch
+  int slot = 0;
+};
+
+struct bh_ctx {
+  int device = 0;
+  uint64_t budget = 0;
+  std::atomic<uint64_t> used{0};
+  int cus = 256;
+  std::mutex mu;  // resources, tile config, batch staging
+  std::map<std::string, bh_tables*> tables;
+  std::map<std::tuple<uint64_t, int, int>, bh_stars*> stars;
+  float4* lut = nullptr;
+  int lut_n = 4096;
+  float lut_x0 = 6.0f, lut_dx = 15.0f / 4095.0f;
+  int tile_cfg = 0;
+  int persistent = 0;  // batched launches: 1 = persistent workgroups, 0 = one per tile
+  // recycled library-allocated images (serving), counted in `used`
+  std::multimap<size_t, void*> pool;
+  // batched launches
+  ViewDev* b_views = nullptr;
+  WorkItem* b_items = nullptr;
+  int* b_counter = nullptr;
+  size_t b_views_cap = 0, b_items_cap = 0;
+  Staging b_stage[2];
+  int b_next_stage = 0;
+  hipEvent_t b_last = nullptr;  // completion of the last batch that used b_views/b_items
+  struct GraphEntry {
+    hipGraphExec_t exec;
+    hipStream_t stream;
+  };
+  std::map<std::tuple<int, int, int, const void*, uintptr_t>, GraphEntry> graphs;
+  // serving
+  std::thread serve_thread;
+  bool serving = false, stop = false;
+  bh_serve_params sp{};
+  hipStream_t serve_stream = nullptr;
+  std::mutex smu;
+  std::condition_variable scv, done_cv;
+  std::deque<ServeReq*> queue;
+  std::unordered_map<uint64_t, ServeReq*> reqs;
+  uint64_t next_ticket = 1;
+  size_t pending = 0;
+};
+
+static double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+static bh_status dev_alloc(bh_ctx* c, size_t bytes, void** p) {
+  if (c->budget && c->used.load() + bytes > c->budget)
+    return fail(BH_ENOMEM, "HBM budget exceeded: " + std::to_string(c->used.load() + bytes) +
+                               " > " + std::to_string(c->budget));
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) return fail(BH_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  c->used += bytes;
+  return BH_OK;
+}
+
+static void dev_free(bh_ctx* c, void* p, size_t bytes) {
+  if (!p) return;
+  (void)hipFree(p);
+  c->used -= bytes;
+}
+
+static bh_status ensure_staging(Staging& s, size_t bytes) {
+  if (s.cap >= bytes) return BH_OK;
+  if (s.host) (void)hipHostFree(s.host);
+  s.host = nullptr;
+  s.cap = 0;
+  size_t cap = std::max(bytes, (size_t)1 << 16);
+  HIPCHK(hipHostMalloc(&s.host, cap, hipHostMallocDefault));
+  s.cap = cap;
+  if (!s.done) HIPCHK(hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
+  return BH_OK;
+}
+
+// ---- context -------------------------------------------------------------------------------
+
+extern "C" bh_status bh_create(int device, uint64_t budget, bh_ctx** out) {
+  if (!out) return fail(BH_EINVAL, "out is NULL");
+  int n = 0;
+  HIPCHK(hipGetDeviceCount(&n));
+  if (device < 0 || device >= n) return fail(BH_EINVAL, "no such device");
+  HIPCHK(hipSetDevice(device));
+  std::unique_ptr<bh_ctx> c(new bh_ctx);
+  c->device = device;
+  c->budget = budget;
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, device));
+  c->cus = prop.multiProcessorCount;
+  bh_status st = dev_alloc(c.get(), sizeof(float4) * c->lut_n, (void**)&c->lut);
+  if (st) return st;
+  HIPCHK(launch_band_lut(c->lut, c->lut_n, c->lut_x0, c->lut_dx, nullptr));
+  HIPCHK(hipDeviceSynchronize());
+  st = dev_alloc(c.get(), sizeof(int) * 64, (void**)&c->b_counter);
+  if (st) return st;
+  *out = c.release();
+  return BH_OK;
+}
+
+static void serve_stop(bh_ctx* c);
+
+extern "C" void bh_destroy(bh_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  serve_stop(c);
+  (void)hipDeviceSynchronize();
+  for (auto& kv : c->graphs) {
+    (void)hipGraphExecDestroy(kv.second.exec);
+  }
+  if (c->b_last) (void)hipEventDestroy(c->b_last);
+  for (auto& kv : c->tables) {
+    dev_free(c, kv.second->D, 0);
+    dev_free(c, kv.second->U, 0);
+    delete kv.second;
+  }
+  for (auto& kv : c->stars) {
+    dev_free(c, kv.second->tex, 0);
+    dev_free(c, kv.second->scale, 0);
+    dev_free(c, kv.second->level_off_dev, 0);
+    dev_free(c, kv.second->occ, 0);
+    dev_free(c, kv.second->occ_off_dev, 0);
+    delete kv.second;
+  }
+  dev_free(c, c->lut, 0);
+  dev_free(c, c->b_counter, 0);
+  dev_free(c, c->b_views, 0);
+  dev_free(c, c->b_items, 0);
+  for (auto& s : c->b_stage) {
+    if (s.host) (void)hipHostFree(s.host);
+    if (s.done) (void)hipEventDestroy(s.done);
+  }
+  delete c;
+}
+
+extern "C" uint64_t bh_bytes_in_use(const bh_ctx* c) { return c ? c->used.load() : 0; }
+
+// ---- tables --------------------------------------------------------------------------------
+
+static std::string table_key(const bh_table_params& p) {
+  char b[256];
+  snprintf(b, sizeof b, "%d/%d/%d/%d/%.17g/%.17g", p.d_n, p.u_ne, p.u_nphi, p.precision,
+           p.fp64_band, p.step);
+  return b;
+}
+
+extern "C" bh_status bh_precompute_tables(bh_ctx* c, const bh_table_params* pin, void* stream,
+                                          bh_tables** out) {
+  if (!c || !pin || !out) return fail(BH_EINVAL, "NULL argument");
+  bh_table_params p = *pin;
+  if (p.step == 0.0) p.step = 2e-3;
+  if (p.d_n < 8 || p.d_n % 2 || p.d_n > 16384) return fail(BH_EINVAL, "d_n must be even, 8..16384");
+  if (p.u_ne < 4 || p.u_nphi < 4 || p.u_ne > 4096 || p.u_nphi > 4096)
+    return fail(BH_EINVAL, "u_ne, u_nphi must be in 4..4096");
+  if (p.precision < BH_TAB_FP32 || p.precision > BH_TAB_FP64_ALL)
+    return fail(BH_EINVAL, "bad precision");
+  if (!(p.fp64_band >= 0.0 && p.fp64_band < 1.0)) return fail(BH_EINVAL, "bad fp64_band");
+  if (!(p.step > 1e-7 && p.step <= 0.05)) return fail(BH_EINVAL, "step must be in (1e-7, 0.05]");
+  HIPCHK(hipSetDevice(c->device));
+  std::lock_guard<std::mutex> g(c->mu);
+  std::string key = table_key(p);
+  auto it = c->tables.find(key);
+  if (it != c->tables.end()) {
+    it->second->refs++;
+    *out = it->second;
+    return BH_OK;
+  }
+  auto* t = new bh_tables;
+  t->ctx = c;
+  t->p = p;
+  t->key = key;
+  size_t bd = sizeof(float) * (size_t)p.d_n * p.d_n, bu = sizeof(float) * (size_t)p.u_ne * p.u_nphi;
+  bh_status st = dev_alloc(c, bd, (void**)&t->D);
+  if (!st) st = dev_alloc(c, bu, (void**)&t->U);
+  if (st) {
+    dev_free(c, t->D, t->D ? bd : 0);
+    delete t;
+    return st;
+  }
+  t->bytes = bd + bu;
+  hipStream_t s = (hipStream_t)stream;
+  int mode = p.precision == BH_TAB_FP32 ? 0 : (p.precision == BH_TAB_FP64_BAND ? 1 : 2);
+  hipError_t e = launch_precompute(t->D, p.d_n, t->U, p.u_ne, p.u_nphi, mode, p.fp64_band, p.step, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    dev_free(c, t->D, bd);
+    dev_free(c, t->U, bu);
+    delete t;
+    return fail(BH_EDEVICE, std::string("precompute: ") + hipGetErrorString(e));
+  }
+  c->tables[key] = t;
+  *out = t;
+  return BH_OK;
+}
+
+extern "C" bh_status bh_tables_download(const bh_tables* t, float* hD, float* hU) {
+  if (!t) return fail(BH_EINVAL, "NULL tables");
+  HIPCHK(hipSetDevice(t->ctx->device));
+  if (hD) HIPCHK(hipMemcpy(hD, t->D, sizeof(float) * (size_t)t->p.d_n * t->p.d_n, hipMemcpyDeviceToHost));
+  if (hU) HIPCHK(hipMemcpy(hU, t->U, sizeof(float) * (size_t)t->p.u_ne * t->p.u_nphi, hipMemcpyDeviceToHost));
+  return BH_OK;
+}
+
+extern "C" bh_status bh_release_tables(bh_tables* t) {
+  if (!t) return fail(BH_EINVAL, "NULL tables");
+  bh_ctx* c = t->ctx;
+  std::lock_guard<std::mutex> g(c->mu);
+  if (--t->refs > 0) return BH_OK;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  c->tables.erase(t->key);
+  dev_free(c, t->D, sizeof(float) * (size_t)t->p.d_n * t->p.d_n);
+  dev_free(c, t->U, sizeof(float) * (size_t)t->p.u_ne * t->p.u_nphi);
+  delete t;
+  return BH_OK;
+}
+
+// ---- stars ---------------------------------------------------------------------------------
+
+extern "C" bh_status bh_build_stars(bh_ctx* c, const bh_star_field* f, void* stream,
+                                    bh_stars** out) {
+  if (!c || !f || !out) return fail(BH_EINVAL, "NULL argument");
+  if (f->n < 0 || (f->n > 0 && (!f->dir_xyz_dev || !f->intensity_dev || !f->temperature_dev)))
+    return fail(BH_EINVAL, "bad star arrays");
+  if (f->n >= (int64_t)1 << 31) return fail(BH_EINVAL, "at most 2^31 - 1 stars");
+  int n0 = f->face_size;
+  if (n0 < 1 || n0 > 8192 || (n0 & (n0 - 1))) return fail(BH_EINVAL, "face_size must be a power of two <= 8192");
+  if (f->texel_format != BH_TEXEL_FP16 && f->texel_format != BH_TEXEL_FP32)
+    return fail(BH_EINVAL, "bad texel_format");
+  HIPCHK(hipSetDevice(c->device));
+  std::lock_guard<std::mutex> g(c->mu);
+  auto key = std::make_tuple(f->key, n0, f->texel_format);
+  if (f->key) {
+    auto it = c->stars.find(key);
+    if (it != c->stars.end()) {
+      it->second->refs++;
+      *out = it->second;
+      return BH_OK;
+    }
+  }
+  int levels = 0;
+  while ((n0 >> levels) >= 1) ++levels;
+  std::vector<uint32_t> off(levels), ooff(levels);
+  uint64_t total = 0, owords = 0;
+  for (int l = 0; l < levels; ++l) {
+    off[l] = (uint32_t)total;
+    total += 6ull * (n0 >> l) * (n0 >> l);
+    ooff[l] = (uint32_t)owords;
+    owords += 6ull * (n0 >> l) * ((((n0 >> l) + 31) >> 5) + 1);
+  }
+  int fp16 = f->texel_format == BH_TEXEL_FP16;
+  size_t tsz = fp16 ? 8 : 16;
+  auto* s = new bh_stars;
+  s->ctx = c;
+  s->key = f->key;
+  s->n0 = n0;
+  s->levels = levels;
+  s->fp16 = fp16;
+  s->level_off = off;
+  s->occ_off = ooff;
+  size_t btex = tsz * total, bsc = sizeof(float) * levels, boff = sizeof(uint32_t) * levels;
+  size_t bocc = sizeof(uint32_t) * owords;
+  bh_status st = dev_alloc(c, btex, &s->tex);
+  if (!st) st = dev_alloc(c, bsc, (void**)&s->scale);
+  if (!st) st = dev_alloc(c, boff, (void**)&s->level_off_dev);
+  if (!st) st = dev_alloc(c, bocc, (void**)&s->occ);
+  if (!st) st = dev_alloc(c, boff, (void**)&s->occ_off_dev);
+  s->occ_bytes = bocc;
+  // build scratch (freed below)
+  int64_t ntex0 = 6ll * n0 * n0, n = f->n;
+  size_t bhead = sizeof(int) * ntex0, bnext = sizeof(int) * std::max<int64_t>(n, 1),
+         bpos = sizeof(float2) * std::max<int64_t>(n, 1), bmaster = sizeof(float4) * total,
+         bmax = sizeof(unsigned) * 64;
+  int* head = nullptr;
+  int* next = nullptr;
+  float2* pos = nullptr;
+  float4* master = nullptr;
+  unsigned* maxbits = nullptr;
+  if (!st) st = dev_alloc(c, bhead, (void**)&head);
+  if (!st) st = dev_alloc(c, bnext, (void**)&next);
+  if (!st) st = dev_alloc(c, bpos, (void**)&pos);
+  if (!st) st = dev_alloc(c, bmaster, (void**)&master);
+  if (!st) st = dev_alloc(c, bmax, (void**)&maxbits);
+  hipError_t e = hipSuccess;
+  hipStream_t hs = (hipStream_t)stream;
+  if (!st) {
+    e = hipMemcpyAsync(s->level_off_dev, off.data(), boff, hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(s->occ_off_dev, ooff.data(), boff, hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess) e = launch_fill_int(head, ntex0, -1, hs);
+    if (e == hipSuccess) e = launch_fill_int((int*)maxbits, 64, 0, hs);
+    if (e == hipSuccess)
+      e = launch_star_build(f->dir_xyz_dev, f->intensity_dev, f->temperature_dev, n, n0, levels,
+                            off.data(), head, next, pos, master, maxbits, s->scale, fp16, s->tex,
+                            hs);
+    if (e == hipSuccess)
+      e = launch_star_occupancy(s->tex, n0, levels, off.data(), ooff.data(), fp16, s->occ, hs);
+    if (e == hipSuccess) e = hipStreamSynchronize(hs);
+  }
+  dev_free(c, head, head ? bhead : 0);
+  dev_free(c, next, next ? bnext : 0);
+  dev_free(c, pos, pos ? bpos : 0);
+  dev_free(c, master, master ? bmaster : 0);
+  dev_free(c, maxbits, maxbits ? bmax : 0);
+  if (st || e != hipSuccess) {
+    dev_free(c, s->tex, s->tex ? btex : 0);
+    dev_free(c, s->scale, s->scale ? bsc : 0);
+    dev_free(c, s->level_off_dev, s->level_off_dev ? boff : 0);
+    dev_free(c, s->occ, s->occ ? bocc : 0);
+    dev_free(c, s->occ_off_dev, s->occ_off_dev ? boff : 0);
+    delete s;
+    if (st) return st;
+    return fail(BH_EDEVICE, std::string("star build: ") + hipGetErrorString(e));
+  }
+  s->bytes = btex + bsc + 2 * boff + bocc;
+  if (f->key) c->stars[key] = s;
+  *out = s;
+  return BH_OK;
+}
+
+extern "C" bh_status bh_stars_download(const bh_stars* s, int32_t level, float* host) {
+  if (!s || !host) return fail(BH_EINVAL, "NULL argument");
+  if (level < 0 || level >= s->levels) return fail(BH_EINVAL, "bad level");
+  bh_ctx* c = s->ctx;
+  HIPCHK(hipSetDevice(c->device));
+  int64_t cnt = 6ll * (s->n0 >> level) * (s->n0 >> level);
+  float scale = 1.0f;
+  HIPCHK(hipMemcpy(&scale, s->scale + level, sizeof(float), hipMemcpyDeviceToHost));
+  float4* tmp = nullptr;
+  HIPCHK(hipMalloc(&tmp, sizeof(float4) * cnt));
+  size_t tsz = s->fp16 ? 8 : 16;
+  hipError_t e = launch_star_unpack((const char*)s->tex + tsz * s->level_off[level], cnt, scale,
+                                    s->fp16, tmp, nullptr);
+  if (e == hipSuccess) e = hipMemcpy(host, tmp, sizeof(float4) * cnt, hipMemcpyDeviceToHost);
+  (void)hipFree(tmp);
+  if (e != hipSuccess) return fail(BH_EDEVICE, hipGetErrorString(e));
+  return BH_OK;
+}
+
+extern "C" bh_status bh_release_stars(bh_stars* s) {
+  if (!s) return fail(BH_EINVAL, "NULL stars");
+  bh_ctx* c = s->ctx;
+  std::lock_guard<std::mutex> g(c->mu);
+  if (--s->refs > 0) return BH_OK;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  if (s->key) c->stars.erase(std::make_tuple(s->key, s->n0, s->fp16 ? BH_TEXEL_FP16 : BH_TEXEL_FP32));
+  size_t tsz = s->fp16 ? 8 : 16;
+  uint64_t total = 0;
+  for (int l = 0; l < s->levels; ++l) total += 6ull * (s->n0 >> l) * (s->n0 >> l);
+  dev_free(c, s->tex, tsz * total);
+  dev_free(c, s->scale, sizeof(float) * s->levels);
+  dev_free(c, s->level_off_dev, sizeof(uint32_t) * s->levels);
+  dev_free(c, s->occ, s->occ_bytes);
+  dev_free(c, s->occ_off_dev, sizeof(uint32_t) * s->levels);
+  delete s;
+  return BH_OK;
+}
+
+// ---- views ---------------------------------------------------------------------------------
+
+static bool finite_all(const double* p, int n) {
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+// Validate a view and build its constant block in FP64 (Section 3.2, Appendix C: the
+// camera basis is O B(v) R; here O is given directly as cam_rot in the boosted frame).
+static bh_status make_view(const bh_view* v, float* out, float* aov, ViewDev* o) {
+  if (!v) return fail(BH_EINVAL, "NULL view");
+  double sc[] = {v->r_s, v->fov_y, v->disc_r_in, v->disc_r_out, v->disc_T0, v->disc_T_exp,
+                 v->disc_opacity, v->k_disc, v->k_star};
+  if (!finite_all(sc, 9) || !finite_all(v->cam_pos, 3) || !finite_all(v->cam_vel, 3) ||
+      !finite_all(v->cam_rot, 9))
+    return fail(BH_EINVAL, "non-finite view parameter");
+  if (!(v->r_s > 0)) return fail(BH_EINVAL, "r_s must be > 0");
+  double r = std::sqrt(v->cam_pos[0] * v->cam_pos[0] + v->cam_pos[1] * v->cam_pos[1] +
+                       v->cam_pos[2] * v->cam_pos[2]) / v->r_s;
+  if (!(r > 1.0)) return fail(BH_EINVAL, "camera must be outside the horizon (|cam_pos| > r_s)");
+  double vm = std::sqrt(v->cam_vel[0] * v->cam_vel[0] + v->cam_vel[1] * v->cam_vel[1] +
+                        v->cam_vel[2] * v->cam_vel[2]);
+  if (!(vm < 1.0)) return fail(BH_EINVAL, "camera speed must be < c");
+  if (!(v->fov_y > 0 && v->fov_y < M_PI)) return fail(BH_EINVAL, "fov_y must be in (0, pi)");
+  if (v->width < 1 || v->height < 1 || v->width > 65536 || v->height > 65536)
+    return fail(BH_EINVAL, "bad image size");
+  if (!(v->disc_r_in >= 3.0 * v->r_s * (1.0 - 1e-12)))
+    return fail(BH_EINVAL, "disc_r_in must be >= 3 r_s (innermost stable circular orbit)");
+  if (!(v->disc_r_out > v->disc_r_in)) return fail(BH_EINVAL, "disc_r_out must exceed disc_r_in");
+  if (!(v->disc_opacity >= 0 && v->disc_opacity <= 1)) return fail(BH_EINVAL, "opacity must be in [0,1]");
+  if (v->disc_T_law != BH_T_POWER && v->disc_T_law != BH_T_PAPER) return fail(BH_EINVAL, "bad T law");
+  if (!(v->disc_T0 >= 0)) return fail(BH_EINVAL, "disc_T0 must be >= 0");
+  const double* R = v->cam_rot;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double d = R[3 * i] * R[3 * j] + R[3 * i + 1] * R[3 * j + 1] + R[3 * i + 2] * R[3 * j + 2];
+      if (std::fabs(d - (i == j ? 1.0 : 0.0)) > 1e-6) return fail(BH_EINVAL, "cam_rot is not orthonormal");
+    }
+  if (!out) return fail(BH_EINVAL, "NULL output");
+  memset(o, 0, sizeof(*o));
+  double u = 1.0 / r;
+  for (int i = 0; i < 3; ++i) {
+    o->rhat[i] = (float)(v->cam_pos[i] / (r * v->r_s));
+    o->ew[i] = (float)R[i];
+    o->eh[i] = (float)R[3 + i];
+    o->ed[i] = (float)R[6 + i];
+    o->vhat[i] = vm > 0 ? (float)(v->cam_vel[i] / vm) : 0.0f;
+  }
+  o->sq1mu = (float)std::sqrt(1.0 - u);
+  o->inv_sq1mu = (float)(1.0 / std::sqrt(1.0 - u));
+  o->u_c = (float)u;
+  o->f = (float)(0.5 * v->height / std::tan(0.5 * v->fov_y));
+  o->gamma = (float)(1.0 / std::sqrt(1.0 - vm * vm));
+  o->vmag = (float)vm;
+  o->half_w = (float)(0.5 * v->width);
+  o->half_h = (float)(0.5 * v->height);
+  o->u_ic = (float)(v->r_s / v->disc_r_in);
+  o->u_oc = (float)(v->r_s / v->disc_r_out);
+  o->T0 = (float)v->disc_T0;
+  o->T_exp = (float)v->disc_T_exp;
+  o->T_law = v->disc_T_law;
+  double pk = 6.0 / 7.0;  // maximum of s^6 (1 - s) / 27 at s = sqrt(3u) = 6/7
+  o->T_norm = (float)(27.0 / (std::pow(pk, 6) * (1.0 - pk)));
+  o->rho = (float)v->disc_opacity;
+  o->k_disc = (float)v->k_disc;
+  o->k_star = (float)v->k_star;
+  o->width = v->width;
+  o->height = v->height;
+  if (v->stars) {
+    const bh_stars* s = v->stars;
+    o->has_stars = 1;
+    o->stars.tex = s->tex;
+    o->stars.scale = s->scale;
+    o->stars.level_off = s->level_off_dev;
+    o->stars.occ = s->occ;
+    o->stars.occ_off = s->occ_off_dev;
+    o->stars.n0 = s->n0;
+    o->stars.levels = s->levels;
+    o->stars.fp16 = s->fp16;
+  }
+  o->out = (float4*)out;
+  o->aov = (float4*)aov;
+  return BH_OK;
+}
+
+static TablesDev tables_dev(const bh_tables* t) {
+  TablesDev T;
+  T.D = t->D;
+  T.U = t->U;
+  T.d_n = t->p.d_n;
+  T.u_ne = t->p.u_ne;
+  T.u_nphi = t->p.u_nphi;
+  T.pad = 0;
+  return T;
+}
+
+static LutDev lut_dev(const bh_ctx* c) {
+  LutDev L;
+  L.lut = c->lut;
+  L.n = c->lut_n;
+  L.x0 = c->lut_x0;
+  L.inv_dx = 1.0f / c->lut_dx;
+  L.pad = 0;
+  return L;
+}
+
+extern "C" bh_status bh_render(bh_ctx* c, const bh_tables* t, const bh_view* v, float* out,
+                               float* aov, void* stream) {
+  if (!c || !t) return fail(BH_EINVAL, "NULL context or tables");
+  ViewDev vd;
+  bh_status st = make_view(v, out, aov, &vd);
+  if (st) return st;
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(launch_render(c->tile_cfg, vd, tables_dev(t), lut_dev(c), (hipStream_t)stream));
+  return BH_OK;
+}
+
+// ---- batched launches ------------------------------------------------------------------------
+
+extern "C" int32_t bh_tile_config_count(void) { return tile_config_count(); }
+
+extern "C" bh_status bh_tile_config_get(int32_t i, bh_tile_config* o) {
+  if (!o || i < 0 || i >= tile_config_count()) return fail(BH_EINVAL, "bad tile config index");
+  tile_config(i, &o->tile_w, &o->tile_h, &o->waves, &o->ppt);
+  return BH_OK;
+}
+
+extern "C" bh_status bh_set_tile_config(bh_ctx* c, int32_t i) {
+  if (!c || i < -1 || i >= tile_config_count()) return fail(BH_EINVAL, "bad tile config index");
+  std::lock_guard<std::mutex> g(c->mu);
+  c->tile_cfg = i < 0 ? 0 : i;
+  return BH_OK;
+}
+
+// Upload view blocks + work items through a pinned staging buffer and enqueue one
+// persistent launch.  Caller holds c->mu.
+static bh_status enqueue_batch(bh_ctx* c, const TablesDev& T, const std::vector<ViewDev>& vds,
+                               const std::vector<WorkItem>& items, ViewDev* dviews,
+                               WorkItem* ditems, int* counter, Staging& stg, hipStream_t s,
+                               bool use_graph) {
+  size_t bv = sizeof(ViewDev) * vds.size(), bi = sizeof(WorkItem) * items.size();
+  bh_status st = ensure_staging(stg, bv + bi);
+  if (st) return st;
+  if (stg.used) HIPCHK(hipEventSynchronize(stg.done));
+  memcpy(stg.host, vds.data(), bv);
+  memcpy((char*)stg.host + bv, items.data(), bi);
+  HIPCHK(hipMemcpyAsync(dviews, stg.host, bv, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(ditems, (char*)stg.host + bv, bi, hipMemcpyHostToDevice, s));
+  HIPCHK(hipEventRecord(stg.done, s));
+  stg.used = true;
+  int cfg = c->tile_cfg;
+  int pers = c->persistent;
+  int tw, th, waves, ppt;
+  tile_config(cfg, &tw, &th, &waves, &ppt);
+  int per_cu = std::max(1, 16 / waves);
+  int grid = std::min<int>((int)items.size(), c->cus * per_cu);
+  grid = std::max(grid, 1);
+  LutDev L = lut_dev(c);
+  if (!use_graph) {
+    HIPCHK(launch_render_batch(cfg, pers, dviews, ditems, (int)items.size(), counter, T, L, grid, s));
+    return BH_OK;
+  }
+  auto key = std::make_tuple(cfg * 2 + pers, (int)items.size(), grid, (const void*)T.D,
+                             (uintptr_t)counter);
+  auto it = c->graphs.find(key);
+  if (it == c->graphs.end()) {
+    hipStream_t cap;
+    HIPCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipGraph_t graph;
+    HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    hipError_t e = launch_render_batch(cfg, pers, dviews, ditems, (int)items.size(), counter, T, L,
+                                       grid, cap);
+    hipError_t e2 = hipStreamEndCapture(cap, &graph);
+    (void)hipStreamDestroy(cap);
+    if (e != hipSuccess || e2 != hipSuccess)
+      return fail(BH_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+    hipGraphExec_t exec;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(BH_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+    it = c->graphs.emplace(key, bh_ctx::GraphEntry{exec, s}).first;
+  }
+  HIPCHK(hipGraphLaunch(it->second.exec, s));
+  return BH_OK;
+}
+
+static void clear_graphs(bh_ctx* c) {
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second.exec);
+  c->graphs.clear();
+}
+
+static bh_status ensure_batch_buffers(bh_ctx* c, size_t nviews, size_t nitems) {
+  if (c->b_views_cap < nviews || c->b_items_cap < nitems) {
+    // captured graphs hold the old buffer addresses
+    if (c->b_last) HIPCHK(hipEventSynchronize(c->b_last));
+    clear_graphs(c);
+  }
+  if (c->b_views_cap < nviews) {
+    dev_free(c, c->b_views, sizeof(ViewDev) * c->b_views_cap);
+    c->b_views = nullptr;
+    c->b_views_cap = 0;
+    size_t cap = std::max<size_t>(nviews, 64);
+    bh_status st = dev_alloc(c, sizeof(ViewDev) * cap, (void**)&c->b_views);
+    if (st) return st;
+    c->b_views_cap = cap;
+  }
+  if (c->b_items_cap < nitems) {
+    dev_free(c, c->b_items, sizeof(WorkItem) * c->b_items_cap);
+    c->b_items = nullptr;
+    c->b_items_cap = 0;
+    size_t cap = std::max<size_t>(nitems, 4096);
+    bh_status st = dev_alloc(c, sizeof(WorkItem) * cap, (void**)&c->b_items);
+    if (st) return st;
+    c->b_items_cap = cap;
+  }
+  return BH_OK;
+}
+
+static void tile_items(int vi, int width, int height, int tw, int th, std::vector<WorkItem>& items) {
+  int tx = (width + tw - 1) / tw, ty = (height + th - 1) / th;
+  for (int y = 0; y < ty; ++y)
+    for (int x = 0; x < tx; ++x) items.push_back(WorkItem{vi, x * tw, y * th, 0});
+}
+
+extern "C" bh_status bh_render_batch(bh_ctx* c, const bh_tables* t, const bh_view* views,
+                                     int32_t n, float* const* outs, void* stream) {
+  if (!c || !t || !views || !outs || n < 1) return fail(BH_EINVAL, "bad batch arguments");
+  std::vector<ViewDev> vds(n);
+  for (int i = 0; i < n; ++i) {
+    bh_status st = make_view(&views[i], outs[i], nullptr, &vds[i]);
+    if (st) return fail(st, "view " + std::to_string(i) + ": " + g_err);
+  }
+  HIPCHK(hipSetDevice(c->device));
+  std::lock_guard<std::mutex> g(c->mu);
+  int tw, th, waves, ppt;
+  tile_config(c->tile_cfg, &tw, &th, &waves, &ppt);
+  // largest views first so the persistent workgroups end together
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return (int64_t)views[a].width * views[a].height > (int64_t)views[b].width * views[b].height;
+  });
+  std::vector<WorkItem> items;
+  for (int i : order) tile_items(i, views[i].width, views[i].height, tw, th, items);
+  if (items.size() >= (size_t)1 << 31) return fail(BH_EINVAL, "too many tiles");
+  bh_status st = ensure_batch_buffers(c, n, items.size());
+  if (st) return st;
+  Staging& stg = c->b_stage[c->b_next_stage];
+  c->b_next_stage ^= 1;
+  hipStream_t s = (hipStream_t)stream;
+  // the view/work buffers are shared by every batched call on this context: order this
+  // call after the previous one even when it was issued on another stream
+  if (!c->b_last) HIPCHK(hipEventCreateWithFlags(&c->b_last, hipEventDisableTiming));
+  else HIPCHK(hipStreamWaitEvent(s, c->b_last, 0));
+  st = enqueue_batch(c, tables_dev(t), vds, items, c->b_views, c->b_items, c->b_counter, stg, s,
+                     true);
+  if (st) return st;
+  HIPCHK(hipEventRecord(c->b_last, s));
+  return BH_OK;
+}
+
+extern "C" bh_status bh_autotune(bh_ctx* c, const bh_tables* t, const bh_view* views, int32_t n,
+                                 float* const* outs, int32_t reps, int32_t* best,
+                                 float* ms_per_config) {
+  if (!c || !t || !views || !outs || n < 1 || reps < 1) return fail(BH_EINVAL, "bad autotune arguments");
+  HIPCHK(hipSetDevice(c->device));
+  hipStream_t s;
+  HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  int nc = tile_config_count(), bi = 0, bp = 0;
+  float bms = 1e30f;
+  bh_status st = BH_OK;
+  for (int kk = 0; kk < 2 * nc && !st; ++kk) {
+    int k = kk >> 1, pers = kk & 1;
+    st = bh_set_tile_config(c, k);
+    {
+      std::lock_guard<std::mutex> g(c->mu);
+      c->persistent = pers;
+    }
+    if (!st) st = bh_render_batch(c, t, views, n, outs, s);  // warm-up and graph build
+    if (st) break;
+    HIPCHK(hipEventRecord(e0, s));
+    for (int r = 0; r < reps && !st; ++r) st = bh_render_batch(c, t, views, n, outs, s);
+    HIPCHK(hipEventRecord(e1, s));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    ms /= reps;
+    if (ms_per_config) ms_per_config[kk] = ms;
+    if (ms < bms) {
+      bms = ms;
+      bi = k;
+      bp = pers;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipStreamDestroy(s);
+  if (st) return st;
+  bh_set_tile_config(c, bi);
+  {
+    std::lock_guard<std::mutex> g(c->mu);
+    c->persistent = bp;
+  }
+  if (best) *best = 2 * bi + bp;
+  return BH_OK;
+}
+
+// ---- unit-level entry points -------------------------------------------------------------------
+
+extern "C" bh_status bh_trace_rays(bh_ctx* c, const bh_tables* t, const float* rays, int64_t n,
+                                   float* out, void* stream) {
+  if (!c || !t || (n > 0 && (!rays || !out)) || n < 0) return fail(BH_EINVAL, "bad arguments");
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(launch_trace_rays(tables_dev(t), rays, n, (float4*)out, (hipStream_t)stream));
+  return BH_OK;
+}
+
+extern "C" bh_status bh_footprint_texels(bh_ctx* c, const bh_tables* t, const bh_view* v,
+                                         float* out, uint64_t* texels) {
+  if (!c || !t || !texels) return fail(BH_EINVAL, "NULL argument");
+  if (!v || !v->stars) return fail(BH_EINVAL, "view without a star map");
+  ViewDev vd;
+  bh_status st = make_view(v, out, nullptr, &vd);
+  if (st) return st;
+  HIPCHK(hipSetDevice(c->device));
+  const bh_stars* s = v->stars;
+  uint64_t total = 0;
+  for (int l = 0; l < s->levels; ++l) total += 6ull * (s->n0 >> l) * (s->n0 >> l);
+  int64_t words = (int64_t)((total + 31) / 32);
+  uint32_t* bits = nullptr;
+  unsigned long long* cnt = nullptr;
+  HIPCHK(hipMalloc(&bits, sizeof(uint32_t) * words));
+  hipError_t e = hipMalloc(&cnt, sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipMemset(bits, 0, sizeof(uint32_t) * words);
+  if (e == hipSuccess) e = hipMemset(cnt, 0, sizeof(unsigned long long));
+  if (e == hipSuccess) e = launch_render_count(vd, tables_dev(t), lut_dev(c), bits, words, cnt, nullptr);
+  unsigned long long h = 0;
+  if (e == hipSuccess) e = hipMemcpy(&h, cnt, sizeof(h), hipMemcpyDeviceToHost);
+  (void)hipFree(bits);
+  if (cnt) (void)hipFree(cnt);
+  if (e != hipSuccess) return fail(BH_EDEVICE, std::string("footprint count: ") + hipGetErrorString(e));
+  *texels = h;
+  return BH_OK;
+}
+
+extern "C" bh_status bh_band_table_info(const bh_ctx* c, int32_t* n, float* x0, float* dx) {
+  if (!c || !n || !x0 || !dx) return fail(BH_EINVAL, "NULL argument");
+  *n = c->lut_n;
+  *x0 = c->lut_x0;
+  *dx = c->lut_dx;
+  return BH_OK;
+}
+
+extern "C" bh_status bh_band_table_download(const bh_ctx* c, float* host) {
+  if (!c || !host) return fail(BH_EINVAL, "NULL argument");
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(hipMemcpy(host, c->lut, sizeof(float4) * c->lut_n, hipMemcpyDeviceToHost));
+  return BH_OK;
+}
+
+extern "C" bh_status bh_band_eval(bh_ctx* c, const float* temps, int64_t n, float* out,
+                                  void* stream) {
+  if (!c || n < 0 || (n > 0 && (!temps || !out))) return fail(BH_EINVAL, "bad arguments");
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(launch_band_eval(lut_dev(c), temps, n, out, (hipStream_t)stream));
+  return BH_OK;
+}
+
+// ---- serving ---------------------------------------------------------------------------------
+// One scheduler thread per context.  Each iteration admits queued requests in arrival
+// order while their library-allocated images fit the HBM budget, then fills one
+// persistent launch with up to max_tiles_per_launch tiles taken from the admitted requests
+// in order (a big frame spills into later launches, so frames that arrive meanwhile join
+// the next launch instead of waiting behind it).  Up to max_inflight_launches launches are
+// kept queued on the serving stream; a request completes with the launch holding its last
+// tile.
+
+// Library-allocated images: reuse a freed image of the same size, else allocate inside
+// the budget, releasing pooled images if that is what it takes.  Caller holds c->smu.
+static void* pool_get(bh_ctx* c, size_t bytes) {
+  auto it = c->pool.find(bytes);
+  if (it != c->pool.end()) {
+    void* p = it->second;
+    c->pool.erase(it);
+    return p;
+  }
+  for (;;) {
+    void* p = nullptr;
+    if (dev_alloc(c, bytes, &p) == BH_OK) return p;
+    if (c->pool.empty()) return nullptr;
+    auto big = std::prev(c->pool.end());
+    dev_free(c, big->second, big->first);
+    c->pool.erase(big);
+  }
+}
+
+static void pool_put(bh_ctx* c, void* p, size_t bytes) { c->pool.emplace(bytes, p); }
+
+static void finish_launch(bh_ctx* c, Launch& L) {
+  double t = now_s();
+  std::lock_guard<std::mutex> g(c->smu);
+  for (uint64_t tk : L.finishing) {
+    auto it = c->reqs.find(tk);
+    if (it == c->reqs.end()) continue;
+    it->second->done = true;
+    it->second->t_done = t;
+    c->pending--;
+  }
+  c->done_cv.notify_all();
+}
+
+static void serve_loop(bh_ctx* c) {
+  (void)hipSetDevice(c->device);
+  const int maxin = std::max(1, c->sp.max_inflight_launches);
+  const int64_t maxtiles = std::max<int64_t>(1, c->sp.max_tiles_per_launch);
+  std::vector<Staging> stg(maxin + 1);
+  std::vector<ViewDev*> dviews(maxin + 1, nullptr);
+  std::vector<WorkItem*> ditems(maxin + 1, nullptr);
+  std::vector<int*> dcounter(maxin + 1, nullptr);
+  std::vector<size_t> vcap(maxin + 1, 0), icap(maxin + 1, 0);
+  for (int k = 0; k <= maxin; ++k) {
+    (void)hipMalloc(&dcounter[k], sizeof(int) * 16);
+  }
+  std::deque<Launch> inflight;
+  std::vector<hipEvent_t> evpool;
+  int slot = 0;
+  std::vector<ServeReq*> active;
+  for (;;) {
+    // retire finished launches
+    while (!inflight.empty() && hipEventQuery(inflight.front().ev) == hipSuccess) {
+      finish_launch(c, inflight.front());
+      evpool.push_back(inflight.front().ev);
+      inflight.pop_front();
+    }
+    std::vector<ServeReq*> admit_now;
+    {
+      std::unique_lock<std::mutex> lk(c->smu);
+      if (c->stop && c->queue.empty() && active.empty() && inflight.empty()) break;
+      // admission: FIFO, stop at the first request that does not fit the budget
+      while (!c->queue.empty()) {
+        ServeReq* r = c->queue.front();
+        if (!r->out) {
+          void* p = pool_get(c, r->out_bytes);
+          if (!p) break;
+          r->out = (float*)p;
+          r->owned = true;
+        }
+        r->admitted = true;
+        c->queue.pop_front();
+        active.push_back(r);
+      }
+      if (active.empty() && inflight.empty()) {
+        if (c->stop) continue;
+        c->scv.wait_for(lk, std::chrono::milliseconds(2));
+        continue;
+      }
+    }
+    if (active.empty()) {
+      // launches in flight, nothing to add: poll so new arrivals are admitted at once
+      std::unique_lock<std::mutex> lk(c->smu);
+      c->scv.wait_for(lk, std::chrono::microseconds(50));
+      continue;
+    }
+    if ((int)inflight.size() >= maxin) {
+      (void)hipEventSynchronize(inflight.front().ev);  // the device is busy: wait for a slot
+      continue;
+    }
+    // fill one launch
+    std::vector<ViewDev> vds;
+    std::vector<WorkItem> items;
+    Launch L;
+    std::vector<ServeReq*> keep;
+    int tw, th, waves, ppt;
+    tile_config(c->tile_cfg, &tw, &th, &waves, &ppt);
+    const bh_tables* tb = active.front()->tables;  // one table set per launch
+    for (ServeReq* r : active) {
+      if ((int64_t)items.size() >= maxtiles || r->tables != tb) {
+        keep.push_back(r);
+        continue;
+      }
+      if (r->tiles_total == 0) {
+        r->tiles_x = (r->view.width + tw - 1) / tw;
+        r->tiles_total = r->tiles_x * ((r->view.height + th - 1) / th);
+      }
+      ViewDev vd;
+      if (make_view(&r->view, r->out, nullptr, &vd) != BH_OK) {  // validated at submit
+        r->status = BH_EINVAL;
+        L.finishing.push_back(r->ticket);
+        continue;
+      }
+      int vi = (int)vds.size();
+      vds.push_back(vd);
+      int64_t take = std::min<int64_t>(r->tiles_total - r->tiles_next, maxtiles - (int64_t)items.size());
+      for (int64_t k = 0; k < take; ++k) {
+        int tt = r->tiles_next + (int)k;
+        items.push_back(WorkItem{vi, (tt % r->tiles_x) * tw, (tt / r->tiles_x) * th, 0});
+      }
+      r->tiles_next += (int)take;
+      if (r->tiles_next >= r->tiles_total)
+        L.finishing.push_back(r->ticket);
+      else
+        keep.push_back(r);
+    }
+    active.swap(keep);
+    if (items.empty()) {
+      if (!L.finishing.empty()) finish_launch(c, L);
+      continue;
+    }
+    // device buffers of this slot
+    if (vcap[slot] < vds.size()) {
+      if (dviews[slot]) (void)hipFree(dviews[slot]);
+      vcap[slot] = std::max<size_t>(vds.size(), 256);
+      (void)hipMalloc(&dviews[slot], sizeof(ViewDev) * vcap[slot]);
+    }
+    if (icap[slot] < items.size()) {
+      if (ditems[slot]) (void)hipFree(ditems[slot]);
+      icap[slot] = std::max<size_t>(items.size(), (size_t)maxtiles);
+      (void)hipMalloc(&ditems[slot], sizeof(WorkItem) * icap[slot]);
+    }
+    bh_status st;
+    {
+      std::lock_guard<std::mutex> g(c->mu);
+      st = enqueue_batch(c, tables_dev(tb), vds, items, dviews[slot], ditems[slot], dcounter[slot],
+                         stg[slot], c->serve_stream, false);
+    }
+    if (evpool.empty()) {
+      hipEvent_t ev;
+      (void)hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+      evpool.push_back(ev);
+    }
+    L.ev = evpool.back();
+    evpool.pop_back();
+    (void)hipEventRecord(L.ev, c->serve_stream);
+    if (st != BH_OK) {
+      std::lock_guard<std::mutex> lk(c->smu);
+      for (uint64_t tk : L.finishing) c->reqs[tk]->status = BH_EDEVICE;
+    }
+    L.slot = slot;
+    slot = (slot + 1) % (maxin + 1);
+    inflight.push_back(L);
+  }
+  (void)hipStreamSynchronize(c->serve_stream);
+  for (int k = 0; k <= maxin; ++k) {
+    if (dviews[k]) (void)hipFree(dviews[k]);
+    if (ditems[k]) (void)hipFree(ditems[k]);
+    if (dcounter[k]) (void)hipFree(dcounter[k]);
+    if (stg[k].host) (void)hipHostFree(stg[k].host);
+    if (stg[k].done) (void)hipEventDestroy(stg[k].done);
+  }
+  for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
+}
+
+extern "C" bh_status bh_serve_start(bh_ctx* c, const bh_serve_params* p) {
+  if (!c) return fail(BH_EINVAL, "NULL context");
+  std::lock_guard<std::mutex> lk(c->smu);
+  if (c->serving) return fail(BH_EINVAL, "serving already started");
+  c->sp.max_queue = p && p->max_queue > 0 ? p->max_queue : 1 << 20;
+  c->sp.max_inflight_launches = p && p->max_inflight_launches > 0 ? p->max_inflight_launches : 2;
+  c->sp.max_tiles_per_launch = p && p->max_tiles_per_launch > 0 ? p->max_tiles_per_launch : 16384;
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(hipStreamCreateWithFlags(&c->serve_stream, hipStreamNonBlocking));
+  c->stop = false;
+  c->serving = true;
+  c->serve_thread = std::thread(serve_loop, c);
+  return BH_OK;
+}
+
+static void serve_stop(bh_ctx* c) {
+  {
+    std::lock_guard<std::mutex> lk(c->smu);
+    if (!c->serving) return;
+    // queued requests that were never admitted are cancelled
+    for (ServeReq* r : c->queue) {
+      r->status = BH_ECANCELED;
+      r->done = true;
+      c->pending--;
+    }
+    c->queue.clear();
+    c->stop = true;
+  }
+  c->scv.notify_all();
+  c->serve_thread.join();
+  (void)hipStreamDestroy(c->serve_stream);
+  c->serving = false;
+  for (auto& kv : c->reqs) {
+    if (kv.second->owned) dev_free(c, kv.second->out, kv.second->out_bytes);
+    delete kv.second;
+  }
+  c->reqs.clear();
+  for (auto& kv : c->pool) dev_free(c, kv.second, kv.first);
+  c->pool.clear();
+}
+
+extern "C" bh_status bh_submit(bh_ctx* c, const bh_tables* t, const bh_view* v, float* out,
+                               uint64_t* ticket) {
+  if (!c || !t || !v || !ticket) return fail(BH_EINVAL, "NULL argument");
+  ViewDev tmp;
+  float dummy = 0;
+  bh_status st = make_view(v, out ? out : &dummy, nullptr, &tmp);
+  if (st) return st;
+  std::lock_guard<std::mutex> lk(c->smu);
+  if (!c->serving) return fail(BH_EINVAL, "serving not started");
+  if ((int)c->queue.size() >= c->sp.max_queue) return fail(BH_EAGAIN, "serving queue full");
+  auto* r = new ServeReq;
+  r->ticket = c->next_ticket++;
+  r->view = *v;
+  r->tables = t;
+  r->out = out;
+  r->out_bytes = sizeof(float4) * (size_t)v->width * v->height;
+  if (!out && c->budget && r->out_bytes > c->budget) {
+    delete r;
+    return fail(BH_ENOMEM, "image larger than the HBM budget");
+  }
+  r->t_submit = now_s();
+  c->reqs[r->ticket] = r;
+  c->queue.push_back(r);
+  c->pending++;
+  *ticket = r->ticket;
+  c->scv.notify_all();
+  return BH_OK;
+}
+
+extern "C" bh_status bh_poll(bh_ctx* c, uint64_t ticket, int32_t* done, double* latency) {
+  if (!c || !done) return fail(BH_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(c->smu);
+  auto it = c->reqs.find(ticket);
+  if (it == c->reqs.end()) return fail(BH_ENOTFOUND, "unknown ticket");
+  ServeReq* r = it->second;
+  *done = r->done ? 1 : 0;
+  if (latency) *latency = r->done ? r->t_done - r->t_submit : now_s() - r->t_submit;
+  return r->status;
+}
+
+extern "C" bh_status bh_ticket_image(bh_ctx* c, uint64_t ticket, float** img) {
+  if (!c || !img) return fail(BH_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(c->smu);
+  auto it = c->reqs.find(ticket);
+  if (it == c->reqs.end()) return fail(BH_ENOTFOUND, "unknown ticket");
+  if (!it->second->done) return fail(BH_EAGAIN, "not finished");
+  *img = it->second->out;
+  return BH_OK;
+}
+
+extern "C" bh_status bh_ticket_free(bh_ctx* c, uint64_t ticket) {
+  if (!c) return fail(BH_EINVAL, "NULL context");
+  std::lock_guard<std::mutex> lk(c->smu);
+  auto it = c->reqs.find(ticket);
+  if (it == c->reqs.end()) return fail(BH_ENOTFOUND, "unknown ticket");
+  if (!it->second->done) return fail(BH_EAGAIN, "not finished");
+  if (it->second->owned) pool_put(c, it->second->out, it->second->out_bytes);
+  delete it->second;
+  c->reqs.erase(it);
+  c->scv.notify_all();  // freed budget may admit queued requests
+  return BH_OK;
+}
+
+extern "C" bh_status bh_serve_drain(bh_ctx* c) {
+  if (!c) return fail(BH_EINVAL, "NULL context");
+  std::unique_lock<std::mutex> lk(c->smu);
+  c->done_cv.wait(lk, [&] { return c->pending == 0; });
+  return BH_OK;
+}

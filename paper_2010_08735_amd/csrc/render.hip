@@ -1,0 +1,537 @@
+// Per-pixel beam tracer (Sections 3.2-3.4) for gfx950.
+//
+// Thread layout: one wavefront covers an 8x8 pixel block; lane l handles quad l >> 2 of
+// the block (4x4 quads) and pixel (l & 1, (l >> 1) & 1) inside the quad, so the 2x2 quad
+// partners needed for screen-space derivatives are lanes l^1 (same row) and l^2 (same
+// column) and are read with DPP quad permutes.  A workgroup tile is TW x TH pixels made of
+// 8x8 blocks; each wave walks PPT blocks.  Pixels outside the image are computed (their
+// rays are valid) but not stored, so every quad is complete.
+//
+// Steps per pixel:
+//   beam init   camera direction n_C -> aberration into the static frame (eq. d) ->
+//               coordinate direction d (e_r has length sqrt(1-u), eq. staticbasis) ->
+//               ray plane e_x', e_y', e_z', angle delta, disc angle alpha (eqs. raybasis,
+//               alpha)
+//   TraceRay    Algorithm 1 with bilinear fetches of D(e,u), D(e,u_a) and U(e,phi)
+//   disc        T' from the temperature law, Doppler factor g(k,l)/g(k',l') with the
+//               Keplerian k' (eq. k_prime), band radiances of a blackbody at D T'
+//               (Section 3.4.2), front-to-back composite
+//   stars       fine quad differences of d' and q, face Jacobian, mip level such that the
+//               extended footprint spans at most 9x9 texels, tent-weighted gather
+//               f(w) f(h), lensing factor Omega/Omega', one Doppler shift per pixel.
+#include "bh_dev.h"
+
+namespace bh {
+
+struct __align__(8) Half4r {
+  _Float16 x, y, z, w;
+};
+
+__device__ __forceinline__ float4 load_texel(const StarsDev& S, uint32_t idx) {
+  if (S.fp16) {
+    Half4r h = ((const Half4r*)S.tex)[idx];
+    return make_float4((float)h.x, (float)h.y * 1024.0f, (float)h.z, (float)h.w);
+  }
+  return ((const float4*)S.tex)[idx];
+}
+
+struct TraceOut {
+  float dprime;        // escape angle (valid if !captured)
+  float ucr[2];
+  int ncross;
+  unsigned bits;
+};
+
+// Algorithm 1, TraceRay, in FP32.  Returns crossings in order along the beam.
+__device__ __forceinline__ TraceOut trace_ray(const TablesDev& T, float u, float delta,
+                                             float alpha, float cotd, float u_ic, float u_oc) {
+  TraceOut o;
+  o.ncross = 0;
+  o.ucr[0] = o.ucr[1] = 0.0f;
+  o.bits = 0;
+  o.dprime = 0.0f;
+  float udot = -u * cotd;
+  float e2 = udot * udot + u * u * (1.0f - u);
+  if (e2 < kMu && u > 2.0f / 3.0f) {
+    o.bits = BH_CAPTURED_BIT;
+    return o;
+  }
+  int s = udot >= 0.0f ? 1 : -1;
+  bool bound = e2 < kMu;
+  float ua = bound ? apsis_f(e2) : 0.0f;
+  float Dl = lookup_D(T, e2, u, ua, udot);
+  float Da = 0.0f, phia = __builtin_inff();
+  if (bound) {
+    Da = lookup_D(T, e2, ua, ua, 0.0f);
+    phia = Da + 0.5f * kPi;
+  }
+  float e = sqrtf(e2);
+  float phi = Dl + (s == 1 ? kPi - delta : delta) + (float)s * alpha;
+  float phi0 = phi - kPi * floorf(phi * (1.0f / kPi));
+  float u0 = lookup_U(T, e2, e, phi0);
+  int sg = (u0 > u) - (u0 < u);
+  if (phi0 < phia && u_oc <= u0 && u0 <= u_ic && sg == s) {
+    o.ucr[0] = u0;
+    o.ncross = 1;
+    o.bits |= BH_CROSS0_BIT;
+  }
+  if (bound && s == 1) {
+    phi = 2.0f * phia - phi;
+    float phi1 = phi - kPi * floorf(phi * (1.0f / kPi));
+    float u1 = lookup_U(T, e2, e, phi1);
+    if (phi1 < phia && u_oc <= u1 && u1 <= u_ic) {
+      // static indices only: a dynamically indexed array would be placed in LDS
+      if (o.ncross == 0) o.ucr[0] = u1; else o.ucr[1] = u1;
+      o.ncross += 1;
+      o.bits |= BH_CROSS1_BIT;
+    }
+  }
+  if (udot > 0.0f) {
+    if (bound) {
+      Dl = 2.0f * Da - Dl;
+    } else {
+      o.bits |= BH_CAPTURED_BIT;
+      return o;
+    }
+  }
+  o.dprime = delta + Dl;
+  return o;
+}
+
+__device__ __forceinline__ float disc_temperature(const ViewDev& v, float u) {
+  if (v.T_law == 1) {
+    float f = u * u * u * (1.0f - sqrtf(3.0f * u));
+    return f > 0.0f ? v.T0 * sqrtf(sqrtf(f * v.T_norm)) : 0.0f;
+  }
+  return v.T0 * exp2f(-v.T_exp * __log2f(3.0f * u));
+}
+
+__device__ __forceinline__ float quad_diff(float x, int mask, int hi) {
+  float p = __shfl_xor(x, mask);
+  return hi ? x - p : p - x;
+}
+
+// One pixel; every lane of the wave must call this together (quad exchanges).
+// COUNT: also mark every star-map texel the footprint visits in `touched` (one bit per
+// texel, measurement only).
+template <bool COUNT>
+__device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& T,
+                                             const LutDev& L, int px, int py,
+                                             uint32_t* touched) {
+  const int lane = threadIdx.x & 63;
+  const int hx = lane & 1, hy = (lane >> 1) & 1;
+
+  // ---- beam initialisation (Section 3.2)
+  float qw = (float)px + 0.5f - v.half_w;
+  float qh = v.half_h - (float)py - 0.5f;
+  float inq = rsqrtf(qw * qw + qh * qh + v.f * v.f);
+  float q0 = qw * inq, q1 = qh * inq, q2 = -v.f * inq;
+  float nc0 = q0 * v.ew[0] + q1 * v.eh[0] + q2 * v.ed[0];
+  float nc1 = q0 * v.ew[1] + q1 * v.eh[1] + q2 * v.ed[1];
+  float nc2 = q0 * v.ew[2] + q1 * v.eh[2] + q2 * v.ed[2];
+  float nv = nc0 * v.vhat[0] + nc1 * v.vhat[1] + nc2 * v.vhat[2];
+  float ka = (v.gamma - 1.0f) * nv - v.gamma * v.vmag;
+  float ns0 = nc0 + ka * v.vhat[0], ns1 = nc1 + ka * v.vhat[1], ns2 = nc2 + ka * v.vhat[2];
+  float dcam = __fdividef(v.inv_sq1mu, v.gamma * (1.0f - v.vmag * nv));
+  float nr = ns0 * v.rhat[0] + ns1 * v.rhat[1] + ns2 * v.rhat[2];
+  float kr = (v.sq1mu - 1.0f) * nr;
+  float d0 = ns0 + kr * v.rhat[0], d1 = ns1 + kr * v.rhat[1], d2 = ns2 + kr * v.rhat[2];
+  float cz0 = v.rhat[1] * d2 - v.rhat[2] * d1;
+  float cz1 = v.rhat[2] * d0 - v.rhat[0] * d2;
+  float cz2 = v.rhat[0] * d1 - v.rhat[1] * d0;
+  float ncz = sqrtf(cz0 * cz0 + cz1 * cz1 + cz2 * cz2);
+  float dr = d0 * v.rhat[0] + d1 * v.rhat[1] + d2 * v.rhat[2];
+  float dn = sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
+  unsigned bits = 0;
+  float u_ic = v.u_ic, u_oc = v.u_oc;
+  if (!(ncz > 1e-7f * dn)) {
+    // radial beam: any plane through it; pick one containing a fixed axis
+    bits |= BH_DEGENERATE_BIT;
+    float ax0 = fabsf(v.rhat[0]) < 0.9f ? 1.0f : 0.0f, ax1 = 1.0f - ax0;
+    cz0 = v.rhat[1] * 0.0f - v.rhat[2] * ax1;
+    cz1 = v.rhat[2] * ax0 - v.rhat[0] * 0.0f;
+    cz2 = v.rhat[0] * ax1 - v.rhat[1] * ax0;
+    float n2 = __fdividef(1.0f, sqrtf(cz0 * cz0 + cz1 * cz1 + cz2 * cz2));
+    cz0 *= n2; cz1 *= n2; cz2 *= n2;
+    ncz = fmaxf(ncz, 1e-7f * dn);
+    u_ic = -1.0f;
+  } else {
+    float inv = __fdividef(1.0f, ncz);
+    cz0 *= inv; cz1 *= inv; cz2 *= inv;
+  }
+  float delta = atan2f(ncz, dr);
+  // e_y' = e_z' x e_x'
+  float ey0 = cz1 * v.rhat[2] - cz2 * v.rhat[1];
+  float ey1 = cz2 * v.rhat[0] - cz0 * v.rhat[2];
+  float ey2 = cz0 * v.rhat[1] - cz1 * v.rhat[0];
+  // t = +-(e_z x e_z') with t.e_y' >= 0; alpha = angle(e_x', t)
+  float t0 = -cz1, t1 = cz0;
+  float nt = sqrtf(t0 * t0 + t1 * t1);
+  float alpha = 0.0f;
+  if (!(nt > 1e-7f)) {
+    bits |= BH_DEGENERATE_BIT;
+    u_ic = -1.0f;
+  } else {
+    float int_ = __fdividef(1.0f, nt);
+    float tx = (t0 * v.rhat[0] + t1 * v.rhat[1]) * int_;
+    float ty = (t0 * ey0 + t1 * ey1) * int_;
+    if (ty < 0.0f) {
+      tx = -tx;
+      ty = -ty;
+    }
+    alpha = atan2f(ty, tx);
+  }
+  float zeta = cz2;
+
+  // ---- TraceRay (Algorithm 1)
+  TraceOut tr = trace_ray(T, v.u_c, delta, alpha, dr / ncz, u_ic, u_oc);
+  bits |= tr.bits;
+  const bool captured = (tr.bits & BH_CAPTURED_BIT) != 0;
+
+  // ---- disc (Sections 3.3.3, 3.4.2), front to back
+  float cr = 0.0f, cg = 0.0f, cb = 0.0f, trans = 1.0f;
+  {
+    float u = v.u_c, cotd = dr / ncz;
+    float e = sqrtf((u * cotd) * (u * cotd) + u * u * (1.0f - u));
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      if (k >= tr.ncross) break;
+      float uk = k == 0 ? tr.ucr[0] : tr.ucr[1];
+      float Tp = disc_temperature(v, uk);
+      float kt = sqrtf(__fdividef(2.0f, 2.0f - 3.0f * uk));
+      float om = sqrtf(0.5f * uk * uk * uk);
+      float D = __fdividef(dcam, kt * (1.0f + __fdividef(om * zeta, e)));
+      float4 Lb = band_lookup(L, D * Tp);
+      float w = trans * v.rho * v.k_disc;
+      cr += w * Lb.x;
+      cg += w * Lb.y;
+      cb += w * Lb.z;
+      trans *= 1.0f - v.rho;
+    }
+  }
+
+  // ---- stars (Sections 3.3.2, 3.4.1)
+  float sdp, cdp;
+  sincosf(tr.dprime, &sdp, &cdp);
+  float dp0 = captured ? 0.0f : cdp * v.rhat[0] + sdp * ey0;
+  float dp1 = captured ? 0.0f : cdp * v.rhat[1] + sdp * ey1;
+  float dp2 = captured ? 0.0f : cdp * v.rhat[2] + sdp * ey2;
+  int cap = captured ? 1 : 0;
+  cap |= __shfl_xor(cap, 1);
+  cap |= __shfl_xor(cap, 2);
+  float dw0 = quad_diff(dp0, 1, hx), dw1 = quad_diff(dp1, 1, hx), dw2 = quad_diff(dp2, 1, hx);
+  float dh0 = quad_diff(dp0, 2, hy), dh1 = quad_diff(dp1, 2, hy), dh2 = quad_diff(dp2, 2, hy);
+  float qw0 = quad_diff(q0, 1, hx), qw1 = quad_diff(q1, 1, hx), qw2 = quad_diff(q2, 1, hx);
+  float qh0 = quad_diff(q0, 2, hy), qh1 = quad_diff(q1, 2, hy), qh2 = quad_diff(q2, 2, hy);
+  int mip = 255;
+  if (cap) bits |= BH_STAR_ZEROED_BIT;
+  if (v.has_stars && !cap) {
+    const StarsDev& S = v.stars;
+    float a0 = fabsf(dp0), a1 = fabsf(dp1), a2 = fabsf(dp2);
+    int k = 0;
+    float m = a0;
+    if (a1 > m) { k = 1; m = a1; }
+    if (a2 > m) { k = 2; m = a2; }
+    float dk = k == 0 ? dp0 : (k == 1 ? dp1 : dp2);
+    float da = k == 0 ? dp1 : (k == 1 ? dp2 : dp0);
+    float db = k == 0 ? dp2 : (k == 1 ? dp0 : dp1);
+    float wk = k == 0 ? dw0 : (k == 1 ? dw1 : dw2);
+    float wa = k == 0 ? dw1 : (k == 1 ? dw2 : dw0);
+    float wb = k == 0 ? dw2 : (k == 1 ? dw0 : dw1);
+    float hk = k == 0 ? dh0 : (k == 1 ? dh1 : dh2);
+    float ha = k == 0 ? dh1 : (k == 1 ? dh2 : dh0);
+    float hb = k == 0 ? dh2 : (k == 1 ? dh0 : dh1);
+    int face = 2 * k + (dk < 0.0f);
+    float sgk = dk < 0.0f ? -1.0f : 1.0f;
+    float im = __fdividef(1.0f, m);
+    float U = da * im, V = db * im;
+    float J00 = (wa - U * sgk * wk) * im, J01 = (ha - U * sgk * hk) * im;
+    float J10 = (wb - V * sgk * wk) * im, J11 = (hb - V * sgk * hk) * im;
+    float hu = fabsf(J00) + fabsf(J01), hv = fabsf(J10) + fabsf(J11);
+    float E0 = fmaxf(hu, hv) * (float)S.n0;
+    // smallest level with E0 / 2^L <= 8: from the exponent and mantissa of E0 / 8
+    int Lv = 0;
+    {
+      float q = E0 * 0.125f;
+      if (q > 1.0f) {
+        unsigned b = __float_as_uint(q);
+        int ex = (int)((b >> 23) & 255u) - 127;   // q = 1.m * 2^ex, q finite and > 1
+        Lv = ex + ((b & 0x7fffffu) != 0u ? 1 : 0);
+      }
+      if (!(q <= 3.0e38f)) Lv = S.levels - 1;      // infinite or NaN footprint
+      Lv = min(Lv, S.levels - 1);
+    }
+    mip = Lv;
+    float det = J00 * J11 - J01 * J10;
+    float A = 0.0f, B = 0.0f;
+    if (fabsf(det) >= 1e-20f) {
+      float idet = __fdividef(1.0f, det);
+      int nL = S.n0 >> Lv;
+      float fn = (float)nL;  // power of two: 2 / fn below is exact
+      // clamp before the integer conversion (equal to floor-then-clamp for in-range values)
+      const float top = fn - 1.0f;
+      int x0 = (int)clampf(0.5f * (U - hu + 1.0f) * fn, 0.0f, top);
+      int x1 = (int)clampf(0.5f * (U + hu + 1.0f) * fn, 0.0f, top);
+      int y0 = (int)clampf(0.5f * (V - hv + 1.0f) * fn, 0.0f, top);
+      int y1 = (int)clampf(0.5f * (V + hv + 1.0f) * fn, 0.0f, top);
+      x1 = min(x1, x0 + 8);
+      y1 = min(y1, y0 + 8);
+      float iscale = S.scale[Lv];
+      uint32_t base = S.level_off[Lv] + (uint32_t)face * (uint32_t)nL * (uint32_t)nL;
+      const int wpr = ((nL + 31) >> 5) + 1;
+      const uint32_t* occ = S.occ + S.occ_off[Lv] + (uint32_t)face * (uint32_t)nL * (uint32_t)wpr;
+      const int w0 = x0 >> 5, sh = x0 & 31;
+      const uint32_t span = (1u << (x1 - x0 + 1)) - 1u;  // x1 - x0 <= 8
+      float tw = __fdividef(2.0f, fn);
+      for (int ty = y0; ty <= y1; ++ty) {
+        const uint32_t* orow = occ + (uint32_t)ty * (uint32_t)wpr + (uint32_t)w0;
+        uint64_t two = (uint64_t)orow[0] | ((uint64_t)orow[1] << 32);
+        uint32_t bits = (uint32_t)(two >> sh) & span;
+        uint32_t row = base + (uint32_t)ty * (uint32_t)nL;
+        float sv0 = (float)ty * tw - 1.0f - V;
+        while (bits) {
+          int tx = x0 + __builtin_ctz(bits);
+          bits &= bits - 1u;
+          if (COUNT) {
+            uint32_t id = row + (uint32_t)tx;
+            atomicOr(&touched[id >> 5], 1u << (id & 31));
+          }
+          float4 tex = load_texel(S, row + (uint32_t)tx);
+          float I = tex.x * iscale;
+          float du = ((float)tx + tex.z) * tw - 1.0f - U;
+          float dv = sv0 + tex.w * tw;
+          float w = (J11 * du - J01 * dv) * idet;
+          float h = (J00 * dv - J10 * du) * idet;
+          float wt = fmaxf(1.0f - fabsf(w), 0.0f) * fmaxf(1.0f - fabsf(h), 0.0f);
+          A += wt * I;
+          B += wt * I * tex.y;
+        }
+      }
+    }
+    float cqx = qw1 * qh2 - qw2 * qh1, cqy = qw2 * qh0 - qw0 * qh2, cqz = qw0 * qh1 - qw1 * qh0;
+    float cdx = dw1 * dh2 - dw2 * dh1, cdy = dw2 * dh0 - dw0 * dh2, cdz = dw0 * dh1 - dw1 * dh0;
+    float om = sqrtf(cqx * cqx + cqy * cqy + cqz * cqz);
+    float omp = sqrtf(cdx * cdx + cdy * cdy + cdz * cdz);
+    if (A > 0.0f && omp > 0.0f) {
+      float Tpix = __fdividef(B, A);
+      float4 Lr = band_lookup(L, dcam * Tpix);
+      float4 Ln = band_lookup(L, Tpix);
+      float sc = trans * v.k_star * __fdividef(om, omp) * __fdividef(A, Ln.w);
+      cr += sc * Lr.x;
+      cg += sc * Lr.y;
+      cb += sc * Lr.z;
+    }
+  }
+
+  if (px < v.width && py < v.height) {
+    size_t idx = (size_t)py * v.width + px;
+    v.out[idx] = make_float4(cr, cg, cb, 1.0f);
+    if (v.aov) {
+      bits |= (unsigned)mip << 8;
+      v.aov[idx] = make_float4(captured ? __builtin_inff() : tr.dprime, tr.ucr[0], tr.ucr[1],
+                               __uint_as_float(bits));
+    }
+  }
+}
+
+template <int TW, int TH, int PPT>
+struct TileCfg {
+  static constexpr int kBX = TW / 8, kBY = TH / 8;           // 8x8 blocks per tile
+  static constexpr int kWaves = kBX * kBY / PPT;
+  static constexpr int kThreads = 64 * kWaves;
+  static_assert(kBX * kBY % PPT == 0, "blocks must divide by pixels per thread");
+};
+
+template <int TW, int TH, int PPT, bool COUNT = false>
+__device__ __forceinline__ void render_tile(const ViewDev& v, const TablesDev& T, const LutDev& L,
+                                            int tx0, int ty0, uint32_t* touched = nullptr) {
+  using C = TileCfg<TW, TH, PPT>;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int q = lane >> 2;
+  const int ox = 2 * (q & 3) + (lane & 1), oy = 2 * (q >> 2) + ((lane >> 1) & 1);
+#pragma unroll 1
+  for (int p = 0; p < PPT; ++p) {
+    int blk = p * C::kWaves + wave;
+    int bx = blk % C::kBX, by = blk / C::kBX;
+    int px = tx0 + 8 * bx + ox, py = ty0 + 8 * by + oy;
+    // skip 8x8 blocks entirely outside the image (uniform per wave)
+    if (tx0 + 8 * bx >= v.width || ty0 + 8 * by >= v.height) continue;
+    render_pixel<COUNT>(v, T, L, px, py, touched);
+  }
+}
+
+// One launch per view: blocks map to tiles in an XCD-aware order (consecutive tile rows go
+// to the same XCD, whose L2 then holds the cube-map region they share).
+template <int TW, int TH, int PPT>
+__global__ void __launch_bounds__((TW / 8) * (TH / 8) * 64 / PPT)
+    k_render(ViewDev v, TablesDev T, LutDev L, int tiles_x, int ntiles, int per_xcd) {
+  int b = blockIdx.x;
+  int tile = (b & 7) * per_xcd + (b >> 3);
+  if (tile >= ntiles) return;
+  render_tile<TW, TH, PPT>(v, T, L, (tile % tiles_x) * TW, (tile / tiles_x) * TH);
+}
+
+// Persistent launch over a work list of (view, tile) items from many views.
+template <int TW, int TH, int PPT>
+__global__ void __launch_bounds__((TW / 8) * (TH / 8) * 64 / PPT)
+    k_render_batch(const ViewDev* __restrict__ views, const WorkItem* __restrict__ items,
+                   int nitems, int* __restrict__ counter, TablesDev T, LutDev L) {
+  __shared__ int s_item;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+    __syncthreads();
+    int it = __builtin_amdgcn_readfirstlane(s_item);
+    __syncthreads();
+    if (it >= nitems) break;
+    WorkItem w = items[it];
+    int vi = __builtin_amdgcn_readfirstlane(w.view);
+    int x0 = __builtin_amdgcn_readfirstlane(w.x0), y0 = __builtin_amdgcn_readfirstlane(w.y0);
+    ViewDev v = views[vi];
+    render_tile<TW, TH, PPT>(v, T, L, x0, y0);
+  }
+}
+
+// Work list without persistence: one workgroup per (view, tile) item, XCD-aware order.
+template <int TW, int TH, int PPT>
+__global__ void __launch_bounds__((TW / 8) * (TH / 8) * 64 / PPT)
+    k_render_list(const ViewDev* __restrict__ views, const WorkItem* __restrict__ items,
+                  int nitems, int per_xcd, TablesDev T, LutDev L) {
+  int b = blockIdx.x;
+  int it = (b & 7) * per_xcd + (b >> 3);
+  if (it >= nitems) return;
+  WorkItem w = items[it];
+  int vi = __builtin_amdgcn_readfirstlane(w.view);
+  int x0 = __builtin_amdgcn_readfirstlane(w.x0), y0 = __builtin_amdgcn_readfirstlane(w.y0);
+  ViewDev v = views[vi];
+  render_tile<TW, TH, PPT>(v, T, L, x0, y0);
+}
+
+__global__ void k_reset_counter(int* c) { *c = 0; }
+
+// Measurement variant of the plain launch (16x16 tiles): marks the star-map texels that
+// the footprints visit.
+__global__ void __launch_bounds__(256)
+    k_render_count(ViewDev v, TablesDev T, LutDev L, int tiles_x, int ntiles,
+                   uint32_t* __restrict__ touched) {
+  int tile = blockIdx.x;
+  if (tile >= ntiles) return;
+  render_tile<16, 16, 1, true>(v, T, L, (tile % tiles_x) * 16, (tile / tiles_x) * 16, touched);
+}
+
+__global__ void k_popcount(const uint32_t* __restrict__ bits, int64_t n,
+                           unsigned long long* __restrict__ total) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  unsigned c = i < n ? __popc(bits[i]) : 0u;
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+  if ((threadIdx.x & 63) == 0 && c) atomicAdd(total, (unsigned long long)c);
+}
+
+// TraceRay alone, for unit tests: rays = [u, delta, alpha, u_ic, u_oc]
+__global__ void k_trace_rays(TablesDev T, const float* __restrict__ rays, int64_t n,
+                             float4* __restrict__ out) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float* r = rays + 5 * i;
+  float u = r[0], delta = r[1];
+  float sd, cd;
+  sincosf(delta, &sd, &cd);
+  TraceOut t = trace_ray(T, u, delta, r[2], cd / sd, r[3], r[4]);
+  bool cap = (t.bits & BH_CAPTURED_BIT) != 0;
+  out[i] = make_float4(cap ? __builtin_inff() : t.dprime, t.ucr[0], t.ucr[1],
+                       __uint_as_float(t.bits));
+}
+
+// ---- host-side launchers ------------------------------------------------------------------
+
+struct TileEntry {
+  int tw, th, waves, ppt;
+  void (*plain)(const ViewDev&, const TablesDev&, const LutDev&, hipStream_t);
+  void (*batch)(const ViewDev*, const WorkItem*, int, int*, const TablesDev&, const LutDev&,
+                int grid, hipStream_t);
+  void (*list)(const ViewDev*, const WorkItem*, int, const TablesDev&, const LutDev&,
+               hipStream_t);
+};
+
+template <int TW, int TH, int PPT>
+static void launch_plain(const ViewDev& v, const TablesDev& T, const LutDev& L, hipStream_t s) {
+  using C = TileCfg<TW, TH, PPT>;
+  int tiles_x = (v.width + TW - 1) / TW, tiles_y = (v.height + TH - 1) / TH;
+  int ntiles = tiles_x * tiles_y;
+  int per_xcd = (ntiles + 7) / 8;
+  hipLaunchKernelGGL((k_render<TW, TH, PPT>), dim3(8 * per_xcd), dim3(C::kThreads), 0, s, v, T,
+                     L, tiles_x, ntiles, per_xcd);
+}
+
+template <int TW, int TH, int PPT>
+static void launch_batch(const ViewDev* views, const WorkItem* items, int nitems, int* counter,
+                         const TablesDev& T, const LutDev& L, int grid, hipStream_t s) {
+  using C = TileCfg<TW, TH, PPT>;
+  hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, counter);
+  hipLaunchKernelGGL((k_render_batch<TW, TH, PPT>), dim3(grid), dim3(C::kThreads), 0, s, views,
+                     items, nitems, counter, T, L);
+}
+
+template <int TW, int TH, int PPT>
+static void launch_list(const ViewDev* views, const WorkItem* items, int nitems,
+                        const TablesDev& T, const LutDev& L, hipStream_t s) {
+  using C = TileCfg<TW, TH, PPT>;
+  int per_xcd = (nitems + 7) / 8;
+  hipLaunchKernelGGL((k_render_list<TW, TH, PPT>), dim3(8 * per_xcd), dim3(C::kThreads), 0, s,
+                     views, items, nitems, per_xcd, T, L);
+}
+
+#define BH_TILE(TW, TH, PPT)                                                         \
+  {TW, TH, TileCfg<TW, TH, PPT>::kWaves, PPT, launch_plain<TW, TH, PPT>,             \
+   launch_batch<TW, TH, PPT>, launch_list<TW, TH, PPT>}
+
+static const TileEntry kTiles[] = {
+    BH_TILE(16, 16, 1), BH_TILE(32, 8, 1), BH_TILE(16, 8, 1), BH_TILE(8, 8, 1),
+    BH_TILE(32, 16, 2), BH_TILE(16, 16, 2), BH_TILE(32, 32, 4), BH_TILE(64, 16, 4),
+};
+
+int tile_config_count() { return (int)(sizeof(kTiles) / sizeof(kTiles[0])); }
+void tile_config(int i, int* tw, int* th, int* waves, int* ppt) {
+  *tw = kTiles[i].tw;
+  *th = kTiles[i].th;
+  *waves = kTiles[i].waves;
+  *ppt = kTiles[i].ppt;
+}
+
+hipError_t launch_render(int cfg, const ViewDev& v, const TablesDev& T, const LutDev& L,
+                         hipStream_t s) {
+  kTiles[cfg].plain(v, T, L, s);
+  return hipGetLastError();
+}
+
+// persistent != 0: grid-stride persistent workgroups pulling items from an atomic counter;
+// otherwise one workgroup per item.
+hipError_t launch_render_batch(int cfg, int persistent, const ViewDev* views,
+                               const WorkItem* items, int nitems, int* counter,
+                               const TablesDev& T, const LutDev& L, int grid, hipStream_t s) {
+  if (persistent)
+    kTiles[cfg].batch(views, items, nitems, counter, T, L, grid, s);
+  else
+    kTiles[cfg].list(views, items, nitems, T, L, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_render_count(const ViewDev& v, const TablesDev& T, const LutDev& L,
+                               uint32_t* touched, int64_t words, unsigned long long* total,
+                               hipStream_t s) {
+  int tiles_x = (v.width + 15) / 16, ntiles = tiles_x * ((v.height + 15) / 16);
+  hipLaunchKernelGGL(k_render_count, dim3(ntiles), dim3(256), 0, s, v, T, L, tiles_x, ntiles,
+                     touched);
+  hipLaunchKernelGGL(k_popcount, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, s, touched,
+                     words, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_trace_rays(const TablesDev& T, const float* rays, int64_t n, float4* out,
+                             hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_trace_rays, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, T, rays,
+                     n, out);
+  return hipGetLastError();
+}
+
+}  // namespace bh

@@ -1,0 +1,242 @@
+// Star cube map (Section 3.3.2 "Emitted light").  Each texel of every mip level holds the
+// intensity sum of the stars inside it, their intensity-weighted mean temperature and
+// their intensity-weighted mean position inside the texel; mips combine the four children
+// with the same rule (sum of intensities, intensity-weighted averages).  Stars that land in
+// the same level-0 texel are merged by the same rule, in star-index order, so the build is
+// deterministic whatever order the atomics run in.
+// Face of a direction d: k = argmax |d_k| (ties to the lowest index), face 2k + (d_k < 0),
+// U = d_{(k+1)%3} / |d_k|, V = d_{(k+2)%3} / |d_k| in [-1, 1].
+// Stored texels: FP16 (I / scale_L, T / 1024, p_u, p_v) with a per-level power-of-two
+// scale chosen from the level's largest intensity, or FP32 (I, T, p_u, p_v).
+#include "bh_dev.h"
+
+namespace bh {
+
+struct __align__(8) Half4 {
+  _Float16 x, y, z, w;
+};
+
+__global__ void k_star_link(const float* __restrict__ dirs, const float* __restrict__ inten,
+                            int64_t n, int n0, int* __restrict__ head, int* __restrict__ next,
+                            float2* __restrict__ pos) {
+  int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  float d0 = dirs[3 * s], d1 = dirs[3 * s + 1], d2 = dirs[3 * s + 2];
+  float I = inten[s];
+  float a0 = fabsf(d0), a1 = fabsf(d1), a2 = fabsf(d2);
+  int k = 0;
+  float m = a0;
+  if (a1 > m) { k = 1; m = a1; }
+  if (a2 > m) { k = 2; m = a2; }
+  if (!(I > 0.0f) || !(m > 0.0f)) {
+    next[s] = -2;
+    return;
+  }
+  float dk = k == 0 ? d0 : (k == 1 ? d1 : d2);
+  float da = k == 0 ? d1 : (k == 1 ? d2 : d0);
+  float db = k == 0 ? d2 : (k == 1 ? d0 : d1);
+  int face = 2 * k + (dk < 0.0f);
+  float U = da / m, V = db / m;
+  float gx = 0.5f * (U + 1.0f) * (float)n0, gy = 0.5f * (V + 1.0f) * (float)n0;
+  int ix = min(max((int)floorf(gx), 0), n0 - 1);
+  int iy = min(max((int)floorf(gy), 0), n0 - 1);
+  pos[s] = make_float2(gx - (float)ix, gy - (float)iy);
+  int key = (face * n0 + iy) * n0 + ix;
+  next[s] = atomicExch(&head[key], (int)s);
+}
+
+// level 0: merge the stars of each texel in increasing star index
+__global__ void k_star_reduce0(const int* __restrict__ head, const int* __restrict__ next,
+                               const float* __restrict__ inten, const float* __restrict__ temp,
+                               const float2* __restrict__ pos, int64_t ntex,
+                               float4* __restrict__ master) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= ntex) return;
+  int h = head[t];
+  double sI = 0, sIT = 0, sIu = 0, sIv = 0;
+  int last = -1;
+  while (h >= 0) {
+    int best = 0x7fffffff;
+    for (int c = h; c >= 0; c = next[c])
+      if (c > last && c < best) best = c;
+    if (best == 0x7fffffff) break;
+    double I = inten[best];
+    float2 p = pos[best];
+    sI += I;
+    sIT += I * (double)temp[best];
+    sIu += I * (double)p.x;
+    sIv += I * (double)p.y;
+    last = best;
+  }
+  master[t] = sI > 0.0 ? make_float4((float)sI, (float)(sIT / sI), (float)(sIu / sI),
+                                     (float)(sIv / sI))
+                       : make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+// parent texel from children (0,0), (1,0), (0,1), (1,1)
+__global__ void k_star_mip(const float4* __restrict__ prev, float4* __restrict__ cur, int nc) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t total = 6LL * nc * nc;
+  if (t >= total) return;
+  int x = (int)(t % nc), y = (int)((t / nc) % nc), f = (int)(t / ((int64_t)nc * nc));
+  int np = 2 * nc;
+  double sI = 0, sIT = 0, sIu = 0, sIv = 0;
+  for (int c = 0; c < 4; ++c) {
+    int cx = 2 * x + (c & 1), cy = 2 * y + (c >> 1);
+    float4 ch = prev[((int64_t)f * np + cy) * np + cx];
+    if (!(ch.x > 0.0f)) continue;
+    double I = ch.x;
+    sI += I;
+    sIT += I * ch.y;
+    sIu += I * 0.5 * ((c & 1) + (double)ch.z);
+    sIv += I * 0.5 * ((c >> 1) + (double)ch.w);
+  }
+  cur[t] = sI > 0.0 ? make_float4((float)sI, (float)(sIT / sI), (float)(sIu / sI),
+                                  (float)(sIv / sI))
+                    : make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+__global__ void k_star_maxI(const float4* __restrict__ lvl, int64_t count,
+                            unsigned* __restrict__ maxbits) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  float v = t < count ? lvl[t].x : 0.0f;
+  // wave reduction then one atomic per wave (I >= 0, so float order == bit order)
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  if ((threadIdx.x & 63) == 0 && v > 0.0f) atomicMax(maxbits, __float_as_uint(v));
+}
+
+__global__ void k_star_pack(const float4* __restrict__ lvl, int64_t count,
+                            const float* __restrict__ scale, int level, int fp16,
+                            void* __restrict__ out) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  float4 m = lvl[t];
+  if (fp16) {
+    float inv = 1.0f / scale[level];
+    Half4 h;
+    h.x = (_Float16)(m.x * inv);
+    h.y = (_Float16)(m.y * (1.0f / 1024.0f));
+    h.z = (_Float16)m.z;
+    h.w = (_Float16)m.w;
+    ((Half4*)out)[t] = h;
+  } else {
+    ((float4*)out)[t] = m;
+  }
+}
+
+__global__ void k_star_unpack(const void* __restrict__ in, int64_t count, float scale, int fp16,
+                              float4* __restrict__ out) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  if (fp16) {
+    Half4 h = ((const Half4*)in)[t];
+    out[t] = make_float4((float)h.x * scale, (float)h.y * 1024.0f, (float)h.z, (float)h.w);
+  } else {
+    out[t] = ((const float4*)in)[t];
+  }
+}
+
+// per-level scale: power of two so that the largest intensity maps to about 2^14
+__global__ void k_star_scales(const unsigned* __restrict__ maxbits, int levels, int fp16,
+                              float* __restrict__ scale) {
+  int l = threadIdx.x;
+  if (l >= levels) return;
+  if (!fp16) {
+    scale[l] = 1.0f;
+    return;
+  }
+  float mx = __uint_as_float(maxbits[l]);
+  scale[l] = mx > 0.0f ? exp2f(ceilf(log2f(mx)) - 14.0f) : 1.0f;
+}
+
+// Occupancy bits of one level: one bit per texel (stored intensity > 0), each texel row
+// padded to whole 32-bit words plus one guard word, so a footprint row of at most 9
+// texels is read with two consecutive word loads that never leave the row's storage.
+__global__ void k_star_occupancy(const void* __restrict__ tex, int nl, int fp16,
+                                 uint32_t* __restrict__ occ) {
+  const int wpr = ((nl + 31) >> 5) + 1;
+  int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t total = 6LL * nl * wpr;
+  if (w >= total) return;
+  int wi = (int)(w % wpr);
+  int64_t row = w / wpr;  // face * nl + y
+  uint32_t bits = 0;
+  for (int b = 0; b < 32; ++b) {
+    int x = wi * 32 + b;
+    if (x >= nl) break;
+    int64_t t = row * nl + x;
+    float I = fp16 ? (float)((const Half4*)tex)[t].x : ((const float4*)tex)[t].x;
+    if (I > 0.0f) bits |= 1u << b;
+  }
+  occ[w] = bits;
+}
+
+static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+hipError_t launch_star_occupancy(const void* tex, int n0, int levels, const uint32_t* level_off,
+                                 const uint32_t* occ_off, int fp16, uint32_t* occ,
+                                 hipStream_t s) {
+  size_t tsz = fp16 ? 8 : 16;
+  for (int l = 0; l < levels; ++l) {
+    int nl = n0 >> l;
+    int64_t words = 6LL * nl * (((nl + 31) >> 5) + 1);
+    hipLaunchKernelGGL(k_star_occupancy, dim3(blocks_for(words, 256)), dim3(256), 0, s,
+                       (const void*)((const char*)tex + tsz * level_off[l]), nl, fp16,
+                       occ + occ_off[l]);
+  }
+  return hipGetLastError();
+}
+
+// Build every level.  Scratch: head (6 n0^2 ints, pre-filled with -1), next (n ints),
+// pos (n float2), master (all levels, float4), maxbits (levels uints, zeroed).
+hipError_t launch_star_build(const float* dirs, const float* inten, const float* temp, int64_t n,
+                             int n0, int levels, const uint32_t* level_off_host, int* head,
+                             int* next, float2* pos, float4* master, unsigned* maxbits,
+                             float* scale, int fp16, void* out, hipStream_t s) {
+  const int B = 256;
+  int64_t ntex0 = 6LL * n0 * n0;
+  if (n > 0)
+    hipLaunchKernelGGL(k_star_link, dim3(blocks_for(n, B)), dim3(B), 0, s, dirs, inten, n, n0,
+                       head, next, pos);
+  hipLaunchKernelGGL(k_star_reduce0, dim3(blocks_for(ntex0, B)), dim3(B), 0, s, head, next,
+                     inten, temp, pos, ntex0, master);
+  for (int l = 1; l < levels; ++l) {
+    int nc = n0 >> l;
+    hipLaunchKernelGGL(k_star_mip, dim3(blocks_for(6LL * nc * nc, B)), dim3(B), 0, s,
+                       master + level_off_host[l - 1], master + level_off_host[l], nc);
+  }
+  for (int l = 0; l < levels; ++l) {
+    int64_t cnt = 6LL * (n0 >> l) * (n0 >> l);
+    hipLaunchKernelGGL(k_star_maxI, dim3(blocks_for(cnt, B)), dim3(B), 0, s,
+                       master + level_off_host[l], cnt, maxbits + l);
+  }
+  hipLaunchKernelGGL(k_star_scales, dim3(1), dim3(64), 0, s, maxbits, levels, fp16, scale);
+  size_t tsz = fp16 ? 8 : 16;
+  for (int l = 0; l < levels; ++l) {
+    int64_t cnt = 6LL * (n0 >> l) * (n0 >> l);
+    hipLaunchKernelGGL(k_star_pack, dim3(blocks_for(cnt, B)), dim3(B), 0, s,
+                       master + level_off_host[l], cnt, scale, l, fp16,
+                       (void*)((char*)out + tsz * level_off_host[l]));
+  }
+  return hipGetLastError();
+}
+
+__global__ void k_fill_int(int* p, int64_t n, int v) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < n) p[t] = v;
+}
+
+hipError_t launch_fill_int(int* p, int64_t n, int v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_int, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_star_unpack(const void* in, int64_t count, float scale, int fp16, float4* out,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_star_unpack, dim3(blocks_for(count, 256)), dim3(256), 0, s, in, count,
+                     scale, fp16, out);
+  return hipGetLastError();
+}
+
+}  // namespace bh

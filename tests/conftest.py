@@ -18,3 +18,47 @@ def orc():
     import oracle
     oracle.lib()
     return oracle
+
+
+# ---- GPU fixtures ----------------------------------------------------------------------
+
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.fixture(scope="session")
+def gpu_ctx():
+    _need_gpu()
+    import torch
+    from paper_2010_08735_amd import bh
+    torch.cuda.init()
+    ctx = bh.bh_create(0, 0)
+    yield ctx
+    torch.cuda.synchronize()
+    bh.bh_destroy(ctx)
+
+
+@pytest.fixture(scope="session")
+def gpu_tables(gpu_ctx):
+    from paper_2010_08735_amd import bh
+    t = bh.bh_precompute_tables(gpu_ctx, 512, 64, 32, bh.BH_TAB_FP64_BAND, 0.05)
+    return t
+
+
+@pytest.fixture(scope="session")
+def orc_tables(orc):
+    return orc.Tables(512, 64, 32)
+
+
+def gpu_star_map(ctx, field, n0, fmt=0, key=0):
+    import torch
+    from paper_2010_08735_amd import bh
+    d = torch.from_numpy(field.dirs).cuda()
+    i = torch.from_numpy(field.intensity).cuda()
+    t = torch.from_numpy(field.temperature).cuda()
+    h = bh.bh_build_stars(ctx, d.data_ptr(), i.data_ptr(), t.data_ptr(), len(field), n0, fmt,
+                          key, bh.current_stream())
+    torch.cuda.synchronize()
+    return h
