@@ -70,6 +70,69 @@ __device__ __forceinline__ float clampf(float x, float lo, float hi) {
   return fminf(fmaxf(x, lo), hi);
 }
 
+// ---- short math for the render path ----------------------------------------------------
+// Hardware square root and reciprocal (about 1 ulp each), for values whose rounding is not
+// amplified afterwards.
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float fdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+
+// log(1 + x), x > -1: with u = fl(1 + x), log(u) * x / (u - 1) cancels the rounding of u.
+__device__ __forceinline__ float flog1p(float x) {
+  float u = 1.0f + x;
+  float d = u - 1.0f;
+  if (d == 0.0f) return x;
+  return __builtin_amdgcn_logf(u) * 0.693147180559945309f * fdiv(x, d);
+}
+
+// sin on |x| <= pi/6: Taylor series through x^11 (remainder below 2e-11).
+__device__ __forceinline__ float fsin_small(float x) {
+  float s = x * x;
+  return x * (1.0f + s * (-1.0f / 6.0f + s * (1.0f / 120.0f + s * (-1.0f / 5040.0f +
+              s * (1.0f / 362880.0f + s * (-1.0f / 39916800.0f))))));
+}
+
+// sin and cos for |x| up to a few hundred: x = k pi/2 + r with k = rint(2x/pi) and pi/2 split
+// as 1.5703125 (exact in FP32) + 4.8382679e-4, then Taylor polynomials on |r| <= pi/4
+// (truncation below 2e-9) and the quadrant of k.
+__device__ __forceinline__ void fsincos(float x, float* sn, float* cs) {
+  float k = rintf(x * 0.636619772367581343f);
+  float r = fmaf(-k, 1.5703125f, x);
+  r = fmaf(-k, 4.83826794896619e-4f, r);
+  float r2 = r * r;
+  float s = r * (1.0f + r2 * (-1.0f / 6.0f + r2 * (1.0f / 120.0f + r2 * (-1.0f / 5040.0f +
+                 r2 * (1.0f / 362880.0f)))));
+  float c = 1.0f + r2 * (-0.5f + r2 * (1.0f / 24.0f + r2 * (-1.0f / 720.0f +
+                 r2 * (1.0f / 40320.0f + r2 * (-1.0f / 3628800.0f)))));
+  int q = (int)k & 3;  // sin(q pi/2 + r), cos(q pi/2 + r)
+  float ss = (q & 1) ? c : s;
+  float cc = (q & 1) ? s : c;
+  *sn = (q & 2) ? -ss : ss;
+  *cs = ((q + 1) & 2) ? -cc : cc;
+}
+
+// atan2(y, x) for y >= 0 (the render path's angles lie in [0, pi]): t = min/max of |x|, |y|
+// in [0, 1], atan(t) = t P(t^2) with a degree-8 P fitted by weighted least squares at
+// Chebyshev nodes (max error 1.2e-7 rad in FP32), then the octant.
+__device__ __forceinline__ float fatan2_pos(float y, float x) {
+  float ax = fabsf(x), ay = fabsf(y);
+  float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
+  float t = mx > 0.0f ? fdiv(mn, mx) : 0.0f;
+  float s = t * t;
+  float p = 0.0024567029904574156f;
+  p = fmaf(p, s, -0.014401259832084179f);
+  p = fmaf(p, s, 0.03978103771805763f);
+  p = fmaf(p, s, -0.07234838604927063f);
+  p = fmaf(p, s, 0.10498934984207153f);
+  p = fmaf(p, s, -0.141612246632576f);
+  p = fmaf(p, s, 0.19985905289649963f);
+  p = fmaf(p, s, -0.33332598209381104f);
+  p = fmaf(p, s, 0.9999998807907104f);
+  float r = p * t;
+  if (ay > ax) r = 1.57079632679489662f - r;
+  if (x < 0.0f) r = 3.14159265358979324f - r;
+  return r;
+}
+
 // bilinear fetch of a row-major table with texel k of n at unit coordinate k/(n-1),
 // columns clamped to [lo, hi] (so the two halves of D are never mixed)
 __device__ __forceinline__ float bilinear(const float* __restrict__ t, int nx, int ny, int lo,
@@ -89,7 +152,7 @@ __device__ __forceinline__ float bilinear(const float* __restrict__ t, int nx, i
 // apsis of a ray with e^2 < mu (Section 3.3.1, eq. uapsis)
 __device__ __forceinline__ float apsis_f(float e2) {
   float a = clampf(e2 * (2.0f / kMu) - 1.0f, -1.0f, 1.0f);
-  return 1.0f / 3.0f + 2.0f / 3.0f * sinf(asinf(a) * (1.0f / 3.0f));
+  return 1.0f / 3.0f + 2.0f / 3.0f * fsin_small(asinf(a) * (1.0f / 3.0f));
 }
 
 // D(e, u) through the Appendix A mapping.  udot = du/dphi at (e, u) on the ray.  For
@@ -101,24 +164,24 @@ __device__ __forceinline__ float lookup_D(const TablesDev& T, float e2, float u,
                                           float udot) {
   const int n = T.d_n;
   if (e2 < kMu) {
-    float x = 0.5f - sqrtf(-log1pf(-e2 * (1.0f / kMu)) * (1.0f / 50.0f));
+    float x = 0.5f - fsqrt(-flog1p(-e2 * (1.0f / kMu)) * (1.0f / 50.0f));
     float den = e2 + u * ua * (1.0f - ua - u);
-    float s2 = den > 0.0f ? fminf(__fdividef(udot * udot, den), 1.0f) : 0.0f;
-    float y = 1.0f - sqrtf(s2);
+    float s2 = den > 0.0f ? fminf(fdiv(udot * udot, den), 1.0f) : 0.0f;
+    float y = 1.0f - fsqrt(s2);
     return bilinear(T.D, n, n, 0, n / 2 - 1, x, y);
   }
-  float x = 0.5f + sqrtf(-log1pf(-kMu / e2) * (1.0f / 50.0f));
+  float x = 0.5f + fsqrt(-flog1p(-kMu / e2) * (1.0f / 50.0f));
   float dz = u - 2.0f / 3.0f;
   const float s23 = 0.816496580927726f, s13 = 0.577350269189626f;
-  float y = (s23 + copysignf(sqrtf(fabsf(dz)), dz)) * (1.0f / (s23 + s13));
+  float y = (s23 + copysignf(fsqrt(fabsf(dz)), dz)) * (1.0f / (s23 + s13));
   return bilinear(T.D, n, n, n / 2, n - 1, x, y);
 }
 
 // U(e, phi) through the Appendix A mapping
 __device__ __forceinline__ float lookup_U(const TablesDev& T, float e2, float e, float phi) {
-  float x = __fdividef(1.0f, 1.0f + 6.0f * e2);
+  float x = fdiv(1.0f, 1.0f + 6.0f * e2);
   // (1 + 6 e^3) / (1 + e^2) written so that it cannot overflow for nearly radial rays
-  float y = phi * (1.0f / 3.0f) * (6.0f * e + __fdividef(1.0f - 6.0f * e, 1.0f + e2));
+  float y = phi * (1.0f / 3.0f) * (6.0f * e + fdiv(1.0f - 6.0f * e, 1.0f + e2));
   return bilinear(T.U, T.u_ne, T.u_nphi, 0, T.u_ne - 1, x, y);
 }
 

@@ -65,7 +65,7 @@ __device__ __forceinline__ TraceOut trace_ray(const TablesDev& T, float u, float
     Da = lookup_D(T, e2, ua, ua, 0.0f);
     phia = Da + 0.5f * kPi;
   }
-  float e = sqrtf(e2);
+  float e = fsqrt(e2);
   float phi = Dl + (s == 1 ? kPi - delta : delta) + (float)s * alpha;
   float phi0 = phi - kPi * floorf(phi * (1.0f / kPi));
   float u0 = lookup_U(T, e2, e, phi0);
@@ -132,7 +132,7 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
   float nv = nc0 * v.vhat[0] + nc1 * v.vhat[1] + nc2 * v.vhat[2];
   float ka = (v.gamma - 1.0f) * nv - v.gamma * v.vmag;
   float ns0 = nc0 + ka * v.vhat[0], ns1 = nc1 + ka * v.vhat[1], ns2 = nc2 + ka * v.vhat[2];
-  float dcam = __fdividef(v.inv_sq1mu, v.gamma * (1.0f - v.vmag * nv));
+  float dcam = fdiv(v.inv_sq1mu, v.gamma * (1.0f - v.vmag * nv));
   float nr = ns0 * v.rhat[0] + ns1 * v.rhat[1] + ns2 * v.rhat[2];
   float kr = (v.sq1mu - 1.0f) * nr;
   float d0 = ns0 + kr * v.rhat[0], d1 = ns1 + kr * v.rhat[1], d2 = ns2 + kr * v.rhat[2];
@@ -141,7 +141,7 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
   float cz2 = v.rhat[0] * d1 - v.rhat[1] * d0;
   float ncz = sqrtf(cz0 * cz0 + cz1 * cz1 + cz2 * cz2);
   float dr = d0 * v.rhat[0] + d1 * v.rhat[1] + d2 * v.rhat[2];
-  float dn = sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
+  float dn = fsqrt(d0 * d0 + d1 * d1 + d2 * d2);
   unsigned bits = 0;
   float u_ic = v.u_ic, u_oc = v.u_oc;
   if (!(ncz > 1e-7f * dn)) {
@@ -151,35 +151,35 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
     cz0 = v.rhat[1] * 0.0f - v.rhat[2] * ax1;
     cz1 = v.rhat[2] * ax0 - v.rhat[0] * 0.0f;
     cz2 = v.rhat[0] * ax1 - v.rhat[1] * ax0;
-    float n2 = __fdividef(1.0f, sqrtf(cz0 * cz0 + cz1 * cz1 + cz2 * cz2));
+    float n2 = fdiv(1.0f, sqrtf(cz0 * cz0 + cz1 * cz1 + cz2 * cz2));
     cz0 *= n2; cz1 *= n2; cz2 *= n2;
     ncz = fmaxf(ncz, 1e-7f * dn);
     u_ic = -1.0f;
   } else {
-    float inv = __fdividef(1.0f, ncz);
+    float inv = fdiv(1.0f, ncz);
     cz0 *= inv; cz1 *= inv; cz2 *= inv;
   }
-  float delta = atan2f(ncz, dr);
+  float delta = fatan2_pos(ncz, dr);
   // e_y' = e_z' x e_x'
   float ey0 = cz1 * v.rhat[2] - cz2 * v.rhat[1];
   float ey1 = cz2 * v.rhat[0] - cz0 * v.rhat[2];
   float ey2 = cz0 * v.rhat[1] - cz1 * v.rhat[0];
   // t = +-(e_z x e_z') with t.e_y' >= 0; alpha = angle(e_x', t)
   float t0 = -cz1, t1 = cz0;
-  float nt = sqrtf(t0 * t0 + t1 * t1);
+  float nt = fsqrt(t0 * t0 + t1 * t1);
   float alpha = 0.0f;
   if (!(nt > 1e-7f)) {
     bits |= BH_DEGENERATE_BIT;
     u_ic = -1.0f;
   } else {
-    float int_ = __fdividef(1.0f, nt);
+    float int_ = fdiv(1.0f, nt);
     float tx = (t0 * v.rhat[0] + t1 * v.rhat[1]) * int_;
     float ty = (t0 * ey0 + t1 * ey1) * int_;
     if (ty < 0.0f) {
       tx = -tx;
       ty = -ty;
     }
-    alpha = atan2f(ty, tx);
+    alpha = fatan2_pos(ty, tx);
   }
   float zeta = cz2;
 
@@ -192,15 +192,15 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
   float cr = 0.0f, cg = 0.0f, cb = 0.0f, trans = 1.0f;
   {
     float u = v.u_c, cotd = dr / ncz;
-    float e = sqrtf((u * cotd) * (u * cotd) + u * u * (1.0f - u));
+    float e = fsqrt((u * cotd) * (u * cotd) + u * u * (1.0f - u));
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       if (k >= tr.ncross) break;
       float uk = k == 0 ? tr.ucr[0] : tr.ucr[1];
       float Tp = disc_temperature(v, uk);
-      float kt = sqrtf(__fdividef(2.0f, 2.0f - 3.0f * uk));
-      float om = sqrtf(0.5f * uk * uk * uk);
-      float D = __fdividef(dcam, kt * (1.0f + __fdividef(om * zeta, e)));
+      float kt = fsqrt(fdiv(2.0f, 2.0f - 3.0f * uk));
+      float om = fsqrt(0.5f * uk * uk * uk);
+      float D = fdiv(dcam, kt * (1.0f + fdiv(om * zeta, e)));
       float4 Lb = band_lookup(L, D * Tp);
       float w = trans * v.rho * v.k_disc;
       cr += w * Lb.x;
@@ -212,7 +212,7 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
 
   // ---- stars (Sections 3.3.2, 3.4.1)
   float sdp, cdp;
-  sincosf(tr.dprime, &sdp, &cdp);
+  fsincos(tr.dprime, &sdp, &cdp);
   float dp0 = captured ? 0.0f : cdp * v.rhat[0] + sdp * ey0;
   float dp1 = captured ? 0.0f : cdp * v.rhat[1] + sdp * ey1;
   float dp2 = captured ? 0.0f : cdp * v.rhat[2] + sdp * ey2;
@@ -243,7 +243,7 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
     float hb = k == 0 ? dh2 : (k == 1 ? dh0 : dh1);
     int face = 2 * k + (dk < 0.0f);
     float sgk = dk < 0.0f ? -1.0f : 1.0f;
-    float im = __fdividef(1.0f, m);
+    float im = fdiv(1.0f, m);
     float U = da * im, V = db * im;
     float J00 = (wa - U * sgk * wk) * im, J01 = (ha - U * sgk * hk) * im;
     float J10 = (wb - V * sgk * wk) * im, J11 = (hb - V * sgk * hk) * im;
@@ -265,7 +265,7 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
     float det = J00 * J11 - J01 * J10;
     float A = 0.0f, B = 0.0f;
     if (fabsf(det) >= 1e-20f) {
-      float idet = __fdividef(1.0f, det);
+      float idet = fdiv(1.0f, det);
       int nL = S.n0 >> Lv;
       float fn = (float)nL;  // power of two: 2 / fn below is exact
       // clamp before the integer conversion (equal to floor-then-clamp for in-range values)
@@ -282,7 +282,7 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
       const uint32_t* occ = S.occ + S.occ_off[Lv] + (uint32_t)face * (uint32_t)nL * (uint32_t)wpr;
       const int w0 = x0 >> 5, sh = x0 & 31;
       const uint32_t span = (1u << (x1 - x0 + 1)) - 1u;  // x1 - x0 <= 8
-      float tw = __fdividef(2.0f, fn);
+      float tw = fdiv(2.0f, fn);
       for (int ty = y0; ty <= y1; ++ty) {
         const uint32_t* orow = occ + (uint32_t)ty * (uint32_t)wpr + (uint32_t)w0;
         uint64_t two = (uint64_t)orow[0] | ((uint64_t)orow[1] << 32);
@@ -310,13 +310,13 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
     }
     float cqx = qw1 * qh2 - qw2 * qh1, cqy = qw2 * qh0 - qw0 * qh2, cqz = qw0 * qh1 - qw1 * qh0;
     float cdx = dw1 * dh2 - dw2 * dh1, cdy = dw2 * dh0 - dw0 * dh2, cdz = dw0 * dh1 - dw1 * dh0;
-    float om = sqrtf(cqx * cqx + cqy * cqy + cqz * cqz);
-    float omp = sqrtf(cdx * cdx + cdy * cdy + cdz * cdz);
+    float om = fsqrt(cqx * cqx + cqy * cqy + cqz * cqz);
+    float omp = fsqrt(cdx * cdx + cdy * cdy + cdz * cdz);
     if (A > 0.0f && omp > 0.0f) {
-      float Tpix = __fdividef(B, A);
+      float Tpix = fdiv(B, A);
       float4 Lr = band_lookup(L, dcam * Tpix);
       float4 Ln = band_lookup(L, Tpix);
-      float sc = trans * v.k_star * __fdividef(om, omp) * __fdividef(A, Ln.w);
+      float sc = trans * v.k_star * fdiv(om, omp) * fdiv(A, Ln.w);
       cr += sc * Lr.x;
       cg += sc * Lr.y;
       cb += sc * Lr.z;
