@@ -23,6 +23,28 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+PROFILE = os.path.join(ROOT, "profiles", "k_render_1080p_summary.txt")
+KERNEL_SOURCES = ("paper_2010_08735_amd/csrc/render.hip", "paper_2010_08735_amd/csrc/bh_dev.h")
+
+
+def kernel_profile():
+    """Per-unit figures of the render kernel from the committed rocprofv3 summary, if they
+    were taken on the current kernel sources (else None)."""
+    import hashlib
+    if not os.path.exists(PROFILE):
+        return None
+    vals = {}
+    for line in open(PROFILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if vals.get("source_sha256") != h.hexdigest():
+        return None
+    return {k: float(v) for k, v in vals.items() if k != "source_sha256"}
 
 
 def log(*a):
@@ -200,19 +222,37 @@ def main():
     kernel_ms = float(np.mean(kms))
     log("plain: %.4f ms/frame wall, kernel %.4f ms (events), %.0f Mpx/s" % (ms_step, kernel_ms, mpx))
 
-    # roofline of the render kernel: algorithmic HBM bytes per launch
+    # roofline of the render kernel.  HBM side: algorithmic bytes per launch (image + the
+    # distinct occupied star texels the footprints read + tables), counted live.  ALU side
+    # (the bound the counters show): FP32 FLOPs per pixel from the committed rocprofv3
+    # summary times the pixels of one launch.  Both over the live event-timed kernel time.
     texels = bh.bh_footprint_texels(ctx, tables, view, out.data_ptr())
     bytes_out = 16 * W * H
     bytes_tex = 8 * texels
     bytes_tab = 4 * (512 * 512 + 64 * 32) + 16 * 4096
     alg = bytes_out + bytes_tex + bytes_tab
-    achieved = alg / (kernel_ms * 1e-3) / 1e9
-    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-            "kernel": "k_render<16,16,1>", "kernel_ms": kernel_ms,
-            "algorithmic_bytes": alg, "bytes_image": bytes_out, "bytes_star_texels": bytes_tex,
-            "star_texels_touched": texels, "bytes_tables_lut": bytes_tab}
-    log("roofline: %.1f MB algorithmic, %.1f GB/s, frac %.4f" % (alg / 1e6, achieved, achieved / HBM_PEAK_GBS))
+    hbm_gbs = alg / (kernel_ms * 1e-3) / 1e9
+    hbm = {"achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": hbm_gbs / HBM_PEAK_GBS, "algorithmic_bytes": alg, "bytes_image": bytes_out,
+           "bytes_star_texels": bytes_tex, "star_texels_touched": texels,
+           "bytes_tables_lut": bytes_tab}
+    prof = kernel_profile()
+    if prof is not None:
+        flops = prof["fp32_flops_per_pixel"] * W * H
+        tf = flops / (kernel_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": tf, "peak": FP32_VECTOR_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": tf / FP32_VECTOR_PEAK_TFLOPS,
+                "traffic": prof["fetch_bytes"] + prof["write_bytes"],
+                "kernel": "k_render<16,16,1>", "kernel_ms": kernel_ms,
+                "flops_per_pixel": prof["fp32_flops_per_pixel"],
+                "valu_busy_pct": prof["valu_busy_pct"], "hbm": hbm}
+    else:
+        roof = {"bound": "hbm", "achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": hbm_gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "k_render<16,16,1>",
+                "kernel_ms": kernel_ms, "note": "counters not taken on the current kernel",
+                "hbm": hbm}
+    log("roofline: %s %.2f %s (frac %.4f); HBM algorithmic %.1f MB, %.0f GB/s"
+        % (roof["bound"], roof["achieved"], roof["unit"], roof["frac"], alg / 1e6, hbm_gbs))
 
     extra = {}
     if "batch" in legs:
