@@ -25,7 +25,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 PROFILE = os.path.join(ROOT, "profiles", "k_render_1080p_summary.txt")
-KERNEL_SOURCES = ("paper_2010_08735_amd/csrc/render.hip", "paper_2010_08735_amd/csrc/bh_dev.h")
+KERNEL_SOURCES = ("paper_2010_08735_amd/csrc/render.hip", "paper_2010_08735_amd/csrc/bh_dev.h",
+                  "paper_2010_08735_amd/build.py")
 
 
 def kernel_profile():

@@ -14,9 +14,12 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed FP32 instructions are kept out of the device code (-packed-fp32-ops).  FP32
 # division and square root stay correctly rounded by default; the kernels opt into the
-# fast forms only where the result is not amplified by cancellation.
+# fast forms only where the result is not amplified by cancellation.  Multiply-adds are
+# fused only inside one expression (-ffp-contract=on), so a kernel's arithmetic does not
+# depend on how the optimiser moves code between loops: every tile shape and launch form
+# produces the same bits.
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Xclang", "-target-feature",
-         "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-function",
+         "-Xclang", "-packed-fp32-ops", "-ffp-contract=on", "-Wall", "-Wno-unused-function",
          "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
 
 

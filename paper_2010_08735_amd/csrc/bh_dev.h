@@ -142,7 +142,7 @@ __device__ __forceinline__ float bilinear(const float* __restrict__ t, int nx, i
   int i0 = min((int)tx, hi - 1);
   int j0 = min((int)ty, ny - 2);
   float fx = tx - (float)i0, fy = ty - (float)j0;
-  const float* r0 = t + (size_t)j0 * nx + i0;
+  const float* r0 = t + (__umul24((unsigned)j0, (unsigned)nx) + (unsigned)i0);  // nx, ny < 2^24
   const float* r1 = r0 + nx;
   float a = r0[0] + fx * (r0[1] - r0[0]);
   float b = r1[0] + fx * (r1[1] - r1[0]);
@@ -194,8 +194,11 @@ __device__ __forceinline__ float4 band_lookup(const LutDev& L, float T) {
   int k = min((int)x, L.n - 2);
   float fr = x - (float)k;  // > 1 above the table: linear extrapolation in log-log
   float4 a = L.lut[k], b = L.lut[k + 1];
-  return make_float4(exp2f(a.x + fr * (b.x - a.x)), exp2f(a.y + fr * (b.y - a.y)),
-                     exp2f(a.z + fr * (b.z - a.z)), exp2f(a.w + fr * (b.w - a.w)));
+  // hardware 2^x (about 1 ulp; results below 2^-126 flush to zero)
+  return make_float4(__builtin_amdgcn_exp2f(a.x + fr * (b.x - a.x)),
+                     __builtin_amdgcn_exp2f(a.y + fr * (b.y - a.y)),
+                     __builtin_amdgcn_exp2f(a.z + fr * (b.z - a.z)),
+                     __builtin_amdgcn_exp2f(a.w + fr * (b.w - a.w)));
 }
 
 }  // namespace bh

@@ -27,12 +27,78 @@ struct __align__(8) Half4r {
   _Float16 x, y, z, w;
 };
 
-__device__ __forceinline__ float4 load_texel(const StarsDev& S, uint32_t idx) {
-  if (S.fp16) {
-    Half4r h = ((const Half4r*)S.tex)[idx];
-    return make_float4((float)h.x, (float)h.y * 1024.0f, (float)h.z, (float)h.w);
+// Stored texels are (I, T, p_u, p_v); the FP16 format keeps I / scale_L and T / 1024, and
+// the caller applies both factors once to the footprint sums.
+
+// Footprint of one pixel on one star-map level: texel columns x0 .. x0 + 8 and rows
+// y0 .. y0 + ny at most, read from the occupancy bits into one 81-bit mask (bit 9 r + c for
+// row y0 + r, column x0 + c; rows 0-6 in `lo`, rows 7-8 in `hi`), then one pass over the set
+// bits.  A single loop over occupied texels keeps the lanes of a wave in step far better
+// than a loop per row.  Adds the tent-weighted sums of I and I T, in stored units, to A, B.
+struct Footprint {
+  uint32_t texel0;       // texel index of (x0, y0)
+  const uint32_t* occ;   // occupancy word holding (x0, y0)
+  int nL, wpr, sh, ny;
+  uint32_t span;         // bit mask of the footprint's columns, shifted to bit 0
+  float cu, cv, tw;      // du = (c + p_u) tw + cu, dv = (r + p_v) tw + cv
+  float i00, i01, i10, i11;  // inverse face Jacobian
+};
+
+template <bool FP16, bool COUNT>
+__device__ __forceinline__ void gather(const void* tex, const Footprint& F, uint32_t* touched,
+                                       float& A, float& B) {
+  uint64_t lo = 0;
+  uint32_t hi = 0;
+  uint32_t off = 0;
+  for (int r = 0; r <= F.ny; ++r, off += (uint32_t)F.wpr) {
+    const uint32_t* orow = F.occ + off;
+    uint64_t two = (uint64_t)orow[0] | ((uint64_t)orow[1] << 32);
+    uint64_t b = (two >> F.sh) & F.span;
+    if (r < 7)
+      lo |= b << (9 * r);
+    else
+      hi |= (uint32_t)b << (9 * (r - 7));
   }
-  return ((const float4*)S.tex)[idx];
+  auto tap = [&](int idx) {
+    int r = (idx * 57) >> 9;  // idx / 9 for idx < 81
+    int c = idx - 9 * r;
+    uint32_t t = F.texel0 + __umul24((unsigned)r, (unsigned)F.nL) + (uint32_t)c;  // nL < 2^24
+    if (COUNT) atomicOr(&touched[t >> 5], 1u << (t & 31));
+    float cu = fmaf((float)c, F.tw, F.cu), cv = fmaf((float)r, F.tw, F.cv);
+    float du, dv;
+    if (FP16) {
+      // half operands go straight into mixed-precision multiply-adds
+      Half4r hx = ((const Half4r*)tex)[t];
+      du = fmaf((float)hx.z, F.tw, cu);
+      dv = fmaf((float)hx.w, F.tw, cv);
+      float w = F.i00 * du + F.i01 * dv;
+      float h = F.i10 * du + F.i11 * dv;
+      float wt = fmaxf(1.0f - fabsf(w), 0.0f) * fmaxf(1.0f - fabsf(h), 0.0f);
+      float wi = fmaf(wt, (float)hx.x, 0.0f);
+      A += wi;
+      B = fmaf(wi, (float)hx.y, B);
+    } else {
+      float4 x = ((const float4*)tex)[t];
+      du = fmaf(x.z, F.tw, cu);
+      dv = fmaf(x.w, F.tw, cv);
+      float w = F.i00 * du + F.i01 * dv;
+      float h = F.i10 * du + F.i11 * dv;
+      float wt = fmaxf(1.0f - fabsf(w), 0.0f) * fmaxf(1.0f - fabsf(h), 0.0f);
+      float wi = wt * x.x;
+      A += wi;
+      B = fmaf(wi, x.y, B);
+    }
+  };
+  while (lo) {
+    int idx = __builtin_ctzll(lo);
+    lo &= lo - 1u;
+    tap(idx);
+  }
+  while (hi) {
+    int idx = 63 + __builtin_ctz(hi);
+    hi &= hi - 1u;
+    tap(idx);
+  }
 }
 
 struct TraceOut {
@@ -103,7 +169,7 @@ __device__ __forceinline__ float disc_temperature(const ViewDev& v, float u) {
     float f = u * u * u * (1.0f - sqrtf(3.0f * u));
     return f > 0.0f ? v.T0 * sqrtf(sqrtf(f * v.T_norm)) : 0.0f;
   }
-  return v.T0 * exp2f(-v.T_exp * __log2f(3.0f * u));
+  return v.T0 * __builtin_amdgcn_exp2f(-v.T_exp * __log2f(3.0f * u));
 }
 
 __device__ __forceinline__ float quad_diff(float x, int mask, int hi) {
@@ -266,8 +332,13 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
     float A = 0.0f, B = 0.0f;
     if (fabsf(det) >= 1e-20f) {
       float idet = fdiv(1.0f, det);
-      int nL = S.n0 >> Lv;
-      float fn = (float)nL;  // power of two: 2 / fn below is exact
+      Footprint F;
+      F.i00 = J11 * idet;
+      F.i01 = -J01 * idet;
+      F.i10 = -J10 * idet;
+      F.i11 = J00 * idet;
+      const int nL = S.n0 >> Lv;
+      const float fn = (float)nL;  // power of two: 2 / fn below is exact
       // clamp before the integer conversion (equal to floor-then-clamp for in-range values)
       const float top = fn - 1.0f;
       int x0 = (int)clampf(0.5f * (U - hu + 1.0f) * fn, 0.0f, top);
@@ -276,37 +347,25 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
       int y1 = (int)clampf(0.5f * (V + hv + 1.0f) * fn, 0.0f, top);
       x1 = min(x1, x0 + 8);
       y1 = min(y1, y0 + 8);
-      float iscale = S.scale[Lv];
-      uint32_t base = S.level_off[Lv] + (uint32_t)face * (uint32_t)nL * (uint32_t)nL;
-      const int wpr = ((nL + 31) >> 5) + 1;
-      const uint32_t* occ = S.occ + S.occ_off[Lv] + (uint32_t)face * (uint32_t)nL * (uint32_t)wpr;
-      const int w0 = x0 >> 5, sh = x0 & 31;
-      const uint32_t span = (1u << (x1 - x0 + 1)) - 1u;  // x1 - x0 <= 8
-      float tw = fdiv(2.0f, fn);
-      for (int ty = y0; ty <= y1; ++ty) {
-        const uint32_t* orow = occ + (uint32_t)ty * (uint32_t)wpr + (uint32_t)w0;
-        uint64_t two = (uint64_t)orow[0] | ((uint64_t)orow[1] << 32);
-        uint32_t bits = (uint32_t)(two >> sh) & span;
-        uint32_t row = base + (uint32_t)ty * (uint32_t)nL;
-        float sv0 = (float)ty * tw - 1.0f - V;
-        while (bits) {
-          int tx = x0 + __builtin_ctz(bits);
-          bits &= bits - 1u;
-          if (COUNT) {
-            uint32_t id = row + (uint32_t)tx;
-            atomicOr(&touched[id >> 5], 1u << (id & 31));
-          }
-          float4 tex = load_texel(S, row + (uint32_t)tx);
-          float I = tex.x * iscale;
-          float du = ((float)tx + tex.z) * tw - 1.0f - U;
-          float dv = sv0 + tex.w * tw;
-          float w = (J11 * du - J01 * dv) * idet;
-          float h = (J00 * dv - J10 * du) * idet;
-          float wt = fmaxf(1.0f - fabsf(w), 0.0f) * fmaxf(1.0f - fabsf(h), 0.0f);
-          A += wt * I;
-          B += wt * I * tex.y;
-        }
-      }
+      F.nL = nL;
+      F.wpr = ((nL + 31) >> 5) + 1;
+      F.sh = x0 & 31;
+      F.ny = y1 - y0;
+      F.span = (1u << (x1 - x0 + 1)) - 1u;  // x1 - x0 <= 8
+      F.texel0 = S.level_off[Lv] + ((uint32_t)face * (uint32_t)nL + (uint32_t)y0) * (uint32_t)nL +
+                 (uint32_t)x0;
+      F.occ = S.occ + S.occ_off[Lv] +
+              ((uint32_t)face * (uint32_t)nL + (uint32_t)y0) * (uint32_t)F.wpr + (uint32_t)(x0 >> 5);
+      F.tw = fdiv(2.0f, fn);
+      F.cu = (float)x0 * F.tw - 1.0f - U;
+      F.cv = (float)y0 * F.tw - 1.0f - V;
+      if (S.fp16)
+        gather<true, COUNT>(S.tex, F, touched, A, B);
+      else
+        gather<false, COUNT>(S.tex, F, touched, A, B);
+      const float iscale = S.scale[Lv];
+      A *= iscale;
+      B *= S.fp16 ? iscale * 1024.0f : iscale;
     }
     float cqx = qw1 * qh2 - qw2 * qh1, cqy = qw2 * qh0 - qw0 * qh2, cqz = qw0 * qh1 - qw1 * qh0;
     float cdx = dw1 * dh2 - dw2 * dh1, cdy = dw2 * dh0 - dw0 * dh2, cdz = dw0 * dh1 - dw1 * dh0;

@@ -52,6 +52,16 @@ def orc_tables(orc):
     return orc.Tables(512, 64, 32)
 
 
+@pytest.fixture(scope="session")
+def big_field_scene(gpu_ctx, orc):
+    """One million seeded stars in a 6 x 2048^2 FP16 map (GPU) and the oracle's map."""
+    from paper_2010_08735_amd import bh, scenes
+    field = scenes.star_field(1_000_000, 1)
+    n0 = 2048
+    h = gpu_star_map(gpu_ctx, field, n0, bh.BH_TEXEL_FP16, key=1001)
+    return field, n0, h, orc.cubemap(field, n0)
+
+
 def gpu_star_map(ctx, field, n0, fmt=0, key=0):
     import torch
     from paper_2010_08735_amd import bh

@@ -176,14 +176,6 @@ def test_small_static_view_full_frame(gpu_ctx, gpu_tables, orc, orc_tables, smal
     assert parity.frac_within(pe, g, 3e-2, "all") > 0.99
 
 
-@pytest.fixture(scope="module")
-def big_field_scene(gpu_ctx, orc):
-    field = scenes.star_field(1_000_000, 1)
-    n0 = 2048
-    h = gpu_star_map(gpu_ctx, field, n0, bh.BH_TEXEL_FP16, key=1001)
-    return field, n0, h, orc.cubemap(field, n0)
-
-
 def test_boosted_orbit_view_sampled(gpu_ctx, gpu_tables, orc, orc_tables, big_field_scene):
     """1920x1080 camera at r = 6 moving at 0.9c: a seeded 1% of the quads."""
     field, n0, h, cube = big_field_scene
