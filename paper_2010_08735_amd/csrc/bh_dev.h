@@ -177,6 +177,17 @@ __device__ __forceinline__ float lookup_D(const TablesDev& T, float e2, float u,
   return bilinear(T.D, n, n, n / 2, n - 1, x, y);
 }
 
+// D(e, u_a) for e^2 < mu: the apsis is the last row (y = 1) of the left half
+__device__ __forceinline__ float lookup_D_apsis(const TablesDev& T, float e2) {
+  const int n = T.d_n, hi = n / 2 - 1;
+  float x = 0.5f - fsqrt(-flog1p(-e2 * (1.0f / kMu)) * (1.0f / 50.0f));
+  float tx = clampf(x * (float)(n - 1), 0.0f, (float)hi);
+  int i0 = min((int)tx, hi - 1);
+  float fx = tx - (float)i0;
+  const float* r = T.D + (__umul24((unsigned)(n - 1), (unsigned)n) + (unsigned)i0);
+  return r[0] + fx * (r[1] - r[0]);
+}
+
 // U(e, phi) through the Appendix A mapping
 __device__ __forceinline__ float lookup_U(const TablesDev& T, float e2, float e, float phi) {
   float x = fdiv(1.0f, 1.0f + 6.0f * e2);

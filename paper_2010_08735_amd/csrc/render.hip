@@ -3,7 +3,7 @@
 // Thread layout: one wavefront covers an 8x8 pixel block; lane l handles quad l >> 2 of
 // the block (4x4 quads) and pixel (l & 1, (l >> 1) & 1) inside the quad, so the 2x2 quad
 // partners needed for screen-space derivatives are lanes l^1 (same row) and l^2 (same
-// column) and are read with DPP quad permutes.  A workgroup tile is TW x TH pixels made of
+// column) and are read with DPP quad permutations.  A workgroup tile is TW x TH pixels made of
 // 8x8 blocks; each wave walks PPT blocks.  Pixels outside the image are computed (their
 // rays are valid) but not stored, so every quad is complete.
 //
@@ -73,7 +73,8 @@ __device__ __forceinline__ void gather(const void* tex, const Footprint& F, uint
       dv = fmaf((float)hx.w, F.tw, cv);
       float w = F.i00 * du + F.i01 * dv;
       float h = F.i10 * du + F.i11 * dv;
-      float wt = fmaxf(1.0f - fabsf(w), 0.0f) * fmaxf(1.0f - fabsf(h), 0.0f);
+      float wt = __builtin_amdgcn_fmed3f(1.0f - fabsf(w), 0.0f, 1.0f) *
+                 __builtin_amdgcn_fmed3f(1.0f - fabsf(h), 0.0f, 1.0f);  // max(1 - |x|, 0)
       float wi = fmaf(wt, (float)hx.x, 0.0f);
       A += wi;
       B = fmaf(wi, (float)hx.y, B);
@@ -83,7 +84,8 @@ __device__ __forceinline__ void gather(const void* tex, const Footprint& F, uint
       dv = fmaf(x.w, F.tw, cv);
       float w = F.i00 * du + F.i01 * dv;
       float h = F.i10 * du + F.i11 * dv;
-      float wt = fmaxf(1.0f - fabsf(w), 0.0f) * fmaxf(1.0f - fabsf(h), 0.0f);
+      float wt = __builtin_amdgcn_fmed3f(1.0f - fabsf(w), 0.0f, 1.0f) *
+                 __builtin_amdgcn_fmed3f(1.0f - fabsf(h), 0.0f, 1.0f);  // max(1 - |x|, 0)
       float wi = wt * x.x;
       A += wi;
       B = fmaf(wi, x.y, B);
@@ -102,6 +104,7 @@ __device__ __forceinline__ void gather(const void* tex, const Footprint& F, uint
 }
 
 struct TraceOut {
+  float e;             // the beam's invariant e = sqrt(e^2)
   float dprime;        // escape angle (valid if !captured)
   float ucr[2];
   int ncross;
@@ -118,6 +121,8 @@ __device__ __forceinline__ TraceOut trace_ray(const TablesDev& T, float u, float
   o.dprime = 0.0f;
   float udot = -u * cotd;
   float e2 = udot * udot + u * u * (1.0f - u);
+  float e = fsqrt(e2);
+  o.e = e;
   if (e2 < kMu && u > 2.0f / 3.0f) {
     o.bits = BH_CAPTURED_BIT;
     return o;
@@ -128,10 +133,9 @@ __device__ __forceinline__ TraceOut trace_ray(const TablesDev& T, float u, float
   float Dl = lookup_D(T, e2, u, ua, udot);
   float Da = 0.0f, phia = __builtin_inff();
   if (bound) {
-    Da = lookup_D(T, e2, ua, ua, 0.0f);
+    Da = lookup_D_apsis(T, e2);
     phia = Da + 0.5f * kPi;
   }
-  float e = fsqrt(e2);
   float phi = Dl + (s == 1 ? kPi - delta : delta) + (float)s * alpha;
   float phi0 = phi - kPi * floorf(phi * (1.0f / kPi));
   float u0 = lookup_U(T, e2, e, phi0);
@@ -172,9 +176,23 @@ __device__ __forceinline__ float disc_temperature(const ViewDev& v, float u) {
   return v.T0 * __builtin_amdgcn_exp2f(-v.T_exp * __log2f(3.0f * u));
 }
 
-__device__ __forceinline__ float quad_diff(float x, int mask, int hi) {
-  float p = __shfl_xor(x, mask);
-  return hi ? x - p : p - x;
+// Partner of this lane inside its quad (DPP quad permutation, all lanes active): MASK 1
+// swaps lanes 0<->1, 2<->3 (row partner), MASK 2 swaps 0<->2, 1<->3 (column partner).
+template <int MASK>
+__device__ __forceinline__ float quad_partner(float x) {
+  constexpr int ctrl = MASK == 1 ? 0xB1 : 0x4E;  // quad_perm [1,0,3,2] / [2,3,0,1]
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), ctrl, 0xF, 0xF, true));
+}
+
+// (value at the quad partner) - (value here): the forward difference along the row
+// (MASK 1) or column (MASK 2) on lanes at the quad's low side and its negative on the
+// others.  Every use below is invariant under flipping the sign of all row (or all
+// column) differences of a lane: footprint extents and the tent weights take |.|, and
+// the solid angles are norms of cross products; IEEE negation is exact, so the results
+// equal those of the forward differences bit for bit.
+template <int MASK>
+__device__ __forceinline__ float quad_diff(float x) {
+  return quad_partner<MASK>(x) - x;
 }
 
 // One pixel; every lane of the wave must call this together (quad exchanges).
@@ -184,8 +202,6 @@ template <bool COUNT>
 __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& T,
                                              const LutDev& L, int px, int py,
                                              uint32_t* touched) {
-  const int lane = threadIdx.x & 63;
-  const int hx = lane & 1, hy = (lane >> 1) & 1;
 
   // ---- beam initialisation (Section 3.2)
   float qw = (float)px + 0.5f - v.half_w;
@@ -256,17 +272,17 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
 
   // ---- disc (Sections 3.3.3, 3.4.2), front to back
   float cr = 0.0f, cg = 0.0f, cb = 0.0f, trans = 1.0f;
-  {
-    float u = v.u_c, cotd = dr / ncz;
-    float e = fsqrt((u * cotd) * (u * cotd) + u * u * (1.0f - u));
+  if (tr.ncross > 0) {
+    const float ie = fdiv(1.0f, tr.e);
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       if (k >= tr.ncross) break;
       float uk = k == 0 ? tr.ucr[0] : tr.ucr[1];
       float Tp = disc_temperature(v, uk);
-      float kt = fsqrt(fdiv(2.0f, 2.0f - 3.0f * uk));
+      // 1 / k'^t = sqrt(1 - 3u/2) and Omega' = sqrt(u^3 / 2) on the circular orbit at u
+      float ikt = fsqrt(1.0f - 1.5f * uk);
       float om = fsqrt(0.5f * uk * uk * uk);
-      float D = fdiv(dcam, kt * (1.0f + fdiv(om * zeta, e)));
+      float D = dcam * ikt * fdiv(1.0f, 1.0f + om * zeta * ie);
       float4 Lb = band_lookup(L, D * Tp);
       float w = trans * v.rho * v.k_disc;
       cr += w * Lb.x;
@@ -283,12 +299,12 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
   float dp1 = captured ? 0.0f : cdp * v.rhat[1] + sdp * ey1;
   float dp2 = captured ? 0.0f : cdp * v.rhat[2] + sdp * ey2;
   int cap = captured ? 1 : 0;
-  cap |= __shfl_xor(cap, 1);
-  cap |= __shfl_xor(cap, 2);
-  float dw0 = quad_diff(dp0, 1, hx), dw1 = quad_diff(dp1, 1, hx), dw2 = quad_diff(dp2, 1, hx);
-  float dh0 = quad_diff(dp0, 2, hy), dh1 = quad_diff(dp1, 2, hy), dh2 = quad_diff(dp2, 2, hy);
-  float qw0 = quad_diff(q0, 1, hx), qw1 = quad_diff(q1, 1, hx), qw2 = quad_diff(q2, 1, hx);
-  float qh0 = quad_diff(q0, 2, hy), qh1 = quad_diff(q1, 2, hy), qh2 = quad_diff(q2, 2, hy);
+  cap |= __builtin_amdgcn_mov_dpp(cap, 0xB1, 0xF, 0xF, true);
+  cap |= __builtin_amdgcn_mov_dpp(cap, 0x4E, 0xF, 0xF, true);
+  float dw0 = quad_diff<1>(dp0), dw1 = quad_diff<1>(dp1), dw2 = quad_diff<1>(dp2);
+  float dh0 = quad_diff<2>(dp0), dh1 = quad_diff<2>(dp1), dh2 = quad_diff<2>(dp2);
+  float qw0 = quad_diff<1>(q0), qw1 = quad_diff<1>(q1), qw2 = quad_diff<1>(q2);
+  float qh0 = quad_diff<2>(q0), qh1 = quad_diff<2>(q1), qh2 = quad_diff<2>(q2);
   int mip = 255;
   if (cap) bits |= BH_STAR_ZEROED_BIT;
   if (v.has_stars && !cap) {
