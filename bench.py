@@ -124,18 +124,23 @@ def batch_leg(bh, ctx, tables, views, reps):
     return res
 
 
-def serve_leg(bh, scenes, tables_of, fields, duration, rate, seed, budget):
+def serve_leg(bh, scenes, tables_of, fields, duration, rate, seed, budget, max_tiles,
+              inflight, tile_config):
     """Poisson arrivals for `duration` seconds through bh_submit/bh_poll (library-allocated
-    images inside the HBM budget), then the same requests submitted all at once."""
+    images inside the HBM budget), then the same requests submitted all at once, twice: the
+    first pass allocates the server's images, the second runs on its recycled images."""
     import torch
     reqs = scenes.serve_requests(rate=rate, duration=duration, seed=seed)
-    out = {"requests": len(reqs), "rate_per_s": rate, "duration_s": duration}
-    for mode in ("poisson", "saturated"):
-        ctx = bh.bh_create(0, budget)
-        try:
-            tables = tables_of(ctx)
-            smaps = [star_map(bh, ctx, f, 2048, 40 + k) for k, f in enumerate(fields)]
-            bh.bh_serve_start(ctx, 0, 3, 8192)
+    out = {"requests": len(reqs), "rate_per_s": rate, "duration_s": duration,
+           "max_tiles_per_launch": max_tiles, "max_inflight_launches": inflight,
+           "tile_config": tile_config}
+    ctx = bh.bh_create(0, budget)
+    try:
+        tables = tables_of(ctx)
+        smaps = [star_map(bh, ctx, f, 2048, 40 + k) for k, f in enumerate(fields)]
+        bh.bh_set_tile_config(ctx, tile_config)
+        bh.bh_serve_start(ctx, 0, inflight, max_tiles)
+        for mode in ("poisson", "saturated_first_pass", "saturated"):
             tickets, lat = [], []
             t_start = time.perf_counter()
             px = 0
@@ -163,12 +168,36 @@ def serve_leg(bh, scenes, tables_of, fields, duration, rate, seed, budget):
                 lat.append(l)
                 bh.bh_ticket_free(ctx, t)
             span = time.perf_counter() - t_start
-        finally:
-            bh.bh_destroy(ctx)
-        lat.sort()
-        out[mode] = {"mpx_per_s": px / span / 1e6, "makespan_s": span,
-                     "latency_p50_ms": 1e3 * lat[len(lat) // 2],
-                     "latency_p99_ms": 1e3 * lat[min(len(lat) - 1, int(0.99 * len(lat)))]}
+            lat.sort()
+            out[mode] = {"mpx_per_s": px / span / 1e6, "makespan_s": span,
+                         "latency_p50_ms": 1e3 * lat[len(lat) // 2],
+                         "latency_p99_ms": 1e3 * lat[min(len(lat) - 1, int(0.99 * len(lat)))]}
+    finally:
+        bh.bh_destroy(ctx)
+    # the same requests as one plain launch per frame, back to back on one stream
+    ctx = bh.bh_create(0, budget)
+    try:
+        tables = tables_of(ctx)
+        smaps = [star_map(bh, ctx, f, 2048, 40 + k) for k, f in enumerate(fields)]
+        imgs = {}
+        for r in reqs:
+            key = (r.view.width, r.view.height)
+            if key not in imgs:
+                imgs[key] = torch.empty((key[1], key[0], 4), dtype=torch.float32, device="cuda")
+        views = [bh.make_view(r.view, smaps[r.field]) for r in reqs]
+        st = bh.current_stream()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        px = 0
+        for r, v in zip(reqs, views):
+            bh.bh_render(ctx, tables, v, imgs[(r.view.width, r.view.height)].data_ptr(), None, st)
+            px += r.view.width * r.view.height
+        torch.cuda.synchronize()
+        span = time.perf_counter() - t0
+        del imgs
+    finally:
+        bh.bh_destroy(ctx)
+    out["plain_per_frame"] = {"mpx_per_s": px / span / 1e6, "makespan_s": span}
     return out
 
 
@@ -205,6 +234,12 @@ def main():
     ap.add_argument("--legs", default="plain,batch,serve,cpu",
                     help="comma list of plain, batch, serve, cpu")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
+    ap.add_argument("--serve-tiles", type=int, default=262144,
+                    help="most 16x16 tiles in one serving launch")
+    ap.add_argument("--serve-inflight", type=int, default=6,
+                    help="serving launches kept in flight")
+    ap.add_argument("--serve-tile-config", type=int, default=0,
+                    help="tile configuration index of the serving launches")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the beam tracer runs on a single MI355X here "
@@ -291,7 +326,8 @@ def main():
         fields = [scenes.star_field(n, s) for n, s in scenes.SERVE_FIELDS]
         tab = lambda c: bh.bh_precompute_tables(c, 512, 64, 32, bh.BH_TAB_FP64_BAND, 0.05)
         extra["served"] = serve_leg(bh, scenes, tab, fields, args.serve_seconds, 200.0, 4,
-                                    64 << 30)
+                                    64 << 30, args.serve_tiles, args.serve_inflight,
+                                    args.serve_tile_config)
         log("serve:", json.dumps(extra["served"]))
 
     if "calib" in legs:

@@ -184,8 +184,8 @@ bh_status bh_autotune(bh_ctx* ctx, const bh_tables* t, const bh_view* views, int
 
 typedef struct {
   int32_t max_queue;          /* submissions beyond this return BH_EAGAIN                */
-  int32_t max_inflight_launches; /* launches kept in flight on the serving stream (2)    */
-  int64_t max_tiles_per_launch;  /* tiles per launch; bigger requests are split (16384)  */
+  int32_t max_inflight_launches; /* launches kept in flight on the serving stream (6)    */
+  int64_t max_tiles_per_launch;  /* tiles per launch; bigger requests are split (262144) */
 } bh_serve_params;
 
 /* Start the serving scheduler thread on its own stream (call once per context). */
@@ -199,7 +199,9 @@ bh_status bh_submit(bh_ctx* ctx, const bh_tables* t, const bh_view* v, float* ou
 bh_status bh_poll(bh_ctx* ctx, uint64_t ticket, int32_t* done, double* latency_s);
 /* Image of a finished ticket that was submitted with out_rgba_dev = NULL. */
 bh_status bh_ticket_image(bh_ctx* ctx, uint64_t ticket, float** out_rgba_dev);
-/* Forget a finished ticket (and free a library-allocated image). */
+/* Forget a finished ticket.  A library-allocated image goes back to the serving pool and
+ * is reused by later frames at once, so the caller must first finish every device
+ * operation that reads it (for instance synchronize the stream of its copy-out). */
 bh_status bh_ticket_free(bh_ctx* ctx, uint64_t ticket);
 /* Block until every submitted request is complete. */
 bh_status bh_serve_drain(bh_ctx* ctx);

@@ -61,9 +61,12 @@ struct ViewDev {
   float4* aov;
 };
 
-// tile work item for the batched kernel: view index and tile origin
-struct WorkItem {
-  int view, x0, y0, pad;
+// Work of the batched kernels, as runs of consecutive tiles of one view: the view's tiles
+// tile0 .. tile0 + n - 1 (row-major tile order, tiles_x tiles per row) take the launch's
+// flat tile indices start .. start + n - 1.  A launch lists its runs in increasing start,
+// the first at 0.
+struct TileRun {
+  int view, tile0, start, tiles_x;
 };
 
 __device__ __forceinline__ float clampf(float x, float lo, float hi) {

@@ -41,7 +41,7 @@ hipError_t launch_star_unpack(const void* in, int64_t count, float scale, int fp
 hipError_t launch_render(int cfg, const ViewDev& v, const TablesDev& T, const LutDev& L,
                          hipStream_t s);
 hipError_t launch_render_batch(int cfg, int persistent, const ViewDev* views,
-                               const WorkItem* items, int nitems, int* counter,
+                               const TileRun* runs, int nruns, int ntiles, int* counter,
                                const TablesDev& T, const LutDev& L, int grid, hipStream_t s);
 hipError_t launch_trace_rays(const TablesDev& T, const float* rays, int64_t n, float4* out,
                              hipStream_t s);
@@ -141,19 +141,22 @@ struct bh_ctx {
   int persistent = 0;  // batched launches: 1 = persistent workgroups, 0 = one per tile
   // recycled library-allocated images (serving), counted in `used`
   std::multimap<size_t, void*> pool;
+  // stream-ordered memory pool of the library-allocated images: allocation and release on
+  // the serving stream never wait for the device
+  hipMemPool_t img_pool = nullptr;
   // batched launches
   ViewDev* b_views = nullptr;
-  WorkItem* b_items = nullptr;
+  TileRun* b_runs = nullptr;
   int* b_counter = nullptr;
-  size_t b_views_cap = 0, b_items_cap = 0;
+  size_t b_cap = 0;  // views and runs held by b_views / b_runs
   Staging b_stage[2];
   int b_next_stage = 0;
-  hipEvent_t b_last = nullptr;  // completion of the last batch that used b_views/b_items
+  hipEvent_t b_last = nullptr;  // completion of the last batch that used b_views/b_runs
   struct GraphEntry {
     hipGraphExec_t exec;
     hipStream_t stream;
   };
-  std::map<std::tuple<int, int, int, const void*, uintptr_t>, GraphEntry> graphs;
+  std::map<std::tuple<int, int, int, int, const void*, uintptr_t>, GraphEntry> graphs;
   // serving
   std::thread serve_thread;
   bool serving = false, stop = false;
@@ -251,7 +254,7 @@ extern "C" void bh_destroy(bh_ctx* c) {
   dev_free(c, c->lut, 0);
   dev_free(c, c->b_counter, 0);
   dev_free(c, c->b_views, 0);
-  dev_free(c, c->b_items, 0);
+  dev_free(c, c->b_runs, 0);
   for (auto& s : c->b_stage) {
     if (s.host) (void)hipHostFree(s.host);
     if (s.done) (void)hipEventDestroy(s.done);
@@ -618,35 +621,45 @@ extern "C" bh_status bh_set_tile_config(bh_ctx* c, int32_t i) {
   return BH_OK;
 }
 
-// Upload view blocks + work items through a pinned staging buffer and enqueue one
-// persistent launch.  Caller holds c->mu.
+// Upload view blocks and tile runs through a pinned staging buffer and enqueue one batched
+// launch over `ntiles` tiles on stream s.  With a copy stream `cs`, the uploads run there
+// (after `slot_free`, the end of the last launch that read dviews/druns) and s waits for
+// them through `copied`, so they overlap the kernels already queued on s.  Caller holds
+// c->mu.
 static bh_status enqueue_batch(bh_ctx* c, const TablesDev& T, const std::vector<ViewDev>& vds,
-                               const std::vector<WorkItem>& items, ViewDev* dviews,
-                               WorkItem* ditems, int* counter, Staging& stg, hipStream_t s,
-                               bool use_graph) {
-  size_t bv = sizeof(ViewDev) * vds.size(), bi = sizeof(WorkItem) * items.size();
-  bh_status st = ensure_staging(stg, bv + bi);
+                               const std::vector<TileRun>& runs, int ntiles, ViewDev* dviews,
+                               TileRun* druns, int* counter, Staging& stg, hipStream_t s,
+                               bool use_graph, hipStream_t cs = nullptr,
+                               hipEvent_t slot_free = nullptr, hipEvent_t copied = nullptr) {
+  size_t bv = sizeof(ViewDev) * vds.size(), br = sizeof(TileRun) * runs.size();
+  bh_status st = ensure_staging(stg, bv + br);
   if (st) return st;
   if (stg.used) HIPCHK(hipEventSynchronize(stg.done));
+  hipStream_t up = cs ? cs : s;
+  if (cs && slot_free) HIPCHK(hipStreamWaitEvent(cs, slot_free, 0));
   memcpy(stg.host, vds.data(), bv);
-  memcpy((char*)stg.host + bv, items.data(), bi);
-  HIPCHK(hipMemcpyAsync(dviews, stg.host, bv, hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(ditems, (char*)stg.host + bv, bi, hipMemcpyHostToDevice, s));
-  HIPCHK(hipEventRecord(stg.done, s));
+  memcpy((char*)stg.host + bv, runs.data(), br);
+  HIPCHK(hipMemcpyAsync(dviews, stg.host, bv, hipMemcpyHostToDevice, up));
+  HIPCHK(hipMemcpyAsync(druns, (char*)stg.host + bv, br, hipMemcpyHostToDevice, up));
+  HIPCHK(hipEventRecord(stg.done, up));
   stg.used = true;
+  if (cs) {
+    HIPCHK(hipEventRecord(copied, cs));
+    HIPCHK(hipStreamWaitEvent(s, copied, 0));
+  }
   int cfg = c->tile_cfg;
   int pers = c->persistent;
   int tw, th, waves, ppt;
   tile_config(cfg, &tw, &th, &waves, &ppt);
   int per_cu = std::max(1, 16 / waves);
-  int grid = std::min<int>((int)items.size(), c->cus * per_cu);
-  grid = std::max(grid, 1);
+  int grid = std::max(1, std::min<int>(ntiles, c->cus * per_cu));
+  int nruns = (int)runs.size();
   LutDev L = lut_dev(c);
   if (!use_graph) {
-    HIPCHK(launch_render_batch(cfg, pers, dviews, ditems, (int)items.size(), counter, T, L, grid, s));
+    HIPCHK(launch_render_batch(cfg, pers, dviews, druns, nruns, ntiles, counter, T, L, grid, s));
     return BH_OK;
   }
-  auto key = std::make_tuple(cfg * 2 + pers, (int)items.size(), grid, (const void*)T.D,
+  auto key = std::make_tuple(cfg * 2 + pers, ntiles, nruns, grid, (const void*)T.D,
                              (uintptr_t)counter);
   auto it = c->graphs.find(key);
   if (it == c->graphs.end()) {
@@ -654,7 +667,7 @@ static bh_status enqueue_batch(bh_ctx* c, const TablesDev& T, const std::vector<
     HIPCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
     hipGraph_t graph;
     HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-    hipError_t e = launch_render_batch(cfg, pers, dviews, ditems, (int)items.size(), counter, T, L,
+    hipError_t e = launch_render_batch(cfg, pers, dviews, druns, nruns, ntiles, counter, T, L,
                                        grid, cap);
     hipError_t e2 = hipStreamEndCapture(cap, &graph);
     (void)hipStreamDestroy(cap);
@@ -675,37 +688,27 @@ static void clear_graphs(bh_ctx* c) {
   c->graphs.clear();
 }
 
-static bh_status ensure_batch_buffers(bh_ctx* c, size_t nviews, size_t nitems) {
-  if (c->b_views_cap < nviews || c->b_items_cap < nitems) {
-    // captured graphs hold the old buffer addresses
-    if (c->b_last) HIPCHK(hipEventSynchronize(c->b_last));
-    clear_graphs(c);
-  }
-  if (c->b_views_cap < nviews) {
-    dev_free(c, c->b_views, sizeof(ViewDev) * c->b_views_cap);
+static bh_status ensure_batch_buffers(bh_ctx* c, size_t nviews) {
+  if (c->b_cap >= nviews) return BH_OK;
+  // captured graphs hold the old buffer addresses
+  if (c->b_last) HIPCHK(hipEventSynchronize(c->b_last));
+  clear_graphs(c);
+  dev_free(c, c->b_views, sizeof(ViewDev) * c->b_cap);
+  dev_free(c, c->b_runs, sizeof(TileRun) * c->b_cap);
+  c->b_views = nullptr;
+  c->b_runs = nullptr;
+  c->b_cap = 0;
+  size_t cap = std::max<size_t>(nviews, 64);
+  bh_status st = dev_alloc(c, sizeof(ViewDev) * cap, (void**)&c->b_views);
+  if (st) return st;
+  st = dev_alloc(c, sizeof(TileRun) * cap, (void**)&c->b_runs);
+  if (st) {
+    dev_free(c, c->b_views, sizeof(ViewDev) * cap);
     c->b_views = nullptr;
-    c->b_views_cap = 0;
-    size_t cap = std::max<size_t>(nviews, 64);
-    bh_status st = dev_alloc(c, sizeof(ViewDev) * cap, (void**)&c->b_views);
-    if (st) return st;
-    c->b_views_cap = cap;
+    return st;
   }
-  if (c->b_items_cap < nitems) {
-    dev_free(c, c->b_items, sizeof(WorkItem) * c->b_items_cap);
-    c->b_items = nullptr;
-    c->b_items_cap = 0;
-    size_t cap = std::max<size_t>(nitems, 4096);
-    bh_status st = dev_alloc(c, sizeof(WorkItem) * cap, (void**)&c->b_items);
-    if (st) return st;
-    c->b_items_cap = cap;
-  }
+  c->b_cap = cap;
   return BH_OK;
-}
-
-static void tile_items(int vi, int width, int height, int tw, int th, std::vector<WorkItem>& items) {
-  int tx = (width + tw - 1) / tw, ty = (height + th - 1) / th;
-  for (int y = 0; y < ty; ++y)
-    for (int x = 0; x < tx; ++x) items.push_back(WorkItem{vi, x * tw, y * th, 0});
 }
 
 extern "C" bh_status bh_render_batch(bh_ctx* c, const bh_tables* t, const bh_view* views,
@@ -726,10 +729,15 @@ extern "C" bh_status bh_render_batch(bh_ctx* c, const bh_tables* t, const bh_vie
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
     return (int64_t)views[a].width * views[a].height > (int64_t)views[b].width * views[b].height;
   });
-  std::vector<WorkItem> items;
-  for (int i : order) tile_items(i, views[i].width, views[i].height, tw, th, items);
-  if (items.size() >= (size_t)1 << 31) return fail(BH_EINVAL, "too many tiles");
-  bh_status st = ensure_batch_buffers(c, n, items.size());
+  std::vector<TileRun> runs;
+  int64_t ntiles = 0;
+  for (int i : order) {
+    int tx = (views[i].width + tw - 1) / tw, ty = (views[i].height + th - 1) / th;
+    runs.push_back(TileRun{i, 0, (int)ntiles, tx});
+    ntiles += (int64_t)tx * ty;
+    if (ntiles >= (int64_t)1 << 31) return fail(BH_EINVAL, "too many tiles");
+  }
+  bh_status st = ensure_batch_buffers(c, n);
   if (st) return st;
   Staging& stg = c->b_stage[c->b_next_stage];
   c->b_next_stage ^= 1;
@@ -738,8 +746,8 @@ extern "C" bh_status bh_render_batch(bh_ctx* c, const bh_tables* t, const bh_vie
   // call after the previous one even when it was issued on another stream
   if (!c->b_last) HIPCHK(hipEventCreateWithFlags(&c->b_last, hipEventDisableTiming));
   else HIPCHK(hipStreamWaitEvent(s, c->b_last, 0));
-  st = enqueue_batch(c, tables_dev(t), vds, items, c->b_views, c->b_items, c->b_counter, stg, s,
-                     true);
+  st = enqueue_batch(c, tables_dev(t), vds, runs, (int)ntiles, c->b_views, c->b_runs, c->b_counter,
+                     stg, s, true);
   if (st) return st;
   HIPCHK(hipEventRecord(c->b_last, s));
   return BH_OK;
@@ -865,7 +873,8 @@ extern "C" bh_status bh_band_eval(bh_ctx* c, const float* temps, int64_t n, floa
 // tile.
 
 // Library-allocated images: reuse a freed image of the same size, else allocate inside
-// the budget, releasing pooled images if that is what it takes.  Caller holds c->smu.
+// the budget from the context's stream-ordered pool, releasing pooled images (in stream
+// order) if that is what it takes.  Caller holds c->smu.
 static void* pool_get(bh_ctx* c, size_t bytes) {
   auto it = c->pool.find(bytes);
   if (it != c->pool.end()) {
@@ -874,11 +883,17 @@ static void* pool_get(bh_ctx* c, size_t bytes) {
     return p;
   }
   for (;;) {
-    void* p = nullptr;
-    if (dev_alloc(c, bytes, &p) == BH_OK) return p;
+    if (!c->budget || c->used.load() + bytes <= c->budget) {
+      void* p = nullptr;
+      if (hipMallocFromPoolAsync(&p, bytes, c->img_pool, c->serve_stream) == hipSuccess) {
+        c->used += bytes;
+        return p;
+      }
+    }
     if (c->pool.empty()) return nullptr;
     auto big = std::prev(c->pool.end());
-    dev_free(c, big->second, big->first);
+    (void)hipFreeAsync(big->second, c->serve_stream);
+    c->used -= big->first;
     c->pool.erase(big);
   }
 }
@@ -903,12 +918,19 @@ static void serve_loop(bh_ctx* c) {
   const int maxin = std::max(1, c->sp.max_inflight_launches);
   const int64_t maxtiles = std::max<int64_t>(1, c->sp.max_tiles_per_launch);
   std::vector<Staging> stg(maxin + 1);
+  // per launch slot: view blocks, tile runs (one per request in the launch), tile counter
   std::vector<ViewDev*> dviews(maxin + 1, nullptr);
-  std::vector<WorkItem*> ditems(maxin + 1, nullptr);
+  std::vector<TileRun*> druns(maxin + 1, nullptr);
   std::vector<int*> dcounter(maxin + 1, nullptr);
-  std::vector<size_t> vcap(maxin + 1, 0), icap(maxin + 1, 0);
+  std::vector<size_t> rcap(maxin + 1, 0);
+  // uploads on their own stream; per slot: end of its last launch, end of its upload
+  hipStream_t copy_stream = nullptr;
+  std::vector<hipEvent_t> slot_free(maxin + 1, nullptr), copied(maxin + 1, nullptr);
+  bool dev_ok = hipStreamCreateWithFlags(&copy_stream, hipStreamNonBlocking) == hipSuccess;
   for (int k = 0; k <= maxin; ++k) {
-    (void)hipMalloc(&dcounter[k], sizeof(int) * 16);
+    dev_ok = dev_ok && hipMalloc(&dcounter[k], sizeof(int) * 16) == hipSuccess;
+    dev_ok = dev_ok && hipEventCreateWithFlags(&slot_free[k], hipEventDisableTiming) == hipSuccess;
+    dev_ok = dev_ok && hipEventCreateWithFlags(&copied[k], hipEventDisableTiming) == hipSuccess;
   }
   std::deque<Launch> inflight;
   std::vector<hipEvent_t> evpool;
@@ -954,16 +976,18 @@ static void serve_loop(bh_ctx* c) {
       (void)hipEventSynchronize(inflight.front().ev);  // the device is busy: wait for a slot
       continue;
     }
-    // fill one launch
+    // fill one launch: one run of tiles per request, at most maxtiles tiles in all
     std::vector<ViewDev> vds;
-    std::vector<WorkItem> items;
+    std::vector<TileRun> runs;
+    std::vector<uint64_t> in_launch;  // tickets with tiles in this launch
+    int64_t ntiles = 0;
     Launch L;
     std::vector<ServeReq*> keep;
     int tw, th, waves, ppt;
     tile_config(c->tile_cfg, &tw, &th, &waves, &ppt);
     const bh_tables* tb = active.front()->tables;  // one table set per launch
     for (ServeReq* r : active) {
-      if ((int64_t)items.size() >= maxtiles || r->tables != tb) {
+      if (ntiles >= maxtiles || r->tables != tb) {
         keep.push_back(r);
         continue;
       }
@@ -979,11 +1003,10 @@ static void serve_loop(bh_ctx* c) {
       }
       int vi = (int)vds.size();
       vds.push_back(vd);
-      int64_t take = std::min<int64_t>(r->tiles_total - r->tiles_next, maxtiles - (int64_t)items.size());
-      for (int64_t k = 0; k < take; ++k) {
-        int tt = r->tiles_next + (int)k;
-        items.push_back(WorkItem{vi, (tt % r->tiles_x) * tw, (tt / r->tiles_x) * th, 0});
-      }
+      int64_t take = std::min<int64_t>(r->tiles_total - r->tiles_next, maxtiles - ntiles);
+      runs.push_back(TileRun{vi, r->tiles_next, (int)ntiles, r->tiles_x});
+      in_launch.push_back(r->ticket);
+      ntiles += take;
       r->tiles_next += (int)take;
       if (r->tiles_next >= r->tiles_total)
         L.finishing.push_back(r->ticket);
@@ -991,26 +1014,33 @@ static void serve_loop(bh_ctx* c) {
         keep.push_back(r);
     }
     active.swap(keep);
-    if (items.empty()) {
+    if (ntiles == 0) {
       if (!L.finishing.empty()) finish_launch(c, L);
       continue;
     }
-    // device buffers of this slot
-    if (vcap[slot] < vds.size()) {
+    // device buffers of this slot (the slot's previous launch has finished: at most maxin
+    // launches are in flight and there are maxin + 1 slots)
+    if (dev_ok && rcap[slot] < vds.size()) {
       if (dviews[slot]) (void)hipFree(dviews[slot]);
-      vcap[slot] = std::max<size_t>(vds.size(), 256);
-      (void)hipMalloc(&dviews[slot], sizeof(ViewDev) * vcap[slot]);
+      if (druns[slot]) (void)hipFree(druns[slot]);
+      dviews[slot] = nullptr;
+      druns[slot] = nullptr;
+      rcap[slot] = 0;
+      size_t cap = std::max<size_t>(vds.size(), 256);
+      if (hipMalloc(&dviews[slot], sizeof(ViewDev) * cap) == hipSuccess &&
+          hipMalloc(&druns[slot], sizeof(TileRun) * cap) == hipSuccess)
+        rcap[slot] = cap;
+      else
+        dev_ok = false;
     }
-    if (icap[slot] < items.size()) {
-      if (ditems[slot]) (void)hipFree(ditems[slot]);
-      icap[slot] = std::max<size_t>(items.size(), (size_t)maxtiles);
-      (void)hipMalloc(&ditems[slot], sizeof(WorkItem) * icap[slot]);
-    }
-    bh_status st;
-    {
+    bh_status st = BH_EDEVICE;
+    if (dev_ok) {
       std::lock_guard<std::mutex> g(c->mu);
-      st = enqueue_batch(c, tables_dev(tb), vds, items, dviews[slot], ditems[slot], dcounter[slot],
-                         stg[slot], c->serve_stream, false);
+      st = enqueue_batch(c, tables_dev(tb), vds, runs, (int)ntiles, dviews[slot], druns[slot],
+                         dcounter[slot], stg[slot], c->serve_stream, false, copy_stream,
+                         slot_free[slot], copied[slot]);
+      if (st == BH_OK && hipEventRecord(slot_free[slot], c->serve_stream) != hipSuccess)
+        st = BH_EDEVICE;
     }
     if (evpool.empty()) {
       hipEvent_t ev;
@@ -1021,17 +1051,34 @@ static void serve_loop(bh_ctx* c) {
     evpool.pop_back();
     (void)hipEventRecord(L.ev, c->serve_stream);
     if (st != BH_OK) {
+      // every request with tiles in this launch fails; the unfinished ones stop here
       std::lock_guard<std::mutex> lk(c->smu);
-      for (uint64_t tk : L.finishing) c->reqs[tk]->status = BH_EDEVICE;
+      for (uint64_t tk : in_launch) {
+        ServeReq* r = c->reqs[tk];
+        r->status = st;
+        if (r->tiles_next < r->tiles_total) {
+          r->tiles_next = r->tiles_total;
+          L.finishing.push_back(tk);
+        }
+      }
+      active.erase(std::remove_if(active.begin(), active.end(),
+                                  [](ServeReq* r) { return r->status != BH_OK; }),
+                   active.end());
     }
     L.slot = slot;
     slot = (slot + 1) % (maxin + 1);
     inflight.push_back(L);
   }
   (void)hipStreamSynchronize(c->serve_stream);
+  if (copy_stream) {
+    (void)hipStreamSynchronize(copy_stream);
+    (void)hipStreamDestroy(copy_stream);
+  }
   for (int k = 0; k <= maxin; ++k) {
+    if (slot_free[k]) (void)hipEventDestroy(slot_free[k]);
+    if (copied[k]) (void)hipEventDestroy(copied[k]);
     if (dviews[k]) (void)hipFree(dviews[k]);
-    if (ditems[k]) (void)hipFree(ditems[k]);
+    if (druns[k]) (void)hipFree(druns[k]);
     if (dcounter[k]) (void)hipFree(dcounter[k]);
     if (stg[k].host) (void)hipHostFree(stg[k].host);
     if (stg[k].done) (void)hipEventDestroy(stg[k].done);
@@ -1044,10 +1091,25 @@ extern "C" bh_status bh_serve_start(bh_ctx* c, const bh_serve_params* p) {
   std::lock_guard<std::mutex> lk(c->smu);
   if (c->serving) return fail(BH_EINVAL, "serving already started");
   c->sp.max_queue = p && p->max_queue > 0 ? p->max_queue : 1 << 20;
-  c->sp.max_inflight_launches = p && p->max_inflight_launches > 0 ? p->max_inflight_launches : 2;
-  c->sp.max_tiles_per_launch = p && p->max_tiles_per_launch > 0 ? p->max_tiles_per_launch : 16384;
+  c->sp.max_inflight_launches = p && p->max_inflight_launches > 0 ? p->max_inflight_launches : 6;
+  c->sp.max_tiles_per_launch = p && p->max_tiles_per_launch > 0 ? p->max_tiles_per_launch : 262144;
   HIPCHK(hipSetDevice(c->device));
   HIPCHK(hipStreamCreateWithFlags(&c->serve_stream, hipStreamNonBlocking));
+  hipMemPoolProps props = {};
+  props.allocType = hipMemAllocationTypePinned;
+  props.location.type = hipMemLocationTypeDevice;
+  props.location.id = c->device;
+  hipError_t e = hipMemPoolCreate(&c->img_pool, &props);
+  if (e == hipSuccess) {
+    uint64_t keep = UINT64_MAX;  // released images stay reserved for the next allocations
+    e = hipMemPoolSetAttribute(c->img_pool, hipMemPoolAttrReleaseThreshold, &keep);
+  }
+  if (e != hipSuccess) {
+    if (c->img_pool) (void)hipMemPoolDestroy(c->img_pool);
+    c->img_pool = nullptr;
+    (void)hipStreamDestroy(c->serve_stream);
+    return fail(BH_EDEVICE, std::string("image pool: ") + hipGetErrorString(e));
+  }
   c->stop = false;
   c->serving = true;
   c->serve_thread = std::thread(serve_loop, c);
@@ -1069,15 +1131,24 @@ static void serve_stop(bh_ctx* c) {
   }
   c->scv.notify_all();
   c->serve_thread.join();
-  (void)hipStreamDestroy(c->serve_stream);
   c->serving = false;
   for (auto& kv : c->reqs) {
-    if (kv.second->owned) dev_free(c, kv.second->out, kv.second->out_bytes);
+    if (kv.second->owned) {
+      (void)hipFreeAsync(kv.second->out, c->serve_stream);
+      c->used -= kv.second->out_bytes;
+    }
     delete kv.second;
   }
   c->reqs.clear();
-  for (auto& kv : c->pool) dev_free(c, kv.second, kv.first);
+  for (auto& kv : c->pool) {
+    (void)hipFreeAsync(kv.second, c->serve_stream);
+    c->used -= kv.first;
+  }
   c->pool.clear();
+  (void)hipStreamSynchronize(c->serve_stream);
+  (void)hipMemPoolDestroy(c->img_pool);
+  c->img_pool = nullptr;
+  (void)hipStreamDestroy(c->serve_stream);
 }
 
 extern "C" bh_status bh_submit(bh_ctx* c, const bh_tables* t, const bh_view* v, float* out,

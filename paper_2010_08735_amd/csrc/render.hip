@@ -446,39 +446,62 @@ __global__ void __launch_bounds__((TW / 8) * (TH / 8) * 64 / PPT)
   render_tile<TW, TH, PPT>(v, T, L, (tile % tiles_x) * TW, (tile / tiles_x) * TH);
 }
 
-// Persistent launch over a work list of (view, tile) items from many views.
+// The run holding flat tile index `it` (wave-uniform): the last run whose start is <= it.
+__device__ __forceinline__ TileRun find_run(const TileRun* __restrict__ runs, int nruns,
+                                            int it) {
+  int lo = 0, hi = nruns - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (__builtin_amdgcn_readfirstlane(runs[mid].start) <= it)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  TileRun r = runs[lo];
+  r.view = __builtin_amdgcn_readfirstlane(r.view);
+  r.tile0 = __builtin_amdgcn_readfirstlane(r.tile0);
+  r.start = __builtin_amdgcn_readfirstlane(r.start);
+  r.tiles_x = __builtin_amdgcn_readfirstlane(r.tiles_x);
+  return r;
+}
+
+template <int TW, int TH, int PPT>
+__device__ __forceinline__ void render_flat_tile(const ViewDev* __restrict__ views,
+                                                 const TileRun* __restrict__ runs, int nruns,
+                                                 int it, const TablesDev& T, const LutDev& L) {
+  TileRun r = find_run(runs, nruns, it);
+  int tile = r.tile0 + (it - r.start);
+  ViewDev v = views[r.view];
+  render_tile<TW, TH, PPT>(v, T, L, (tile % r.tiles_x) * TW, (tile / r.tiles_x) * TH);
+}
+
+// Persistent launch over the tiles of many views: workgroups take flat tile indices from
+// an atomic counter until all ntiles are done.
 template <int TW, int TH, int PPT>
 __global__ void __launch_bounds__((TW / 8) * (TH / 8) * 64 / PPT)
-    k_render_batch(const ViewDev* __restrict__ views, const WorkItem* __restrict__ items,
-                   int nitems, int* __restrict__ counter, TablesDev T, LutDev L) {
+    k_render_batch(const ViewDev* __restrict__ views, const TileRun* __restrict__ runs,
+                   int nruns, int ntiles, int* __restrict__ counter, TablesDev T, LutDev L) {
   __shared__ int s_item;
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
     __syncthreads();
     int it = __builtin_amdgcn_readfirstlane(s_item);
     __syncthreads();
-    if (it >= nitems) break;
-    WorkItem w = items[it];
-    int vi = __builtin_amdgcn_readfirstlane(w.view);
-    int x0 = __builtin_amdgcn_readfirstlane(w.x0), y0 = __builtin_amdgcn_readfirstlane(w.y0);
-    ViewDev v = views[vi];
-    render_tile<TW, TH, PPT>(v, T, L, x0, y0);
+    if (it >= ntiles) break;
+    render_flat_tile<TW, TH, PPT>(views, runs, nruns, it, T, L);
   }
 }
 
-// Work list without persistence: one workgroup per (view, tile) item, XCD-aware order.
+// Tiles of many views without persistence: one workgroup per flat tile index, XCD-aware
+// order.
 template <int TW, int TH, int PPT>
 __global__ void __launch_bounds__((TW / 8) * (TH / 8) * 64 / PPT)
-    k_render_list(const ViewDev* __restrict__ views, const WorkItem* __restrict__ items,
-                  int nitems, int per_xcd, TablesDev T, LutDev L) {
+    k_render_list(const ViewDev* __restrict__ views, const TileRun* __restrict__ runs,
+                  int nruns, int ntiles, int per_xcd, TablesDev T, LutDev L) {
   int b = blockIdx.x;
   int it = (b & 7) * per_xcd + (b >> 3);
-  if (it >= nitems) return;
-  WorkItem w = items[it];
-  int vi = __builtin_amdgcn_readfirstlane(w.view);
-  int x0 = __builtin_amdgcn_readfirstlane(w.x0), y0 = __builtin_amdgcn_readfirstlane(w.y0);
-  ViewDev v = views[vi];
-  render_tile<TW, TH, PPT>(v, T, L, x0, y0);
+  if (it >= ntiles) return;
+  render_flat_tile<TW, TH, PPT>(views, runs, nruns, it, T, L);
 }
 
 __global__ void k_reset_counter(int* c) { *c = 0; }
@@ -521,9 +544,9 @@ __global__ void k_trace_rays(TablesDev T, const float* __restrict__ rays, int64_
 struct TileEntry {
   int tw, th, waves, ppt;
   void (*plain)(const ViewDev&, const TablesDev&, const LutDev&, hipStream_t);
-  void (*batch)(const ViewDev*, const WorkItem*, int, int*, const TablesDev&, const LutDev&,
-                int grid, hipStream_t);
-  void (*list)(const ViewDev*, const WorkItem*, int, const TablesDev&, const LutDev&,
+  void (*batch)(const ViewDev*, const TileRun*, int, int, int*, const TablesDev&,
+                const LutDev&, int grid, hipStream_t);
+  void (*list)(const ViewDev*, const TileRun*, int, int, const TablesDev&, const LutDev&,
                hipStream_t);
 };
 
@@ -538,21 +561,22 @@ static void launch_plain(const ViewDev& v, const TablesDev& T, const LutDev& L, 
 }
 
 template <int TW, int TH, int PPT>
-static void launch_batch(const ViewDev* views, const WorkItem* items, int nitems, int* counter,
-                         const TablesDev& T, const LutDev& L, int grid, hipStream_t s) {
+static void launch_batch(const ViewDev* views, const TileRun* runs, int nruns, int ntiles,
+                         int* counter, const TablesDev& T, const LutDev& L, int grid,
+                         hipStream_t s) {
   using C = TileCfg<TW, TH, PPT>;
   hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, counter);
   hipLaunchKernelGGL((k_render_batch<TW, TH, PPT>), dim3(grid), dim3(C::kThreads), 0, s, views,
-                     items, nitems, counter, T, L);
+                     runs, nruns, ntiles, counter, T, L);
 }
 
 template <int TW, int TH, int PPT>
-static void launch_list(const ViewDev* views, const WorkItem* items, int nitems,
+static void launch_list(const ViewDev* views, const TileRun* runs, int nruns, int ntiles,
                         const TablesDev& T, const LutDev& L, hipStream_t s) {
   using C = TileCfg<TW, TH, PPT>;
-  int per_xcd = (nitems + 7) / 8;
+  int per_xcd = (ntiles + 7) / 8;
   hipLaunchKernelGGL((k_render_list<TW, TH, PPT>), dim3(8 * per_xcd), dim3(C::kThreads), 0, s,
-                     views, items, nitems, per_xcd, T, L);
+                     views, runs, nruns, ntiles, per_xcd, T, L);
 }
 
 #define BH_TILE(TW, TH, PPT)                                                         \
@@ -578,15 +602,16 @@ hipError_t launch_render(int cfg, const ViewDev& v, const TablesDev& T, const Lu
   return hipGetLastError();
 }
 
-// persistent != 0: grid-stride persistent workgroups pulling items from an atomic counter;
-// otherwise one workgroup per item.
+// persistent != 0: `grid` persistent workgroups pulling tiles from an atomic counter;
+// otherwise one workgroup per tile.
 hipError_t launch_render_batch(int cfg, int persistent, const ViewDev* views,
-                               const WorkItem* items, int nitems, int* counter,
+                               const TileRun* runs, int nruns, int ntiles, int* counter,
                                const TablesDev& T, const LutDev& L, int grid, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
   if (persistent)
-    kTiles[cfg].batch(views, items, nitems, counter, T, L, grid, s);
+    kTiles[cfg].batch(views, runs, nruns, ntiles, counter, T, L, grid, s);
   else
-    kTiles[cfg].list(views, items, nitems, T, L, s);
+    kTiles[cfg].list(views, runs, nruns, ntiles, T, L, s);
   return hipGetLastError();
 }
 

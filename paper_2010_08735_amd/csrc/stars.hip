@@ -8,6 +8,8 @@
 // U = d_{(k+1)%3} / |d_k|, V = d_{(k+2)%3} / |d_k| in [-1, 1].
 // Stored texels: FP16 (I / scale_L, T / 1024, p_u, p_v) with a per-level power-of-two
 // scale chosen from the level's largest intensity, or FP32 (I, T, p_u, p_v).
+#include <algorithm>
+
 #include "bh_dev.h"
 
 namespace bh {
@@ -96,13 +98,23 @@ __global__ void k_star_mip(const float4* __restrict__ prev, float4* __restrict__
                     : make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
-__global__ void k_star_maxI(const float4* __restrict__ lvl, int64_t count,
-                            unsigned* __restrict__ maxbits) {
-  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  float v = t < count ? lvl[t].x : 0.0f;
-  // wave reduction then one atomic per wave (I >= 0, so float order == bit order)
+// Largest stored intensity of one level: grid-stride partial maxima, a wave then a
+// workgroup reduction, one atomic per workgroup (I >= 0, so float order == bit order).
+// Launched with 256 threads per workgroup.
+__global__ void __launch_bounds__(256)
+    k_star_maxI(const float4* __restrict__ lvl, int64_t count, unsigned* __restrict__ maxbits) {
+  __shared__ float wmax[4];
+  float v = 0.0f;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < count;
+       t += (int64_t)gridDim.x * blockDim.x)
+    v = fmaxf(v, lvl[t].x);
   for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
-  if ((threadIdx.x & 63) == 0 && v > 0.0f) atomicMax(maxbits, __float_as_uint(v));
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float m = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
+    if (m > 0.0f) atomicMax(maxbits, __float_as_uint(m));
+  }
 }
 
 __global__ void k_star_pack(const float4* __restrict__ lvl, int64_t count,
@@ -207,8 +219,9 @@ hipError_t launch_star_build(const float* dirs, const float* inten, const float*
   }
   for (int l = 0; l < levels; ++l) {
     int64_t cnt = 6LL * (n0 >> l) * (n0 >> l);
-    hipLaunchKernelGGL(k_star_maxI, dim3(blocks_for(cnt, B)), dim3(B), 0, s,
-                       master + level_off_host[l], cnt, maxbits + l);
+    unsigned grid = std::min(blocks_for(cnt, B), 2048u);
+    hipLaunchKernelGGL(k_star_maxI, dim3(grid), dim3(B), 0, s, master + level_off_host[l], cnt,
+                       maxbits + l);
   }
   hipLaunchKernelGGL(k_star_scales, dim3(1), dim3(64), 0, s, maxbits, levels, fp16, scale);
   size_t tsz = fp16 ? 8 : 16;
