@@ -23,13 +23,16 @@ class OrcView(C.Structure):
                 ("disc_r_in", C.c_double), ("disc_r_out", C.c_double),
                 ("disc_T_law", C.c_int32), ("pad0", C.c_int32),
                 ("disc_T0", C.c_double), ("disc_T_exp", C.c_double),
-                ("disc_opacity", C.c_double), ("k_disc", C.c_double), ("k_star", C.c_double)]
+                ("disc_opacity", C.c_double), ("k_disc", C.c_double), ("k_star", C.c_double),
+                ("time", C.c_double), ("disc_density", C.c_int32), ("n_particles", C.c_int32),
+                ("particles", C.POINTER(C.c_double))]
 
 
 class OrcRay(C.Structure):
     _fields_ = [("delta_prime", C.c_double), ("captured", C.c_int32), ("n_cross", C.c_int32),
                 ("u_cross", C.c_double * 4), ("phi_cross", C.c_double * 4),
-                ("branch", C.c_int32 * 4), ("steps", C.c_int32), ("pad0", C.c_int32)]
+                ("branch", C.c_int32 * 4), ("steps", C.c_int32), ("pad0", C.c_int32),
+                ("t_cross", C.c_double * 4)]
 
 
 PIXEL_DTYPE = np.dtype([
@@ -39,9 +42,17 @@ PIXEL_DTYPE = np.dtype([
     ("delta", "<f8"), ("alpha", "<f8"), ("zeta", "<f8"),
     ("x", "<i4"), ("y", "<i4"), ("n_cross", "<i4"), ("branch_bits", "<i4"),
     ("captured", "<i4"), ("star_zeroed", "<i4"), ("degenerate", "<i4"), ("mip_level", "<i4"),
+    ("pad0", "<i4"), ("pad1", "<i4"), ("t_ret", "<f8", 2), ("hit_az", "<f8", 2), ("density", "<f8", 2),
 ])
 
 _lib = None
+
+
+def _check_layout(L):
+    """The record layouts above must match the C structs byte for byte."""
+    if L.orc_sizeof_pixel() != PIXEL_DTYPE.itemsize or L.orc_sizeof_ray() != C.sizeof(OrcRay) \
+            or L.orc_sizeof_view() != C.sizeof(OrcView):
+        raise RuntimeError("oracle record layout mismatch")
 
 
 def lib():
@@ -73,6 +84,25 @@ def lib():
         L.orc_render_quads.argtypes = [C.POINTER(OrcView), dp, C.c_int32, dp, C.c_int32, dp,
                                        C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.c_int64,
                                        C.c_void_p, C.c_int]
+        L.orc_render_quads_t.argtypes = [C.POINTER(OrcView), dp, C.c_int32, dp, dp, C.c_int32,
+                                         dp, dp, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
+                                         C.c_int64, C.c_void_p, C.c_int]
+        L.orc_tables_time.argtypes = [C.c_int32, C.c_int32, C.c_int32, dp, dp, C.c_int]
+        L.orc_trace_table_t.argtypes = [dp, dp, C.c_int32, dp, dp, C.c_int32, C.c_int32] + \
+            [C.c_double] * 5 + [C.POINTER(OrcRay)]
+        L.orc_tau_in.restype = C.c_double
+        L.orc_tau_in.argtypes = [C.c_double, C.c_double]
+        L.orc_time_singular.restype = C.c_double
+        L.orc_time_singular.argtypes = [C.c_double]
+        L.orc_ellipk.restype = C.c_double
+        L.orc_ellipk.argtypes = [C.c_double]
+        L.orc_particle_u.restype = C.c_double
+        L.orc_particle_u.argtypes = [dp, C.c_double, C.c_double]
+        L.orc_disc_density.restype = C.c_double
+        L.orc_disc_density.argtypes = [dp, C.c_int32, C.c_double, C.c_double, C.c_double]
+        for f in ("orc_sizeof_pixel", "orc_sizeof_ray", "orc_sizeof_view"):
+            getattr(L, f).restype = C.c_int64
+        _check_layout(L)
         L.orc_quad_poly_check.restype = C.c_double
         L.orc_quad_poly_check.argtypes = [C.c_int]
         _lib = L
@@ -103,7 +133,8 @@ def _ray_dict(r: OrcRay):
     n = r.n_cross
     return {"delta_prime": r.delta_prime, "captured": bool(r.captured), "n_cross": n,
             "u": [r.u_cross[k] for k in range(n)], "phi": [r.phi_cross[k] for k in range(n)],
-            "branch": [r.branch[k] for k in range(n)], "steps": r.steps}
+            "branch": [r.branch[k] for k in range(n)], "steps": r.steps,
+            "t": [r.t_cross[k] for k in range(n)]}
 
 
 def trace_exact(u_c, delta, alpha, u_ic, u_oc, gr=1.0):
@@ -113,19 +144,53 @@ def trace_exact(u_c, delta, alpha, u_ic, u_oc, gr=1.0):
 
 
 class Tables:
-    def __init__(self, d_n=512, u_ne=64, u_nphi=32, nthreads=None):
+    """Quadrature tables at the texel centres; time=True also fills the regularised time
+    channels Dt, Ut (same layout)."""
+
+    def __init__(self, d_n=512, u_ne=64, u_nphi=32, nthreads=None, time=False):
         self.d_n, self.u_ne, self.u_nphi = d_n, u_ne, u_nphi
         self.D = np.zeros((d_n, d_n), np.float64)
         self.U = np.zeros((u_nphi, u_ne), np.float64)
         rc = lib().orc_tables(d_n, u_ne, u_nphi, _dp(self.D), _dp(self.U), nthreads or threads())
         if rc:
             raise ValueError("orc_tables failed")
+        self.Dt = self.Ut = None
+        if time:
+            self.Dt = np.zeros((d_n, d_n), np.float64)
+            self.Ut = np.zeros((u_nphi, u_ne), np.float64)
+            rc = lib().orc_tables_time(d_n, u_ne, u_nphi, _dp(self.Dt), _dp(self.Ut),
+                                       nthreads or threads())
+            if rc:
+                raise ValueError("orc_tables_time failed")
 
     def trace(self, u_c, delta, alpha, u_ic, u_oc):
         r = OrcRay()
-        lib().orc_trace_table(_dp(self.D), self.d_n, _dp(self.U), self.u_ne, self.u_nphi,
-                              u_c, delta, alpha, u_ic, u_oc, C.byref(r))
+        lib().orc_trace_table_t(_dp(self.D), _dp(self.Dt), self.d_n, _dp(self.U), _dp(self.Ut),
+                                self.u_ne, self.u_nphi, u_c, delta, alpha, u_ic, u_oc,
+                                C.byref(r))
         return _ray_dict(r)
+
+
+def tau_in(e2: float, u: float) -> float:
+    return lib().orc_tau_in(e2, u)
+
+
+def time_singular(u: float) -> float:
+    return lib().orc_time_singular(u)
+
+
+def ellipk(kappa: float) -> float:
+    return lib().orc_ellipk(kappa)
+
+
+def particle_u(particle, a: float, t: float) -> float:
+    p = np.ascontiguousarray(particle, np.float64)
+    return lib().orc_particle_u(_dp(p), a, t)
+
+
+def disc_density(particles, ht: float, hr: float, hphi: float) -> float:
+    p = np.ascontiguousarray(particles, np.float64).reshape(-1, 3)
+    return lib().orc_disc_density(_dp(p), len(p), ht, hr, hphi)
 
 
 def table_entry_D(n, i, j):
@@ -186,6 +251,14 @@ def to_orc_view(v) -> OrcView:
     o.disc_T_law = v.disc_T_law
     o.disc_T0, o.disc_T_exp = v.disc_T0, v.disc_T_exp
     o.disc_opacity, o.k_disc, o.k_star = v.disc_opacity, v.k_disc, v.k_star
+    o.time = getattr(v, "time", 0.0)
+    o.disc_density = getattr(v, "disc_density", 0)
+    parts = getattr(v, "particles", None)
+    if parts is not None:
+        arr = np.ascontiguousarray(parts.as_array(), np.float64).reshape(-1, 3)
+        o._keep = arr  # keeps the triples alive as long as the record
+        o.n_particles = len(arr)
+        o.particles = _dp(arr)
     return o
 
 
@@ -196,14 +269,15 @@ def render_quads(view, quads: np.ndarray, cube: np.ndarray = None, n0: int = 0,
     nq = q.shape[0]
     out = np.zeros(4 * nq, PIXEL_DTYPE)
     ov = to_orc_view(view)
-    D = U = None
+    D = U = Dt = Ut = None
     dn = une = unphi = 0
     if tables is not None:
         D, U, dn, une, unphi = tables.D, tables.U, tables.d_n, tables.u_ne, tables.u_nphi
-    rc = lib().orc_render_quads(C.byref(ov), _dp(cube) if cube is not None else None, n0,
-                                _dp(D), dn, _dp(U), une, unphi,
-                                q.ctypes.data_as(C.POINTER(C.c_int32)), nq,
-                                out.ctypes.data, nthreads or threads())
+        Dt, Ut = tables.Dt, tables.Ut
+    rc = lib().orc_render_quads_t(C.byref(ov), _dp(cube) if cube is not None else None, n0,
+                                  _dp(D), _dp(Dt), dn, _dp(U), _dp(Ut), une, unphi,
+                                  q.ctypes.data_as(C.POINTER(C.c_int32)), nq,
+                                  out.ctypes.data, nthreads or threads())
     if rc:
         raise ValueError("orc_render_quads rejected the view")
     return out

@@ -44,6 +44,11 @@ typedef struct {
   int32_t pad0;
   double disc_T0, disc_T_exp;
   double disc_opacity, k_disc, k_star;
+  /* animated disc (Appendix B): disc_density 0 = uniform, 1 = particles */
+  double time;            /* the camera's coordinate time */
+  int32_t disc_density;
+  int32_t n_particles;
+  const double* particles;  /* n_particles triples (r_peri, r_apo, phi0) */
 } orc_view;
 
 /* Result of tracing one ray in its orbital plane. */
@@ -56,6 +61,8 @@ typedef struct {
   int32_t branch[4];      /* 0: before the apsis of the backward ray, 1: after it       */
   int32_t steps;          /* accepted integrator steps (exact mode), 0 in table mode    */
   int32_t pad0;
+  double t_cross[4];      /* retarded time: coordinate time from the crossing to the
+                             camera (exact mode; table mode with time channels)          */
 } orc_ray;
 
 /* One rendered pixel with the diagnostics the parity mask needs. */
@@ -78,6 +85,10 @@ typedef struct {
   int32_t star_zeroed;    /* a member of the 2x2 quad is captured */
   int32_t degenerate;     /* ray radial or ray plane == disc plane */
   int32_t mip_level;      /* -1 if no gather happened */
+  int32_t pad0, pad1;
+  double t_ret[2];        /* retarded time of each crossing (animated disc only) */
+  double hit_az[2];       /* disc azimuth of each crossing (animated disc only) */
+  double density[2];      /* particle density at each crossing (animated disc only) */
 } orc_pixel;
 
 /* ---- geometry of rays (Section 3.3.1) --------------------------------------------- */
@@ -94,6 +105,14 @@ int orc_table_entry_U(int32_t u_ne, int32_t u_nphi, int32_t i, int32_t j, double
                       double* e2, double* phi);
 int orc_trace_table(const double* D, int32_t d_n, const double* U, int32_t u_ne, int32_t u_nphi,
                     double u_c, double delta, double alpha, double u_ic, double u_oc, orc_ray* out);
+/* time channels (regularised time tau at the same texel centres) and TraceRay with them */
+int orc_tables_time(int32_t d_n, int32_t u_ne, int32_t u_nphi, double* Dt, double* Ut,
+                    int nthreads);
+int orc_trace_table_t(const double* D, const double* Dt, int32_t d_n, const double* U,
+                      const double* Ut, int32_t u_ne, int32_t u_nphi, double u_c, double delta,
+                      double alpha, double u_ic, double u_oc, orc_ray* out);
+double orc_tau_in(double e2, double u);              /* tau on the incoming branch */
+double orc_time_singular(double u);                  /* S(u) = ln(u/(1-u)) - 1/u */
 
 /* ---- emission (Sections 3.3.3, 3.4.2) ----------------------------------------------- */
 void orc_band_radiance(double T, double out[3]);     /* R, G, B box bands, W m^-2 sr^-1 */
@@ -112,6 +131,22 @@ int orc_render_quads(const orc_view* v, const double* cubemap, int32_t n0,
                      const double* D, int32_t d_n, const double* U, int32_t u_ne,
                      int32_t u_nphi, const int32_t* quads, int64_t nq, orc_pixel* out,
                      int nthreads);
+/* the same with time channels (table mode of an animated disc needs Dt and Ut) */
+int orc_render_quads_t(const orc_view* v, const double* cubemap, int32_t n0,
+                       const double* D, const double* Dt, int32_t d_n, const double* U,
+                       const double* Ut, int32_t u_ne, int32_t u_nphi, const int32_t* quads,
+                       int64_t nq, orc_pixel* out, int nthreads);
+
+/* ---- animated disc (Appendix B) ------------------------------------------------------- */
+double orc_ellipk(double kappa);                     /* complete elliptic integral K */
+double orc_particle_u(const double* particle, double a, double t);
+double orc_disc_density(const double* particles, int32_t n, double ht, double hr,
+                        double hphi);
+
+/* record sizes (layout check of the Python front end) */
+int64_t orc_sizeof_pixel(void);
+int64_t orc_sizeof_ray(void);
+int64_t orc_sizeof_view(void);
 
 /* quadrature helper exposed for its own pin (Gauss-Legendre exactness) */
 double orc_quad_poly_check(int degree);

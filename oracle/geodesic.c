@@ -14,6 +14,11 @@
  * disc-plane angles are hit exactly by clipping the step; the escape point is located by
  * Newton iteration on the step length.  gr = 0 drops the 3/2 u^2 term (flat space), which
  * reduces rays to straight lines u = u_c sin(delta - phi) / sin(delta).
+ *
+ * Coordinate time rides along as a quadrature, dt/dphi = e / (u^2 (1 - u)) (the motion
+ * constants of Section 3.1; Algorithm 1 Precompute integrates the same rate), so each
+ * crossing also carries the time the light takes from it to the camera.  In flat space
+ * the rate is e / u^2, the distance travelled along the straight line.
  */
 #include <math.h>
 #include <string.h>
@@ -36,10 +41,14 @@ static const double E1 = 35.0 / 384.0 - 5179.0 / 57600.0, E3 = 500.0 / 1113.0 - 
                     E6 = 11.0 / 84.0 - 187.0 / 2100.0, E7 = -1.0 / 40.0;
 
 static inline double accel(double u, double gr) { return gr * 1.5 * u * u - u; }
+static inline double trate(double u, double e, double gr) {
+  return e / (u * u * (1.0 - gr * u));
+}
 
-/* one step of size h from (u, w); returns the 5th-order state and the error estimate */
-static void dopri(double u, double w, double h, double gr, double* u5, double* w5,
-                  double* eu, double* ew) {
+/* one step of size h from (u, w); returns the 5th-order state and the error estimate,
+ * and the increment of the coordinate time (5th order) in *dt */
+static void dopri(double u, double w, double h, double gr, double e, double* u5, double* w5,
+                  double* eu, double* ew, double* dt) {
   double k1u = w, k1w = accel(u, gr);
   double u2 = u + h * (A21 * k1u), w2 = w + h * (A21 * k1w);
   double k2u = w2, k2w = accel(u2, gr);
@@ -57,6 +66,9 @@ static void dopri(double u, double w, double h, double gr, double* u5, double* w
   double un = u + h * (B1 * k1u + B3 * k3u + B4 * k4u + B5 * k5u + B6 * k6u);
   double wn = w + h * (B1 * k1w + B3 * k3w + B4 * k4w + B5 * k5w + B6 * k6w);
   double k7u = wn, k7w = accel(un, gr);
+  if (dt)
+    *dt = h * (B1 * trate(u, e, gr) + B3 * trate(u3, e, gr) + B4 * trate(u4, e, gr) +
+               B5 * trate(uu5, e, gr) + B6 * trate(u6, e, gr));
   *u5 = un;
   *w5 = wn;
   *eu = h * (E1 * k1u + E3 * k3u + E4 * k4u + E5 * k5u + E6 * k6u + E7 * k7u);
@@ -69,11 +81,12 @@ static void dopri(double u, double w, double h, double gr, double* u5, double* w
 void orc_integrate_ray(double u0, double w0, double alpha, double u_ic, double u_oc,
                        double gr, orc_ray* o) {
   memset(o, 0, sizeof(*o));
-  double u = u0, w = w0, phi = 0.0;
+  double u = u0, w = w0, phi = 0.0, t = 0.0;
   double h = 1e-3 / (1.0 + fabs(w0));
   /* u and du/dphi are bounded by the invariant e = sqrt(w^2 + u^2 (1-u)) away from the
    * horizon, so tolerances scale with it (weak-field rays far away have tiny u) */
-  double escale = sqrt(w0 * w0 + u0 * u0 * fabs(1.0 - u0));
+  double escale = sqrt(w0 * w0 + u0 * u0 * fabs(1.0 - gr * u0));
+  const double e_inv = escale;  /* the ray's invariant e, rate of the coordinate time */
   if (!(escale > 0.0)) escale = 1.0;
   const double atol = ATOL_REL * fmin(escale, 1.0);
   int passed_apsis = 0;
@@ -97,8 +110,8 @@ void orc_integrate_ray(double u0, double w0, double alpha, double u_ic, double u
       hh = phi_d - phi;
       hit_disc = 1;
     }
-    double un, wn, eu, ew;
-    dopri(u, w, hh, gr, &un, &wn, &eu, &ew);
+    double un, wn, eu, ew, dtn;
+    dopri(u, w, hh, gr, e_inv, &un, &wn, &eu, &ew, &dtn);
     double su = atol + RTOL * fmax(fabs(u), fabs(un));
     double sw = atol + RTOL * fmax(fabs(w), fabs(wn));
     double err = fmax(fabs(eu) / su, fabs(ew) / sw);
@@ -114,7 +127,7 @@ void orc_integrate_ray(double u0, double w0, double alpha, double u_ic, double u
       double s = hh * u / (u - un);
       for (int it = 0; it < 60; ++it) {
         double us, ws, e1, e2;
-        dopri(u, w, s, gr, &us, &ws, &e1, &e2);
+        dopri(u, w, s, gr, e_inv, &us, &ws, &e1, &e2, NULL);
         double ds = us / ws;
         s -= ds;
         if (fabs(ds) < 1e-16 * (1.0 + s)) break;
@@ -128,12 +141,14 @@ void orc_integrate_ray(double u0, double w0, double alpha, double u_ic, double u
     if (w >= 0.0 && wn < 0.0) passed_apsis = 1;
     u = un;
     w = wn;
+    t += dtn;
     o->steps++;
     if (hit_disc) {
       if (u >= u_oc && u <= u_ic && o->n_cross < 4) {
         o->u_cross[o->n_cross] = u;
         o->phi_cross[o->n_cross] = phi;
         o->branch[o->n_cross] = passed_apsis;
+        o->t_cross[o->n_cross] = t;
         o->n_cross++;
       }
       ++m;

@@ -24,6 +24,10 @@
  *   (1-u)^-1/2 times the special-relativistic Doppler factor, g(k, l) with k = e_tau);
  *   D = D_cam / emitter factor; received band radiance k_disc * L_b(D T').
  *   Front-to-back composite with opacity rho (reading; the paper does not say).
+ *   Animated disc (Appendix B): the crossing at beam-plane angle psi (from e_x' towards
+ *   e_y') sits in direction cos(psi) e_x' + sin(psi) e_y', whose azimuth about e_z is h^phi;
+ *   h^r = 1/u', h^t = camera time - retarded time; the crossing's opacity is
+ *   min(1, rho * density(h)) (reading: the density scales the opaque layer).
  *
  * Stars (Section 3.3.2 filtering, Section 3.4.1 lensing): fine 2x2-quad differences give
  *   d_w X = X(x0+1, y) - X(x0, y), d_h X = X(x, y0+1) - X(x, y0) for X = d' and X = q
@@ -86,6 +90,7 @@ typedef struct {
   int captured, degenerate;
   double dprime[3];
   double q[3];
+  double ey[3];
   double e2, zeta, d_cam, delta, alpha;
   orc_ray ray;
 } ray_out;
@@ -95,7 +100,7 @@ typedef struct {
   vsetup s;
   const double* cube;
   int32_t n0, nl;
-  const double *D, *U;
+  const double *D, *U, *Dt, *Ut;
   int32_t d_n, u_ne, u_nphi;
 } ctx_t;
 
@@ -139,6 +144,7 @@ static void trace_pixel(const ctx_t* c, int32_t x, int32_t y, ray_out* o) {
   }
   double ez[3] = {cz[0] / ncz, cz[1] / ncz, cz[2] / ncz}, ey[3];
   cross3(ez, s->rhat, ey);
+  for (int i = 0; i < 3; ++i) o->ey[i] = ey[i];
   double t[3] = {-ez[1], ez[0], 0.0}; /* e_z x e_z' */
   double nt = norm3(t);
   double alpha = 0.0;
@@ -161,8 +167,8 @@ static void trace_pixel(const ctx_t* c, int32_t x, int32_t y, ray_out* o) {
   double cot = dot3(s->rhat, d) / ncz;
   o->e2 = s->u_c * s->u_c * cot * cot + s->u_c * s->u_c * (1.0 - s->u_c);
   if (c->D)
-    orc_trace_table(c->D, c->d_n, c->U, c->u_ne, c->u_nphi, s->u_c, delta, alpha, u_ic, u_oc,
-                    &o->ray);
+    orc_trace_table_t(c->D, c->Dt, c->d_n, c->U, c->Ut, c->u_ne, c->u_nphi, s->u_c, delta,
+                      alpha, u_ic, u_oc, &o->ray);
   else
     orc_trace_exact(s->u_c, delta, alpha, u_ic, u_oc, 1.0, &o->ray);
   o->captured = o->ray.captured;
@@ -273,8 +279,22 @@ static void shade_quad(const ctx_t* c, int32_t x0, int32_t y0, orc_pixel* out) {
       double D = o->d_cam / (kt * (1.0 + om * o->zeta / e));
       double L[3];
       orc_band_radiance(D * Tp, L);
-      for (int b = 0; b < 3; ++b) p->disc_rgb[b] += trans * rho * v->k_disc * L[b];
-      trans *= 1.0 - rho;
+      double rk = rho;
+      if (v->disc_density == 1) {
+        double psi = o->ray.phi_cross[k], P[3];
+        for (int i = 0; i < 3; ++i) P[i] = cos(psi) * c->s.rhat[i] + sin(psi) * o->ey[i];
+        double hphi = atan2(P[1], P[0]);
+        double ht = v->time - o->ray.t_cross[k];
+        double dens = orc_disc_density(v->particles, v->n_particles, ht, 1.0 / u, hphi);
+        rk = fmin(1.0, rho * dens);
+        if (k < 2) {
+          p->t_ret[k] = o->ray.t_cross[k];
+          p->hit_az[k] = hphi;
+          p->density[k] = dens;
+        }
+      }
+      for (int b = 0; b < 3; ++b) p->disc_rgb[b] += trans * rk * v->k_disc * L[b];
+      trans *= 1.0 - rk;
     }
     /* stars */
     p->star_zeroed = any_captured;
@@ -338,7 +358,18 @@ static void* rworker(void* p) {
 int orc_render_quads(const orc_view* v, const double* cube, int32_t n0, const double* D,
                      int32_t d_n, const double* U, int32_t u_ne, int32_t u_nphi,
                      const int32_t* quads, int64_t nq, orc_pixel* out, int nthreads) {
+  return orc_render_quads_t(v, cube, n0, D, NULL, d_n, U, NULL, u_ne, u_nphi, quads, nq, out,
+                            nthreads);
+}
+
+int orc_render_quads_t(const orc_view* v, const double* cube, int32_t n0, const double* D,
+                       const double* Dt, int32_t d_n, const double* U, const double* Ut,
+                       int32_t u_ne, int32_t u_nphi, const int32_t* quads, int64_t nq,
+                       orc_pixel* out, int nthreads) {
   if (!(v->r_s > 0) || v->width < 1 || v->height < 1) return 1;
+  if (v->disc_density == 1 && (v->n_particles < 0 || (v->n_particles > 0 && !v->particles) ||
+                               (D && (!Dt || !Ut))))
+    return 1;
   ctx_t c;
   memset(&c, 0, sizeof(c));
   c.v = v;
@@ -351,6 +382,8 @@ int orc_render_quads(const orc_view* v, const double* cube, int32_t n0, const do
     while ((n0 >> c.nl) >= 1) ++c.nl;
   c.D = D;
   c.U = U;
+  c.Dt = Dt;
+  c.Ut = Ut;
   c.d_n = d_n;
   c.u_ne = u_ne;
   c.u_nphi = u_nphi;
@@ -362,3 +395,8 @@ int orc_render_quads(const orc_view* v, const double* cube, int32_t n0, const do
   for (int t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
   return 0;
 }
+
+/* record sizes, so the Python front end can check its layouts */
+int64_t orc_sizeof_pixel(void) { return (int64_t)sizeof(orc_pixel); }
+int64_t orc_sizeof_ray(void) { return (int64_t)sizeof(orc_ray); }
+int64_t orc_sizeof_view(void) { return (int64_t)sizeof(orc_view); }

@@ -23,6 +23,20 @@
  *
  * Layout: D[j * d_n + i] (row j: u coordinate, column i: e coordinate),
  *         U[j * u_ne + i] (row j: phi coordinate, column i: e coordinate).
+ *
+ * Time channels (Algorithm 1 Precompute stores t beside D and U, with dt/dphi =
+ * e / (u^2 - u^3), Section 3.3.3 "Intersections").  On a ray from infinity t diverges, and
+ * only differences along one ray are used.  With w = |du/dphi| = sqrt(e^2 - u^2 (1 - u)):
+ *   dt/du = e / (u^2 (1 - u) w) = 1 / (w (e + w)) + S'(u),  S(u) = ln(u / (1 - u)) - 1/u,
+ * (because 1/u^2 + 1/u + 1/(1 - u) = 1 / (u^2 (1 - u)) and e - w = u^2 (1 - u) / (e + w)),
+ * so t = tau + S(u) + const with the finite regularised time
+ *   tau(u) = integral_0^u dv / (w (e + w))                      (incoming branch).
+ * tau grows like 1/e for small e (tau ~ tan(phi/2) / e on a nearly straight ray), so the
+ * tables hold e tau, which stays finite on the e -> 0 edge of U and interpolates well
+ * (reading: the paper stores t itself).  Dt and Ut hold e tau at the same texel centres
+ * as D and U.  Past the apsis (U only), t = 2 t_a - t_in(u) gives
+ * tau = 2 tau_a + 2 S(u_a) - tau_in(u) - 2 S(u).  On the e = 0 column of U the limit is
+ * tan(phi/2) before the apsis (phi = pi/2) and 2/sin(phi) - cot(phi/2) after it.
  */
 #include <math.h>
 #include <pthread.h>
@@ -83,6 +97,52 @@ static double hi_phi_between(double e2, double a, double b) {
   return orc_integrate(hi_integrand, &k, a, b, QTOL);
 }
 
+/* ---- regularised time tau ----------------------------------------------------------------- */
+typedef struct { lo_ctx k; double e; } lo_tctx;
+
+static double lo_tau_integrand(double s, void* c) {
+  const lo_tctx* q = (const lo_tctx*)c;
+  return lo_integrand(s, (void*)&q->k) / (q->e + lo_udot(&q->k, s));
+}
+
+/* tau between s and s_prev (s < s_prev) on the incoming branch, e^2 < mu */
+static double lo_tau_between(const lo_tctx* q, double s, double s_prev) {
+  return orc_integrate(lo_tau_integrand, (void*)q, s, s_prev, QTOL);
+}
+
+static double hi_tau_integrand(double v, void* c) {
+  double e2 = ((const hi_ctx*)c)->e2;
+  double w = sqrt(e2 - v * v * (1.0 - v));
+  return 1.0 / (w * (sqrt(e2) + w));
+}
+
+static double hi_tau_between(double e2, double a, double b) {
+  hi_ctx k = {e2};
+  const double ps = 2.0 / 3.0;
+  if (a < ps && b > ps)
+    return orc_integrate(hi_tau_integrand, &k, a, ps, QTOL) +
+           orc_integrate(hi_tau_integrand, &k, ps, b, QTOL);
+  return orc_integrate(hi_tau_integrand, &k, a, b, QTOL);
+}
+
+/* singular part of the time along a ray: t = tau + S(u) + const */
+double orc_time_singular(double u) { return log(u / (1.0 - u)) - 1.0 / u; }
+
+/* tau(u) on the incoming branch of the ray with invariant e^2 (0 <= u, below the apsis
+ * when e^2 < mu) */
+double orc_tau_in(double e2, double u) {
+  if (!(u > 0.0)) return 0.0;
+  if (e2 < ORC_MU) {
+    lo_tctx q;
+    cubic_roots(e2, &q.k.ua, &q.k.u2, &q.k.u3);
+    q.e = sqrt(e2);
+    double r = 1.0 - u / q.k.ua;
+    double s = r > 0.0 ? sqrt(r) : 0.0;
+    return lo_tau_between(&q, s, 1.0);
+  }
+  return hi_tau_between(e2, 0.0, u);
+}
+
 /* ---- texel centres ---------------------------------------------------------------------- */
 static double d_col_e2(int32_t n, int32_t i) {
   double x = (double)i / (n - 1);
@@ -131,6 +191,31 @@ static void fill_D_column(int32_t n, int32_t i, double* D) {
   }
 }
 
+/* one column of Dt (tau at the D texel centres) */
+static void fill_Dt_column(int32_t n, int32_t i, double* Dt) {
+  double e2 = d_col_e2(n, i);
+  if (i < n / 2) {
+    lo_tctx q;
+    cubic_roots(e2, &q.k.ua, &q.k.u2, &q.k.u3);
+    q.e = sqrt(e2);
+    double tau = 0.0, s_prev = 1.0;
+    for (int32_t j = 0; j < n; ++j) {
+      double s = 1.0 - (double)j / (n - 1);
+      tau += lo_tau_between(&q, s, s_prev);
+      s_prev = s;
+      Dt[(size_t)j * n + i] = q.e * tau;
+    }
+  } else {
+    double tau = 0.0, u_prev = 0.0;
+    for (int32_t j = 0; j < n; ++j) {
+      double u = d_row_u_hi(n, j); /* the last row is the horizon u = 1: tau stays finite */
+      tau += hi_tau_between(e2, u_prev, u);
+      u_prev = u;
+      Dt[(size_t)j * n + i] = sqrt(e2) * tau;
+    }
+  }
+}
+
 /* u on a ray from infinity at rotated angle phi_t (0 <= phi_t < pi) */
 static double u_at_phi(double e2, double phi_t) {
   if (e2 < ORC_MU) {
@@ -157,6 +242,35 @@ static double u_at_phi(double e2, double phi_t) {
   return 0.5 * (lo + hi);
 }
 
+/* tau at the U texel (i, j): on the incoming branch tau_in(u(phi)); past the apsis the
+ * reflection formula; 0 on the e -> infinity and e = 0 columns and after a fall-in */
+static double ut_entry(int32_t ne, int32_t nphi, int32_t i, int32_t j) {
+  double y = (double)j / (nphi - 1);
+  if (i == 0) return 0.0;       /* e -> infinity: e tau ~ u / (2 e) -> 0 */
+  if (i == ne - 1) {            /* e -> 0: phi = 3 y */
+    double phi = 3.0 * y;
+    if (phi <= 0.5 * M_PI) return tan(0.5 * phi);
+    return 2.0 / sin(phi) - 1.0 / tan(0.5 * phi);
+  }
+  double e2 = u_col_e2(ne, i);
+  double e = sqrt(e2);
+  double phi = 3.0 * y * (1.0 + e2) / (1.0 + 6.0 * e2 * e);
+  double u = u_at_phi(e2, phi);
+  if (e2 < ORC_MU) {
+    lo_ctx k;
+    cubic_roots(e2, &k.ua, &k.u2, &k.u3);
+    double phi_a = lo_phi(&k, 0.0);
+    if (phi > phi_a) {
+      double tau_a = orc_tau_in(e2, k.ua);
+      return e * (2.0 * tau_a + 2.0 * orc_time_singular(k.ua) - orc_tau_in(e2, u) -
+                  2.0 * orc_time_singular(u));
+    }
+    return e * orc_tau_in(e2, u);
+  }
+  if (u >= 1.0) return 0.0;
+  return e * orc_tau_in(e2, u);
+}
+
 static double u_entry(int32_t ne, int32_t nphi, int32_t i, int32_t j, double* e2o,
                       double* phio) {
   double y = (double)j / (nphi - 1);
@@ -179,6 +293,7 @@ typedef struct {
   double *D, *U;
   int next;
   pthread_mutex_t mu;
+  int time;  /* fill tau (Dt, Ut) instead of D, U */
 } tab_job;
 
 static void* tab_worker(void* p) {
@@ -190,12 +305,16 @@ static void* tab_worker(void* p) {
     pthread_mutex_unlock(&jb->mu);
     if (c >= total) break;
     if (jb->D && c < jb->d_n) {
-      fill_D_column(jb->d_n, c, jb->D);
+      if (jb->time)
+        fill_Dt_column(jb->d_n, c, jb->D);
+      else
+        fill_D_column(jb->d_n, c, jb->D);
     } else {
       int i = c - (jb->D ? jb->d_n : 0);
       for (int32_t j = 0; j < jb->u_nphi; ++j) {
         double e2, phi;
-        jb->U[(size_t)j * jb->u_ne + i] = u_entry(jb->u_ne, jb->u_nphi, i, j, &e2, &phi);
+        jb->U[(size_t)j * jb->u_ne + i] = jb->time ? ut_entry(jb->u_ne, jb->u_nphi, i, j)
+                                                   : u_entry(jb->u_ne, jb->u_nphi, i, j, &e2, &phi);
       }
     }
   }
@@ -206,7 +325,19 @@ int orc_tables(int32_t d_n, int32_t u_ne, int32_t u_nphi, double* D, double* U, 
   if ((D && (d_n < 4 || d_n % 2)) || (U && (u_ne < 2 || u_nphi < 2))) return 1;
   if (nthreads < 1) nthreads = 1;
   if (nthreads > 256) nthreads = 256;
-  tab_job jb = {d_n, u_ne, u_nphi, D, U, 0, PTHREAD_MUTEX_INITIALIZER};
+  tab_job jb = {d_n, u_ne, u_nphi, D, U, 0, PTHREAD_MUTEX_INITIALIZER, 0};
+  pthread_t th[256];
+  for (int t = 0; t < nthreads; ++t) pthread_create(&th[t], NULL, tab_worker, &jb);
+  for (int t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
+  return 0;
+}
+
+int orc_tables_time(int32_t d_n, int32_t u_ne, int32_t u_nphi, double* Dt, double* Ut,
+                    int nthreads) {
+  if ((Dt && (d_n < 4 || d_n % 2)) || (Ut && (u_ne < 2 || u_nphi < 2))) return 1;
+  if (nthreads < 1) nthreads = 1;
+  if (nthreads > 256) nthreads = 256;
+  tab_job jb = {d_n, u_ne, u_nphi, Dt, Ut, 0, PTHREAD_MUTEX_INITIALIZER, 1};
   pthread_t th[256];
   for (int t = 0; t < nthreads; ++t) pthread_create(&th[t], NULL, tab_worker, &jb);
   for (int t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
@@ -282,9 +413,13 @@ static double lookup_U(const double* U, int32_t ne, int32_t nphi, double e2, dou
 
 static double fmod_floor(double a, double m) { return a - m * floor(a / m); }
 
-int orc_trace_table(const double* D, int32_t n, const double* U, int32_t ne, int32_t nphi,
-                    double u, double delta, double alpha, double u_ic, double u_oc,
-                    orc_ray* o) {
+/* TraceRay with the time channels (Dt, Ut may be NULL: no times).  The retarded time of a
+ * crossing is the coordinate time the light takes from the crossing to the camera:
+ * crossing 0: s (t_0 - t), crossing 1: 2 t_a - t - t_1 (Algorithm 1), with t = tau + S(u)
+ * read from the tables at the camera (t), the apsis (t_a) and the crossings. */
+int orc_trace_table_t(const double* D, const double* Dt, int32_t n, const double* U,
+                      const double* Ut, int32_t ne, int32_t nphi, double u, double delta,
+                      double alpha, double u_ic, double u_oc, orc_ray* o) {
   memset(o, 0, sizeof(*o));
   double udot = -u * cos(delta) / sin(delta);
   double e2 = udot * udot + u * u * (1.0 - u);
@@ -301,6 +436,13 @@ int orc_trace_table(const double* D, int32_t n, const double* U, int32_t ne, int
     Da = lookup_D(D, n, e2, ua, ua);
     phi_a = Da + M_PI / 2.0;
   }
+  /* times at the camera and the apsis on the incoming branch */
+  double t_cam = 0.0, t_a = 0.0;
+  const double ie = 1.0 / sqrt(e2);  /* the tables hold e tau */
+  if (Dt) {
+    t_cam = lookup_D(Dt, n, e2, u, ua) * ie + orc_time_singular(u);
+    if (e2 < ORC_MU) t_a = lookup_D(Dt, n, e2, ua, ua) * ie + orc_time_singular(ua);
+  }
   double phi = Dl + (s == 1 ? M_PI - delta : delta) + s * alpha;
   double phi0 = fmod_floor(phi, M_PI);
   double u0 = lookup_U(U, ne, nphi, e2, phi0);
@@ -309,6 +451,8 @@ int orc_trace_table(const double* D, int32_t n, const double* U, int32_t ne, int
     o->u_cross[o->n_cross] = u0;
     o->phi_cross[o->n_cross] = alpha + phi - phi0;
     o->branch[o->n_cross] = 0;
+    if (Ut) o->t_cross[o->n_cross] = s * (lookup_U(Ut, ne, nphi, e2, phi0) * ie +
+                                          orc_time_singular(u0) - t_cam);
     o->n_cross++;
   }
   if (e2 < ORC_MU && s == 1) {
@@ -319,6 +463,9 @@ int orc_trace_table(const double* D, int32_t n, const double* U, int32_t ne, int
       o->u_cross[o->n_cross] = u1;
       o->phi_cross[o->n_cross] = alpha + phi - phi1;
       o->branch[o->n_cross] = 1;
+      if (Ut) o->t_cross[o->n_cross] = 2.0 * t_a - t_cam -
+                                       (lookup_U(Ut, ne, nphi, e2, phi1) * ie +
+                                        orc_time_singular(u1));
       o->n_cross++;
     }
   }
@@ -334,4 +481,10 @@ int orc_trace_table(const double* D, int32_t n, const double* U, int32_t ne, int
   }
   o->delta_prime = delta + Dl2;
   return 0;
+}
+
+int orc_trace_table(const double* D, int32_t n, const double* U, int32_t ne, int32_t nphi,
+                    double u, double delta, double alpha, double u_ic, double u_oc,
+                    orc_ray* o) {
+  return orc_trace_table_t(D, NULL, n, U, NULL, ne, nphi, u, delta, alpha, u_ic, u_oc, o);
 }

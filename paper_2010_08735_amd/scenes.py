@@ -13,18 +13,23 @@ Input recipes (all RNG draws use numpy's PCG64 ``default_rng(seed)`` in the orde
   temperature ~ U(3000, 12000) K, each drawn as a whole array in that order;
 * camera orientation: the camera looks at the apparent direction of the hole centre
   (the hole direction carried from the static frame into the moving camera's frame), with
-  the image "up" axis the projection of +z (or +x when the camera looks along z).
+  the image "up" axis the projection of +z (or +x when the camera looks along z);
+* disc particles (animated disc): mid radius ~ U(r_in + 1, r_out - 1), relative
+  half-width of the radial excursion ~ U(0, 0.05), initial phase ~ U(0, 2 pi), each drawn
+  as a whole array in that order; pericentre = mid (1 - w), apocentre = mid (1 + w).
 """
 from __future__ import annotations
 
 import dataclasses
 import math
-from typing import List, Sequence, Tuple
+from typing import List, Optional, Sequence, Tuple
 
 import numpy as np
 
 T_LAW_POWER = 0   # T' = T0 * (r' / (3 r_s)) ** T_exp
 T_LAW_PAPER = 1   # T'^4 proportional to u^3 (1 - sqrt(3u)), peak value T0
+DENSITY_UNIFORM = 0
+DENSITY_PARTICLES = 1
 
 
 @dataclasses.dataclass
@@ -45,9 +50,38 @@ class View:
     disc_opacity: float = 1.0
     k_disc: float = 1.0e-7
     k_star: float = 1.0
+    # animated disc: 0 = uniform density, 1 = procedural particles at the camera time
+    disc_density: int = DENSITY_UNIFORM
+    time: float = 0.0
+    particles: Optional["ParticleSet"] = None
 
     def pixels(self) -> int:
         return self.width * self.height
+
+
+@dataclasses.dataclass
+class ParticleSet:
+    """Disc particles: pericentre and apocentre radii (units of r_s) and initial phase
+    (radians), float64 arrays of equal length."""
+    r_peri: np.ndarray
+    r_apo: np.ndarray
+    phi0: np.ndarray
+    seed: int
+
+    def __len__(self) -> int:
+        return len(self.phi0)
+
+    def as_array(self) -> np.ndarray:
+        """(n, 3) triples (r_peri, r_apo, phi0)."""
+        return np.stack([self.r_peri, self.r_apo, self.phi0], axis=1)
+
+
+def disc_particles(n: int, r_in: float, r_out: float, seed: int) -> ParticleSet:
+    rng = np.random.default_rng(seed)
+    mid = rng.uniform(r_in + 1.0, r_out - 1.0, n)
+    w = rng.uniform(0.0, 0.05, n)
+    phi0 = rng.uniform(0.0, 2.0 * math.pi, n)
+    return ParticleSet(r_peri=mid * (1.0 - w), r_apo=mid * (1.0 + w), phi0=phi0, seed=seed)
 
 
 @dataclasses.dataclass
@@ -136,6 +170,22 @@ def small_static_view() -> View:
     """128x128, static camera at r = 15, 80 deg from the disc normal, disc [3, 12]."""
     pos = spherical_position(15.0, math.radians(80.0), 0.0)
     return aimed_view(pos, np.zeros(3), 128, 128, disc_r_in=3.0, disc_r_out=12.0)
+
+
+def animated_disc_view(width: int = 128, height: int = 128, n_particles: int = 24,
+                       time: float = 1000.0, seed: int = 7) -> View:
+    """The small static view with the paper's temperature law and a particle disc seen at
+    camera time `time` (disc [4, 12] so particle radii stay outside r = 3)."""
+    v = small_static_view()
+    v.width, v.height = width, height
+    v.disc_r_in, v.disc_r_out = 4.0, 12.0
+    v.disc_T_law = T_LAW_PAPER
+    v.disc_T0 = 8000.0
+    v.disc_density = DENSITY_PARTICLES
+    v.disc_opacity = 0.5
+    v.time = time
+    v.particles = disc_particles(n_particles, v.disc_r_in, v.disc_r_out, seed)
+    return v
 
 
 def boosted_orbit_view(width: int = 1920, height: int = 1080) -> View:
