@@ -231,8 +231,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--legs", default="plain,batch,serve,cpu",
-                    help="comma list of plain, batch, serve, cpu")
+    ap.add_argument("--legs", default="plain,anim,batch,serve,cpu",
+                    help="comma list of plain, anim, batch, serve, cpu")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--serve-tiles", type=int, default=262144,
                     help="most 16x16 tiles in one serving launch")
@@ -298,7 +298,7 @@ def main():
         roof = {"bound": "alu", "achieved": tf, "peak": FP32_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": tf / FP32_VECTOR_PEAK_TFLOPS,
                 "traffic": prof["fetch_bytes"] + prof["write_bytes"],
-                "kernel": "k_render<16,16,1>", "kernel_ms": kernel_ms,
+                "kernel": "k_render<16,16,1,false>", "kernel_ms": kernel_ms,
                 "flops_per_pixel": prof["fp32_flops_per_pixel"],
                 "frac_of_packed_fp32_peak": tf / FP32_PACKED_PEAK_TFLOPS,
                 "valu_issue": {"achieved": gi, "peak": VALU_ISSUE_PEAK_G,
@@ -308,13 +308,30 @@ def main():
                 "hbm": hbm}
     else:
         roof = {"bound": "hbm", "achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": hbm_gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "k_render<16,16,1>",
+                "frac": hbm_gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "k_render<16,16,1,false>",
                 "kernel_ms": kernel_ms, "note": "counters not taken on the current kernel",
                 "hbm": hbm}
     log("roofline: %s %.2f %s (frac %.4f); HBM algorithmic %.1f MB, %.0f GB/s"
         % (roof["bound"], roof["achieved"], roof["unit"], roof["frac"], alg / 1e6, hbm_gbs))
 
     extra = {}
+    if "anim" in legs:
+        # the same frame with an animated particle disc (retarded times, Appendix B)
+        av = scenes.boosted_orbit_view()
+        av.disc_density = scenes.DENSITY_PARTICLES
+        av.disc_opacity = 0.5
+        av.time = 1000.0
+        av.particles = scenes.disc_particles(64, av.disc_r_in, av.disc_r_out, 9)
+        ph = bh.bh_create_particles(ctx, av.particles.as_array())
+        aview = bh.make_view(av, stars, ph)
+        awall, akms, _ = plain_leg(bh, ctx, tables, aview, max(10, args.steps // 4),
+                                   args.warmup)
+        n_a = max(10, args.steps // 4)
+        extra["animated"] = {"particles": len(av.particles), "ms_per_frame": 1e3 * awall / n_a,
+                             "kernel_ms": float(np.mean(akms)),
+                             "mpx_per_s": W * H * n_a / awall / 1e6}
+        bh.bh_release_particles(ph)
+        log("animated:", json.dumps(extra["animated"]))
     if "batch" in legs:
         views = [bh.make_view(v, stars) for v in scenes.batch_views(64, 3)]
         extra["batched"] = batch_leg(bh, ctx, tables, views, reps=3)

@@ -43,6 +43,7 @@ typedef enum {
 typedef struct bh_ctx bh_ctx;
 typedef struct bh_tables bh_tables;
 typedef struct bh_stars bh_stars;
+typedef struct bh_particles bh_particles;
 
 /* ---- context ----------------------------------------------------------------------- */
 
@@ -75,7 +76,10 @@ typedef struct {
 /* Integrate the orbit equation u'' = 3/2 u^2 - u on the device for every table column
  * and fill the deflection table D(e,u) = phi - atan2(u, du/dphi) (incoming branch) and
  * the intersection table U(e,phi) = u (phi < pi, 1 after the ray falls in), both FP32,
- * at the texel centres k/(N-1) of the Appendix A mappings.  Shared by parameter key.
+ * at the texel centres k/(N-1) of the Appendix A mappings, and their time channels
+ * (Algorithm 1 Precompute stores t beside D and U): e * tau, where the regularised time
+ * tau = t - ln(u/(1-u)) + 1/u (+ a constant per ray) is finite along rays from infinity.
+ * Shared by parameter key.
  * Synchronises hip_stream before returning (the tables are then ready for any stream). */
 bh_status bh_precompute_tables(bh_ctx* ctx, const bh_table_params* p, void* hip_stream,
                                bh_tables** out);
@@ -83,7 +87,22 @@ bh_status bh_precompute_tables(bh_ctx* ctx, const bh_table_params* p, void* hip_
  * i (e coordinate) minor; host_U u_nphi*u_ne floats, row (phi) major.  Either may be NULL.
  * Blocking. */
 bh_status bh_tables_download(const bh_tables* t, float* host_D, float* host_U);
+/* Copy the time channels (e * tau) in the layouts of D and U.  Either may be NULL. */
+bh_status bh_tables_download_time(const bh_tables* t, float* host_Dt, float* host_Ut);
 bh_status bh_release_tables(bh_tables* t);
+
+/* ---- disc particles (Appendix B) --------------------------------------------------------- */
+
+/* Procedural particles of an animated disc: n triples (r_peri, r_apo, phi0) in host memory
+ * (units of r_s; 3 <= r_peri <= r_apo; phi0 the orbital phase at t = 0).  Each particle
+ * point a in [0, 2 pi) follows the quasi-circular orbit u = u1 + (u2 - u1)
+ * sin^2(pi / (4K) (a + phi(t)) sqrt(u3 - u1)), phi(t) = sqrt(ubar^3 / 2) t + phi0
+ * (u1 = 1/r_apo, u2 = 1/r_peri, u3 = 1 - u1 - u2, K = K(sqrt((u2-u1)/(u3-u1)))), and a hit
+ * point at distance d from the particle centre gets density (1 - d^2)^2 for d < 1.
+ * The library copies the records; n <= 65536.  BH_EINVAL for bad values. */
+bh_status bh_create_particles(bh_ctx* ctx, const double* host_triples, int32_t n,
+                              bh_particles** out);
+bh_status bh_release_particles(bh_particles* p);
 
 /* ---- star map (Section 3.3.2 "Emitted light") -------------------------------------- */
 
@@ -135,7 +154,17 @@ typedef struct {
   double k_disc;        /* exposure applied to disc band radiances (W m^-2 sr^-1)         */
   double k_star;        /* exposure applied to star intensities                           */
   const bh_stars* stars;/* NULL: black sky                                                 */
+  /* animated disc (Section 3.3.3 "Emitted light", Appendix B) */
+  int32_t disc_density; /* BH_DENSITY_UNIFORM, or BH_DENSITY_PARTICLES: each crossing's
+                           opacity is min(1, disc_opacity * particle density) at the
+                           crossing's position and retarded time                          */
+  int32_t pad1;
+  double time;          /* the camera's coordinate time (units of r_s / c)                */
+  const bh_particles* particles; /* required with BH_DENSITY_PARTICLES                    */
 } bh_view;
+
+#define BH_DENSITY_UNIFORM 0
+#define BH_DENSITY_PARTICLES 1
 
 /* AOV record written per pixel when aov_dev is not NULL (4 floats):
  *   [0] escape angle delta' (radians, +inf if the beam falls into the hole)
@@ -212,6 +241,12 @@ bh_status bh_serve_drain(bh_ctx* ctx);
  * [u = 1/p^r, delta, alpha, u_ic, u_oc]; writes 4 floats per ray in the AOV layout. */
 bh_status bh_trace_rays(bh_ctx* ctx, const bh_tables* t, const float* rays_dev, int64_t n,
                         float* out_dev, void* hip_stream);
+/* The same, also writing 4 floats per ray to out_time_dev: the retarded times of the two
+ * crossings in beam order (coordinate time from the crossing to the camera, Algorithm 1)
+ * and, as floats, the integers m_0, m_1 placing each crossing at beam-plane angle
+ * alpha + m pi (0 where there is no crossing). */
+bh_status bh_trace_rays_timed(bh_ctx* ctx, const bh_tables* t, const float* rays_dev, int64_t n,
+                              float* out_dev, float* out_time_dev, void* hip_stream);
 /* Measurement: render v once (into out_rgba_dev) with a variant of the render kernel that
  * marks every star-map texel the footprints visit, and return how many distinct texels were
  * visited (the star-map bytes one frame must read at least once).  Blocking. */

@@ -18,17 +18,19 @@ BH_TEXEL_FP16, BH_TEXEL_FP32 = 0, 1
 BH_T_POWER, BH_T_PAPER = 0, 1
 BH_AOV_CAPTURED, BH_AOV_CROSS0, BH_AOV_CROSS1 = 1, 2, 4
 BH_AOV_STAR_ZEROED, BH_AOV_DEGENERATE = 8, 16
+BH_DENSITY_UNIFORM, BH_DENSITY_PARTICLES = 0, 1
 
 # every symbol include/bh.h declares
 EXPORTS = [
     "bh_create", "bh_destroy", "bh_last_error", "bh_bytes_in_use",
-    "bh_precompute_tables", "bh_tables_download", "bh_release_tables",
+    "bh_precompute_tables", "bh_tables_download", "bh_tables_download_time", "bh_release_tables",
+    "bh_create_particles", "bh_release_particles",
     "bh_build_stars", "bh_stars_download", "bh_release_stars",
     "bh_render", "bh_render_batch", "bh_tile_config_count", "bh_tile_config_get",
     "bh_set_tile_config", "bh_autotune",
     "bh_serve_start", "bh_submit", "bh_poll", "bh_ticket_image", "bh_ticket_free",
     "bh_serve_drain",
-    "bh_trace_rays", "bh_footprint_texels", "bh_band_table_info", "bh_band_table_download", "bh_band_eval",
+    "bh_trace_rays", "bh_trace_rays_timed", "bh_footprint_texels", "bh_band_table_info", "bh_band_table_download", "bh_band_eval",
 ]
 
 
@@ -57,7 +59,8 @@ class View(C.Structure):
                 ("disc_T_law", C.c_int32), ("pad0", C.c_int32),
                 ("disc_T0", C.c_double), ("disc_T_exp", C.c_double),
                 ("disc_opacity", C.c_double), ("k_disc", C.c_double), ("k_star", C.c_double),
-                ("stars", C.c_void_p)]
+                ("stars", C.c_void_p), ("disc_density", C.c_int32), ("pad1", C.c_int32),
+                ("time", C.c_double), ("particles", C.c_void_p)]
 
 
 class TileConfig(C.Structure):
@@ -89,6 +92,9 @@ def lib():
             "bh_bytes_in_use": ([vp], u64),
             "bh_precompute_tables": ([vp, C.POINTER(TableParams), vp, C.POINTER(vp)], i32),
             "bh_tables_download": ([vp, vp, vp], i32),
+            "bh_tables_download_time": ([vp, vp, vp], i32),
+            "bh_create_particles": ([vp, vp, i32, C.POINTER(vp)], i32),
+            "bh_release_particles": ([vp], i32),
             "bh_release_tables": ([vp], i32),
             "bh_build_stars": ([vp, C.POINTER(StarField), vp, C.POINTER(vp)], i32),
             "bh_stars_download": ([vp, i32, vp], i32),
@@ -107,6 +113,7 @@ def lib():
             "bh_ticket_free": ([vp, u64], i32),
             "bh_serve_drain": ([vp], i32),
             "bh_trace_rays": ([vp, vp, vp, i64, vp, vp], i32),
+            "bh_trace_rays_timed": ([vp, vp, vp, i64, vp, vp, vp], i32),
             "bh_footprint_texels": ([vp, vp, C.POINTER(View), vp, C.POINTER(u64)], i32),
             "bh_band_table_info": ([vp, C.POINTER(i32), C.POINTER(C.c_float),
                                     C.POINTER(C.c_float)], i32),
@@ -156,8 +163,25 @@ def bh_tables_download(tables, host_D_ptr, host_U_ptr) -> None:
     _check(lib().bh_tables_download(tables, host_D_ptr, host_U_ptr))
 
 
+def bh_tables_download_time(tables, host_Dt_ptr, host_Ut_ptr) -> None:
+    _check(lib().bh_tables_download_time(tables, host_Dt_ptr, host_Ut_ptr))
+
+
 def bh_release_tables(tables) -> None:
     _check(lib().bh_release_tables(tables))
+
+
+def bh_create_particles(ctx, triples) -> int:
+    """triples: (n, 3) array-like of (r_peri, r_apo, phi0), copied by the library."""
+    import numpy as np
+    arr = np.ascontiguousarray(triples, np.float64).reshape(-1, 3)
+    out = C.c_void_p()
+    _check(lib().bh_create_particles(ctx, arr.ctypes.data, len(arr), C.byref(out)))
+    return out.value
+
+
+def bh_release_particles(particles) -> None:
+    _check(lib().bh_release_particles(particles))
 
 
 def bh_build_stars(ctx, dir_ptr, inten_ptr, temp_ptr, n, face_size, texel_format=BH_TEXEL_FP16,
@@ -247,6 +271,10 @@ def bh_trace_rays(ctx, tables, rays_ptr, n, out_ptr, stream=None) -> None:
     _check(lib().bh_trace_rays(ctx, tables, rays_ptr, n, out_ptr, stream))
 
 
+def bh_trace_rays_timed(ctx, tables, rays_ptr, n, out_ptr, out_time_ptr, stream=None) -> None:
+    _check(lib().bh_trace_rays_timed(ctx, tables, rays_ptr, n, out_ptr, out_time_ptr, stream))
+
+
 def bh_footprint_texels(ctx, tables, view: View, out_ptr) -> int:
     n = C.c_uint64()
     _check(lib().bh_footprint_texels(ctx, tables, C.byref(view), out_ptr, C.byref(n)))
@@ -269,8 +297,9 @@ def bh_band_eval(ctx, temps_ptr, n, out_ptr, stream=None) -> None:
 
 # ---- helpers ------------------------------------------------------------------------------
 
-def make_view(v, stars=None) -> View:
-    """bh View record from a scenes.View (same field names)."""
+def make_view(v, stars=None, particles=None) -> View:
+    """bh View record from a scenes.View (same field names); `particles` is the handle from
+    bh_create_particles for a view with a particle disc."""
     o = View()
     o.r_s = v.r_s
     o.cam_pos[:] = list(v.cam_pos)
@@ -283,6 +312,9 @@ def make_view(v, stars=None) -> View:
     o.disc_T0, o.disc_T_exp = v.disc_T0, v.disc_T_exp
     o.disc_opacity, o.k_disc, o.k_star = v.disc_opacity, v.k_disc, v.k_star
     o.stars = stars
+    o.disc_density = getattr(v, "disc_density", BH_DENSITY_UNIFORM)
+    o.time = getattr(v, "time", 0.0)
+    o.particles = particles
     return o
 
 

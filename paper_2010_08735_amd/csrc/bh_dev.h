@@ -22,8 +22,10 @@ constexpr float kPi = 3.14159265358979323846f;
 
 // ---- tables -------------------------------------------------------------------------
 struct TablesDev {
-  const float* D;  // d_n x d_n, row j (u coordinate) major
-  const float* U;  // u_nphi x u_ne, row j (phi coordinate) major
+  const float* D;   // d_n x d_n, row j (u coordinate) major
+  const float* U;   // u_nphi x u_ne, row j (phi coordinate) major
+  const float* Dt;  // time channels: e tau (regularised time) in the layouts of D and U
+  const float* Ut;
   int d_n, u_ne, u_nphi, pad;
 };
 
@@ -59,6 +61,10 @@ struct ViewDev {
   StarsDev stars;
   float4* out;
   float4* aov;
+  // animated disc: density_mode 1 = particles at the crossings' retarded times
+  float time;             // camera coordinate time
+  int density_mode, nparts, pad1;
+  const float4* parts;    // 2 float4 per particle (see disc_density)
 };
 
 // Work of the batched kernels, as runs of consecutive tiles of one view: the view's tiles
@@ -158,45 +164,47 @@ __device__ __forceinline__ float apsis_f(float e2) {
   return 1.0f / 3.0f + 2.0f / 3.0f * fsin_small(asinf(a) * (1.0f / 3.0f));
 }
 
-// D(e, u) through the Appendix A mapping.  udot = du/dphi at (e, u) on the ray.  For
+// D(e, u) through the Appendix A mapping, read from `tab` (T.D, or the time channel T.Dt,
+// which shares its layout).  udot = du/dphi at (e, u) on the ray.  For
 // e^2 < mu the row coordinate y = 1 - sqrt(1 - u/u_a) is evaluated as
 // 1 - sqrt(udot^2 / (e^2 + u u_a (1 - u_a - u))): the two are equal because
 // udot^2 = (u_a - u)(u_2 - u)(u - u_3) with u_2 + u_3 = 1 - u_a and u_2 u_3 = -e^2 / u_a,
 // and the second form has no cancellation when the camera sits near the apsis.
-__device__ __forceinline__ float lookup_D(const TablesDev& T, float e2, float u, float ua,
-                                          float udot) {
+__device__ __forceinline__ float lookup_D(const TablesDev& T, const float* tab, float e2,
+                                          float u, float ua, float udot) {
   const int n = T.d_n;
   if (e2 < kMu) {
     float x = 0.5f - fsqrt(-flog1p(-e2 * (1.0f / kMu)) * (1.0f / 50.0f));
     float den = e2 + u * ua * (1.0f - ua - u);
     float s2 = den > 0.0f ? fminf(fdiv(udot * udot, den), 1.0f) : 0.0f;
     float y = 1.0f - fsqrt(s2);
-    return bilinear(T.D, n, n, 0, n / 2 - 1, x, y);
+    return bilinear(tab, n, n, 0, n / 2 - 1, x, y);
   }
   float x = 0.5f + fsqrt(-flog1p(-kMu / e2) * (1.0f / 50.0f));
   float dz = u - 2.0f / 3.0f;
   const float s23 = 0.816496580927726f, s13 = 0.577350269189626f;
   float y = (s23 + copysignf(fsqrt(fabsf(dz)), dz)) * (1.0f / (s23 + s13));
-  return bilinear(T.D, n, n, n / 2, n - 1, x, y);
+  return bilinear(tab, n, n, n / 2, n - 1, x, y);
 }
 
 // D(e, u_a) for e^2 < mu: the apsis is the last row (y = 1) of the left half
-__device__ __forceinline__ float lookup_D_apsis(const TablesDev& T, float e2) {
+__device__ __forceinline__ float lookup_D_apsis(const TablesDev& T, const float* tab, float e2) {
   const int n = T.d_n, hi = n / 2 - 1;
   float x = 0.5f - fsqrt(-flog1p(-e2 * (1.0f / kMu)) * (1.0f / 50.0f));
   float tx = clampf(x * (float)(n - 1), 0.0f, (float)hi);
   int i0 = min((int)tx, hi - 1);
   float fx = tx - (float)i0;
-  const float* r = T.D + (__umul24((unsigned)(n - 1), (unsigned)n) + (unsigned)i0);
+  const float* r = tab + (__umul24((unsigned)(n - 1), (unsigned)n) + (unsigned)i0);
   return r[0] + fx * (r[1] - r[0]);
 }
 
-// U(e, phi) through the Appendix A mapping
-__device__ __forceinline__ float lookup_U(const TablesDev& T, float e2, float e, float phi) {
+// U(e, phi) through the Appendix A mapping, read from `tab` (T.U or the time channel T.Ut)
+__device__ __forceinline__ float lookup_U(const TablesDev& T, const float* tab, float e2, float e,
+                                          float phi) {
   float x = fdiv(1.0f, 1.0f + 6.0f * e2);
   // (1 + 6 e^3) / (1 + e^2) written so that it cannot overflow for nearly radial rays
   float y = phi * (1.0f / 3.0f) * (6.0f * e + fdiv(1.0f - 6.0f * e, 1.0f + e2));
-  return bilinear(T.U, T.u_ne, T.u_nphi, 0, T.u_ne - 1, x, y);
+  return bilinear(tab, T.u_ne, T.u_nphi, 0, T.u_ne - 1, x, y);
 }
 
 // band radiances (R, G, B, sum) at temperature T from the log-log band table

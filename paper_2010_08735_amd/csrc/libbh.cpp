@@ -11,6 +11,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <set>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -23,8 +24,8 @@
 #include "bh_dev.h"
 
 namespace bh {
-hipError_t launch_precompute(float* D, int d_n, float* U, int u_ne, int u_nphi, int mode,
-                             double band, double step, hipStream_t s);
+hipError_t launch_precompute(float* D, float* Dt, int d_n, float* U, float* Ut, int u_ne,
+                             int u_nphi, int mode, double band, double step, hipStream_t s);
 hipError_t launch_band_lut(float4* lut, int n, float x0, float dx, hipStream_t s);
 hipError_t launch_band_eval(const LutDev& L, const float* temps, int64_t n, float* out,
                             hipStream_t s);
@@ -40,11 +41,11 @@ hipError_t launch_star_unpack(const void* in, int64_t count, float scale, int fp
                               hipStream_t s);
 hipError_t launch_render(int cfg, const ViewDev& v, const TablesDev& T, const LutDev& L,
                          hipStream_t s);
-hipError_t launch_render_batch(int cfg, int persistent, const ViewDev* views,
+hipError_t launch_render_batch(int cfg, int persistent, int anim, const ViewDev* views,
                                const TileRun* runs, int nruns, int ntiles, int* counter,
                                const TablesDev& T, const LutDev& L, int grid, hipStream_t s);
 hipError_t launch_trace_rays(const TablesDev& T, const float* rays, int64_t n, float4* out,
-                             hipStream_t s);
+                             float4* out_time, hipStream_t s);
 hipError_t launch_render_count(const ViewDev& v, const TablesDev& T, const LutDev& L,
                                uint32_t* touched, int64_t words, unsigned long long* total,
                                hipStream_t s);
@@ -80,8 +81,16 @@ struct bh_tables {
   std::string key;
   float* D = nullptr;
   float* U = nullptr;
+  float* Dt = nullptr;  // time channels: e tau at the same texel centres
+  float* Ut = nullptr;
   size_t bytes = 0;
   int refs = 1;
+};
+
+struct bh_particles {
+  bh_ctx* ctx;
+  float4* dev = nullptr;  // 2 records per particle
+  int n = 0;
 };
 
 struct bh_stars {
@@ -134,6 +143,7 @@ struct bh_ctx {
   std::mutex mu;  // resources, tile config, batch staging
   std::map<std::string, bh_tables*> tables;
   std::map<std::tuple<uint64_t, int, int>, bh_stars*> stars;
+  std::set<bh_particles*> particles;
   float4* lut = nullptr;
   int lut_n = 4096;
   float lut_x0 = 6.0f, lut_dx = 15.0f / 4095.0f;
@@ -241,6 +251,8 @@ extern "C" void bh_destroy(bh_ctx* c) {
   for (auto& kv : c->tables) {
     dev_free(c, kv.second->D, 0);
     dev_free(c, kv.second->U, 0);
+    dev_free(c, kv.second->Dt, 0);
+    dev_free(c, kv.second->Ut, 0);
     delete kv.second;
   }
   for (auto& kv : c->stars) {
@@ -250,6 +262,10 @@ extern "C" void bh_destroy(bh_ctx* c) {
     dev_free(c, kv.second->occ, 0);
     dev_free(c, kv.second->occ_off_dev, 0);
     delete kv.second;
+  }
+  for (bh_particles* p : c->particles) {
+    dev_free(c, p->dev, 0);
+    delete p;
   }
   dev_free(c, c->lut, 0);
   dev_free(c, c->b_counter, 0);
@@ -301,19 +317,26 @@ extern "C" bh_status bh_precompute_tables(bh_ctx* c, const bh_table_params* pin,
   size_t bd = sizeof(float) * (size_t)p.d_n * p.d_n, bu = sizeof(float) * (size_t)p.u_ne * p.u_nphi;
   bh_status st = dev_alloc(c, bd, (void**)&t->D);
   if (!st) st = dev_alloc(c, bu, (void**)&t->U);
+  if (!st) st = dev_alloc(c, bd, (void**)&t->Dt);
+  if (!st) st = dev_alloc(c, bu, (void**)&t->Ut);
   if (st) {
     dev_free(c, t->D, t->D ? bd : 0);
+    dev_free(c, t->U, t->U ? bu : 0);
+    dev_free(c, t->Dt, t->Dt ? bd : 0);
     delete t;
     return st;
   }
-  t->bytes = bd + bu;
+  t->bytes = 2 * (bd + bu);
   hipStream_t s = (hipStream_t)stream;
   int mode = p.precision == BH_TAB_FP32 ? 0 : (p.precision == BH_TAB_FP64_BAND ? 1 : 2);
-  hipError_t e = launch_precompute(t->D, p.d_n, t->U, p.u_ne, p.u_nphi, mode, p.fp64_band, p.step, s);
+  hipError_t e = launch_precompute(t->D, t->Dt, p.d_n, t->U, t->Ut, p.u_ne, p.u_nphi, mode,
+                                   p.fp64_band, p.step, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
     dev_free(c, t->D, bd);
     dev_free(c, t->U, bu);
+    dev_free(c, t->Dt, bd);
+    dev_free(c, t->Ut, bu);
     delete t;
     return fail(BH_EDEVICE, std::string("precompute: ") + hipGetErrorString(e));
   }
@@ -330,6 +353,14 @@ extern "C" bh_status bh_tables_download(const bh_tables* t, float* hD, float* hU
   return BH_OK;
 }
 
+extern "C" bh_status bh_tables_download_time(const bh_tables* t, float* hDt, float* hUt) {
+  if (!t) return fail(BH_EINVAL, "NULL tables");
+  HIPCHK(hipSetDevice(t->ctx->device));
+  if (hDt) HIPCHK(hipMemcpy(hDt, t->Dt, sizeof(float) * (size_t)t->p.d_n * t->p.d_n, hipMemcpyDeviceToHost));
+  if (hUt) HIPCHK(hipMemcpy(hUt, t->Ut, sizeof(float) * (size_t)t->p.u_ne * t->p.u_nphi, hipMemcpyDeviceToHost));
+  return BH_OK;
+}
+
 extern "C" bh_status bh_release_tables(bh_tables* t) {
   if (!t) return fail(BH_EINVAL, "NULL tables");
   bh_ctx* c = t->ctx;
@@ -340,7 +371,74 @@ extern "C" bh_status bh_release_tables(bh_tables* t) {
   c->tables.erase(t->key);
   dev_free(c, t->D, sizeof(float) * (size_t)t->p.d_n * t->p.d_n);
   dev_free(c, t->U, sizeof(float) * (size_t)t->p.u_ne * t->p.u_nphi);
+  dev_free(c, t->Dt, sizeof(float) * (size_t)t->p.d_n * t->p.d_n);
+  dev_free(c, t->Ut, sizeof(float) * (size_t)t->p.u_ne * t->p.u_nphi);
   delete t;
+  return BH_OK;
+}
+
+// ---- disc particles (Appendix B) -------------------------------------------------------------
+
+// complete elliptic integral of the first kind by the arithmetic-geometric mean (Gauss):
+// K(kappa) = pi / (2 AGM(1, sqrt(1 - kappa^2)))
+static double ellipk_agm(double kappa) {
+  double a = 1.0, b = std::sqrt(1.0 - kappa * kappa);
+  for (int it = 0; it < 40 && std::fabs(a - b) > 1e-16 * a; ++it) {
+    double an = 0.5 * (a + b);
+    b = std::sqrt(a * b);
+    a = an;
+  }
+  return M_PI / (a + b);
+}
+
+extern "C" bh_status bh_create_particles(bh_ctx* c, const double* tr, int32_t n,
+                                         bh_particles** out) {
+  if (!c || !out || n < 0 || n > 65536 || (n > 0 && !tr)) return fail(BH_EINVAL, "bad arguments");
+  std::vector<float4> rec(2 * (size_t)std::max(n, 1));
+  for (int32_t j = 0; j < n; ++j) {
+    double rp = tr[3 * j], ra = tr[3 * j + 1], ph0 = tr[3 * j + 2];
+    if (!(std::isfinite(rp) && std::isfinite(ra) && std::isfinite(ph0)) || !(rp >= 3.0) ||
+        !(ra >= rp) || ra > 1e6)
+      return fail(BH_EINVAL, "particle " + std::to_string(j) + ": need 3 <= r_peri <= r_apo");
+    double u1 = 1.0 / ra, u2 = 1.0 / rp, u3 = 1.0 - u1 - u2;
+    double K = ellipk_agm(std::sqrt((u2 - u1) / (u3 - u1)));
+    double ubar = 0.5 * (u1 + u2);
+    rec[2 * j] = make_float4((float)u1, (float)(u2 - u1),
+                             (float)(M_PI / (4.0 * K) * std::sqrt(u3 - u1)),
+                             (float)std::sqrt(ubar * ubar * ubar / 2.0));
+    rec[2 * j + 1] = make_float4((float)ph0, (float)(rp - 1.0), (float)(ra + 1.0), 0.0f);
+  }
+  HIPCHK(hipSetDevice(c->device));
+  std::lock_guard<std::mutex> g(c->mu);
+  auto* p = new bh_particles;
+  p->ctx = c;
+  p->n = n;
+  size_t bytes = sizeof(float4) * rec.size();
+  bh_status st = dev_alloc(c, bytes, (void**)&p->dev);
+  if (st) {
+    delete p;
+    return st;
+  }
+  hipError_t e = hipMemcpy(p->dev, rec.data(), bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    dev_free(c, p->dev, bytes);
+    delete p;
+    return fail(BH_EDEVICE, std::string("hipMemcpy: ") + hipGetErrorString(e));
+  }
+  c->particles.insert(p);
+  *out = p;
+  return BH_OK;
+}
+
+extern "C" bh_status bh_release_particles(bh_particles* p) {
+  if (!p) return fail(BH_EINVAL, "NULL particles");
+  bh_ctx* c = p->ctx;
+  std::lock_guard<std::mutex> g(c->mu);
+  if (!c->particles.erase(p)) return fail(BH_ENOTFOUND, "unknown particles");
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();  // launches may still read the records
+  dev_free(c, p->dev, sizeof(float4) * 2 * (size_t)std::max(p->n, 1));
+  delete p;
   return BH_OK;
 }
 
@@ -519,6 +617,10 @@ static bh_status make_view(const bh_view* v, float* out, float* aov, ViewDev* o)
   if (!(v->disc_opacity >= 0 && v->disc_opacity <= 1)) return fail(BH_EINVAL, "opacity must be in [0,1]");
   if (v->disc_T_law != BH_T_POWER && v->disc_T_law != BH_T_PAPER) return fail(BH_EINVAL, "bad T law");
   if (!(v->disc_T0 >= 0)) return fail(BH_EINVAL, "disc_T0 must be >= 0");
+  if (v->disc_density != BH_DENSITY_UNIFORM && v->disc_density != BH_DENSITY_PARTICLES)
+    return fail(BH_EINVAL, "bad disc_density");
+  if (v->disc_density == BH_DENSITY_PARTICLES && (!v->particles || !std::isfinite(v->time)))
+    return fail(BH_EINVAL, "a particle disc needs particles and a finite time");
   const double* R = v->cam_rot;
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) {
@@ -555,6 +657,12 @@ static bh_status make_view(const bh_view* v, float* out, float* aov, ViewDev* o)
   o->k_star = (float)v->k_star;
   o->width = v->width;
   o->height = v->height;
+  if (v->disc_density == BH_DENSITY_PARTICLES) {
+    o->density_mode = 1;
+    o->time = (float)v->time;
+    o->nparts = v->particles->n;
+    o->parts = v->particles->dev;
+  }
   if (v->stars) {
     const bh_stars* s = v->stars;
     o->has_stars = 1;
@@ -576,6 +684,8 @@ static TablesDev tables_dev(const bh_tables* t) {
   TablesDev T;
   T.D = t->D;
   T.U = t->U;
+  T.Dt = t->Dt;
+  T.Ut = t->Ut;
   T.d_n = t->p.d_n;
   T.u_ne = t->p.u_ne;
   T.u_nphi = t->p.u_nphi;
@@ -654,12 +764,15 @@ static bh_status enqueue_batch(bh_ctx* c, const TablesDev& T, const std::vector<
   int per_cu = std::max(1, 16 / waves);
   int grid = std::max(1, std::min<int>(ntiles, c->cus * per_cu));
   int nruns = (int)runs.size();
+  int anim = 0;
+  for (const ViewDev& vd : vds) anim |= vd.density_mode != 0;
   LutDev L = lut_dev(c);
   if (!use_graph) {
-    HIPCHK(launch_render_batch(cfg, pers, dviews, druns, nruns, ntiles, counter, T, L, grid, s));
+    HIPCHK(launch_render_batch(cfg, pers, anim, dviews, druns, nruns, ntiles, counter, T, L,
+                               grid, s));
     return BH_OK;
   }
-  auto key = std::make_tuple(cfg * 2 + pers, ntiles, nruns, grid, (const void*)T.D,
+  auto key = std::make_tuple(cfg * 4 + pers * 2 + anim, ntiles, nruns, grid, (const void*)T.D,
                              (uintptr_t)counter);
   auto it = c->graphs.find(key);
   if (it == c->graphs.end()) {
@@ -667,8 +780,8 @@ static bh_status enqueue_batch(bh_ctx* c, const TablesDev& T, const std::vector<
     HIPCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
     hipGraph_t graph;
     HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-    hipError_t e = launch_render_batch(cfg, pers, dviews, druns, nruns, ntiles, counter, T, L,
-                                       grid, cap);
+    hipError_t e = launch_render_batch(cfg, pers, anim, dviews, druns, nruns, ntiles, counter,
+                                       T, L, grid, cap);
     hipError_t e2 = hipStreamEndCapture(cap, &graph);
     (void)hipStreamDestroy(cap);
     if (e != hipSuccess || e2 != hipSuccess)
@@ -808,7 +921,17 @@ extern "C" bh_status bh_trace_rays(bh_ctx* c, const bh_tables* t, const float* r
                                    float* out, void* stream) {
   if (!c || !t || (n > 0 && (!rays || !out)) || n < 0) return fail(BH_EINVAL, "bad arguments");
   HIPCHK(hipSetDevice(c->device));
-  HIPCHK(launch_trace_rays(tables_dev(t), rays, n, (float4*)out, (hipStream_t)stream));
+  HIPCHK(launch_trace_rays(tables_dev(t), rays, n, (float4*)out, nullptr, (hipStream_t)stream));
+  return BH_OK;
+}
+
+extern "C" bh_status bh_trace_rays_timed(bh_ctx* c, const bh_tables* t, const float* rays,
+                                         int64_t n, float* out, float* out_time, void* stream) {
+  if (!c || !t || (n > 0 && (!rays || !out || !out_time)) || n < 0)
+    return fail(BH_EINVAL, "bad arguments");
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(launch_trace_rays(tables_dev(t), rays, n, (float4*)out, (float4*)out_time,
+                           (hipStream_t)stream));
   return BH_OK;
 }
 

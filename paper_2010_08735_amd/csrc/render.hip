@@ -107,16 +107,29 @@ struct TraceOut {
   float e;             // the beam's invariant e = sqrt(e^2)
   float dprime;        // escape angle (valid if !captured)
   float ucr[2];
+  float tret[2];       // retarded times of the crossings (TIMED only)
+  int mcr[2];          // crossing k lies at beam-plane angle alpha + mcr[k] pi (TIMED only)
   int ncross;
   unsigned bits;
 };
 
-// Algorithm 1, TraceRay, in FP32.  Returns crossings in order along the beam.
+// singular part of the coordinate time along a ray: t = tau + S(u) + const
+__device__ __forceinline__ float time_singular(float u) {
+  return __log2f(fdiv(u, 1.0f - u)) * 0.693147180559945309f - fdiv(1.0f, u);
+}
+
+// Algorithm 1, TraceRay, in FP32.  Returns crossings in order along the beam.  TIMED also
+// returns each crossing's retarded time (the coordinate time the light takes from it to
+// the camera): s (t_0 - t) for crossing 0 and 2 t_a - t - t_1 for crossing 1, with
+// t = tau + S(u) and tau = (e tau from the time channels) / e.
+template <bool TIMED>
 __device__ __forceinline__ TraceOut trace_ray(const TablesDev& T, float u, float delta,
                                              float alpha, float cotd, float u_ic, float u_oc) {
   TraceOut o;
   o.ncross = 0;
   o.ucr[0] = o.ucr[1] = 0.0f;
+  o.tret[0] = o.tret[1] = 0.0f;
+  o.mcr[0] = o.mcr[1] = 0;
   o.bits = 0;
   o.dprime = 0.0f;
   float udot = -u * cotd;
@@ -130,28 +143,51 @@ __device__ __forceinline__ TraceOut trace_ray(const TablesDev& T, float u, float
   int s = udot >= 0.0f ? 1 : -1;
   bool bound = e2 < kMu;
   float ua = bound ? apsis_f(e2) : 0.0f;
-  float Dl = lookup_D(T, e2, u, ua, udot);
+  float Dl = lookup_D(T, T.D, e2, u, ua, udot);
   float Da = 0.0f, phia = __builtin_inff();
   if (bound) {
-    Da = lookup_D_apsis(T, e2);
+    Da = lookup_D_apsis(T, T.D, e2);
     phia = Da + 0.5f * kPi;
   }
+  float ie = 0.0f, t_cam = 0.0f, t_a = 0.0f;
+  if (TIMED) {
+    ie = fdiv(1.0f, e);
+    t_cam = lookup_D(T, T.Dt, e2, u, ua, udot) * ie + time_singular(u);
+    if (bound) t_a = lookup_D_apsis(T, T.Dt, e2) * ie + time_singular(ua);
+  }
   float phi = Dl + (s == 1 ? kPi - delta : delta) + (float)s * alpha;
-  float phi0 = phi - kPi * floorf(phi * (1.0f / kPi));
-  float u0 = lookup_U(T, e2, e, phi0);
+  float m0 = floorf(phi * (1.0f / kPi));
+  float phi0 = phi - kPi * m0;
+  float u0 = lookup_U(T, T.U, e2, e, phi0);
   int sg = (u0 > u) - (u0 < u);
   if (phi0 < phia && u_oc <= u0 && u0 <= u_ic && sg == s) {
     o.ucr[0] = u0;
     o.ncross = 1;
     o.bits |= BH_CROSS0_BIT;
+    if (TIMED) {
+      o.tret[0] = (float)s * (lookup_U(T, T.Ut, e2, e, phi0) * ie + time_singular(u0) - t_cam);
+      o.mcr[0] = (int)m0;
+    }
   }
   if (bound && s == 1) {
     phi = 2.0f * phia - phi;
-    float phi1 = phi - kPi * floorf(phi * (1.0f / kPi));
-    float u1 = lookup_U(T, e2, e, phi1);
+    float m1 = floorf(phi * (1.0f / kPi));
+    float phi1 = phi - kPi * m1;
+    float u1 = lookup_U(T, T.U, e2, e, phi1);
     if (phi1 < phia && u_oc <= u1 && u1 <= u_ic) {
+      float t1 = 0.0f;
+      if (TIMED)
+        t1 = 2.0f * t_a - t_cam - (lookup_U(T, T.Ut, e2, e, phi1) * ie + time_singular(u1));
       // static indices only: a dynamically indexed array would be placed in LDS
-      if (o.ncross == 0) o.ucr[0] = u1; else o.ucr[1] = u1;
+      if (o.ncross == 0) {
+        o.ucr[0] = u1;
+        o.tret[0] = t1;
+        o.mcr[0] = (int)m1;
+      } else {
+        o.ucr[1] = u1;
+        o.tret[1] = t1;
+        o.mcr[1] = (int)m1;
+      }
       o.ncross += 1;
       o.bits |= BH_CROSS1_BIT;
     }
@@ -195,10 +231,42 @@ __device__ __forceinline__ float quad_diff(float x) {
   return quad_partner<MASK>(x) - x;
 }
 
+// atan2 over the whole circle, from the half-plane version
+__device__ __forceinline__ float fatan2_any(float y, float x) {
+  float r = fatan2_pos(fabsf(y), x);
+  return y < 0.0f ? -r : r;
+}
+
+// Density of the procedural disc particles (Appendix B) at the hit point (ht, hr, hphi):
+// particle j's point a = (hphi - phi_j(ht)) mod 2 pi, phi_j(t) = omega_j t + phi0_j, has
+// u_a = u1 + (u2 - u1) sin^2(c_j (a + phi_j(ht))); d^2 = (a/pi - 1)^2 + (hr - 1/u_a)^2 and
+// the particle adds (1 - d^2)^2 inside d < 1.  Particle records (two float4 each):
+// (u1, u2 - u1, c, omega), (phi0, r_peri - 1, r_apo + 1, 0); the radial bounds skip
+// particles that cannot reach d < 1.
+__device__ __forceinline__ float disc_density(const ViewDev& v, float ht, float hr, float hphi) {
+  const float k2Pi = 2.0f * kPi;
+  float rho = 0.0f;
+  for (int j = 0; j < v.nparts; ++j) {
+    float4 p0 = v.parts[2 * j], p1 = v.parts[2 * j + 1];
+    if (hr < p1.y || hr > p1.z) continue;
+    float ph = fmaf(p0.w, ht, p1.x);
+    float a = hphi - ph;
+    a -= k2Pi * floorf(a * (1.0f / k2Pi));
+    float sn, cs;
+    fsincos(p0.z * (a + ph), &sn, &cs);
+    float ua = fmaf(p0.y, sn * sn, p0.x);
+    float dr = hr - fdiv(1.0f, ua);
+    float da = a * (1.0f / kPi) - 1.0f;
+    float d2 = da * da + dr * dr;
+    if (d2 < 1.0f) rho += (1.0f - d2) * (1.0f - d2);
+  }
+  return rho;
+}
+
 // One pixel; every lane of the wave must call this together (quad exchanges).
 // COUNT: also mark every star-map texel the footprint visits in `touched` (one bit per
-// texel, measurement only).
-template <bool COUNT>
+// texel, measurement only).  ANIM: views may have a particle disc (retarded times).
+template <bool COUNT, bool ANIM = false>
 __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& T,
                                              const LutDev& L, int px, int py,
                                              uint32_t* touched) {
@@ -260,13 +328,15 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
     if (ty < 0.0f) {
       tx = -tx;
       ty = -ty;
+      t0 = -t0;  // t now points along the line of nodes with t.e_y' >= 0
+      t1 = -t1;
     }
     alpha = fatan2_pos(ty, tx);
   }
   float zeta = cz2;
 
   // ---- TraceRay (Algorithm 1)
-  TraceOut tr = trace_ray(T, v.u_c, delta, alpha, dr / ncz, u_ic, u_oc);
+  TraceOut tr = trace_ray<ANIM>(T, v.u_c, delta, alpha, dr / ncz, u_ic, u_oc);
   bits |= tr.bits;
   const bool captured = (tr.bits & BH_CAPTURED_BIT) != 0;
 
@@ -274,6 +344,10 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
   float cr = 0.0f, cg = 0.0f, cb = 0.0f, trans = 1.0f;
   if (tr.ncross > 0) {
     const float ie = fdiv(1.0f, tr.e);
+    // animated disc: crossing k sits at (-1)^m_k t, i.e. at disc azimuth az0 + m_k pi
+    const bool anim = ANIM && v.density_mode == 1;
+    float az0 = 0.0f;
+    if (anim) az0 = fatan2_any(t1, t0);
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       if (k >= tr.ncross) break;
@@ -284,11 +358,18 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
       float om = fsqrt(0.5f * uk * uk * uk);
       float D = dcam * ikt * fdiv(1.0f, 1.0f + om * zeta * ie);
       float4 Lb = band_lookup(L, D * Tp);
-      float w = trans * v.rho * v.k_disc;
+      float rk = v.rho;
+      if (anim) {
+        float tk = k == 0 ? tr.tret[0] : tr.tret[1];
+        int mk = k == 0 ? tr.mcr[0] : tr.mcr[1];
+        float dens = disc_density(v, v.time - tk, fdiv(1.0f, uk), az0 + (float)mk * kPi);
+        rk = fminf(1.0f, v.rho * dens);
+      }
+      float w = trans * rk * v.k_disc;
       cr += w * Lb.x;
       cg += w * Lb.y;
       cb += w * Lb.z;
-      trans *= 1.0f - v.rho;
+      trans *= 1.0f - rk;
     }
   }
 
@@ -417,7 +498,7 @@ struct TileCfg {
   static_assert(kBX * kBY % PPT == 0, "blocks must divide by pixels per thread");
 };
 
-template <int TW, int TH, int PPT, bool COUNT = false>
+template <int TW, int TH, int PPT, bool COUNT = false, bool ANIM = false>
 __device__ __forceinline__ void render_tile(const ViewDev& v, const TablesDev& T, const LutDev& L,
                                             int tx0, int ty0, uint32_t* touched = nullptr) {
   using C = TileCfg<TW, TH, PPT>;
@@ -431,19 +512,19 @@ __device__ __forceinline__ void render_tile(const ViewDev& v, const TablesDev& T
     int px = tx0 + 8 * bx + ox, py = ty0 + 8 * by + oy;
     // skip 8x8 blocks entirely outside the image (uniform per wave)
     if (tx0 + 8 * bx >= v.width || ty0 + 8 * by >= v.height) continue;
-    render_pixel<COUNT>(v, T, L, px, py, touched);
+    render_pixel<COUNT, ANIM>(v, T, L, px, py, touched);
   }
 }
 
 // One launch per view: blocks map to tiles in an XCD-aware order (consecutive tile rows go
 // to the same XCD, whose L2 then holds the cube-map region they share).
-template <int TW, int TH, int PPT>
+template <int TW, int TH, int PPT, bool ANIM>
 __global__ void __launch_bounds__((TW / 8) * (TH / 8) * 64 / PPT)
     k_render(ViewDev v, TablesDev T, LutDev L, int tiles_x, int ntiles, int per_xcd) {
   int b = blockIdx.x;
   int tile = (b & 7) * per_xcd + (b >> 3);
   if (tile >= ntiles) return;
-  render_tile<TW, TH, PPT>(v, T, L, (tile % tiles_x) * TW, (tile / tiles_x) * TH);
+  render_tile<TW, TH, PPT, false, ANIM>(v, T, L, (tile % tiles_x) * TW, (tile / tiles_x) * TH);
 }
 
 // The run holding flat tile index `it` (wave-uniform): the last run whose start is <= it.
@@ -465,19 +546,20 @@ __device__ __forceinline__ TileRun find_run(const TileRun* __restrict__ runs, in
   return r;
 }
 
-template <int TW, int TH, int PPT>
+template <int TW, int TH, int PPT, bool ANIM>
 __device__ __forceinline__ void render_flat_tile(const ViewDev* __restrict__ views,
                                                  const TileRun* __restrict__ runs, int nruns,
                                                  int it, const TablesDev& T, const LutDev& L) {
   TileRun r = find_run(runs, nruns, it);
   int tile = r.tile0 + (it - r.start);
   ViewDev v = views[r.view];
-  render_tile<TW, TH, PPT>(v, T, L, (tile % r.tiles_x) * TW, (tile / r.tiles_x) * TH);
+  render_tile<TW, TH, PPT, false, ANIM>(v, T, L, (tile % r.tiles_x) * TW,
+                                        (tile / r.tiles_x) * TH);
 }
 
 // Persistent launch over the tiles of many views: workgroups take flat tile indices from
 // an atomic counter until all ntiles are done.
-template <int TW, int TH, int PPT>
+template <int TW, int TH, int PPT, bool ANIM>
 __global__ void __launch_bounds__((TW / 8) * (TH / 8) * 64 / PPT)
     k_render_batch(const ViewDev* __restrict__ views, const TileRun* __restrict__ runs,
                    int nruns, int ntiles, int* __restrict__ counter, TablesDev T, LutDev L) {
@@ -488,20 +570,20 @@ __global__ void __launch_bounds__((TW / 8) * (TH / 8) * 64 / PPT)
     int it = __builtin_amdgcn_readfirstlane(s_item);
     __syncthreads();
     if (it >= ntiles) break;
-    render_flat_tile<TW, TH, PPT>(views, runs, nruns, it, T, L);
+    render_flat_tile<TW, TH, PPT, ANIM>(views, runs, nruns, it, T, L);
   }
 }
 
 // Tiles of many views without persistence: one workgroup per flat tile index, XCD-aware
 // order.
-template <int TW, int TH, int PPT>
+template <int TW, int TH, int PPT, bool ANIM>
 __global__ void __launch_bounds__((TW / 8) * (TH / 8) * 64 / PPT)
     k_render_list(const ViewDev* __restrict__ views, const TileRun* __restrict__ runs,
                   int nruns, int ntiles, int per_xcd, TablesDev T, LutDev L) {
   int b = blockIdx.x;
   int it = (b & 7) * per_xcd + (b >> 3);
   if (it >= ntiles) return;
-  render_flat_tile<TW, TH, PPT>(views, runs, nruns, it, T, L);
+  render_flat_tile<TW, TH, PPT, ANIM>(views, runs, nruns, it, T, L);
 }
 
 __global__ void k_reset_counter(int* c) { *c = 0; }
@@ -524,64 +606,71 @@ __global__ void k_popcount(const uint32_t* __restrict__ bits, int64_t n,
   if ((threadIdx.x & 63) == 0 && c) atomicAdd(total, (unsigned long long)c);
 }
 
-// TraceRay alone, for unit tests: rays = [u, delta, alpha, u_ic, u_oc]
+// TraceRay alone, for unit tests: rays = [u, delta, alpha, u_ic, u_oc].  TIMED also writes
+// (retarded time 0, retarded time 1, m_0, m_1) per ray to out_time.
+template <bool TIMED>
 __global__ void k_trace_rays(TablesDev T, const float* __restrict__ rays, int64_t n,
-                             float4* __restrict__ out) {
+                             float4* __restrict__ out, float4* __restrict__ out_time) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
   const float* r = rays + 5 * i;
   float u = r[0], delta = r[1];
   float sd, cd;
   sincosf(delta, &sd, &cd);
-  TraceOut t = trace_ray(T, u, delta, r[2], cd / sd, r[3], r[4]);
+  TraceOut t = trace_ray<TIMED>(T, u, delta, r[2], cd / sd, r[3], r[4]);
   bool cap = (t.bits & BH_CAPTURED_BIT) != 0;
   out[i] = make_float4(cap ? __builtin_inff() : t.dprime, t.ucr[0], t.ucr[1],
                        __uint_as_float(t.bits));
+  if (TIMED)
+    out_time[i] = make_float4(t.tret[0], t.tret[1], (float)t.mcr[0], (float)t.mcr[1]);
 }
 
 // ---- host-side launchers ------------------------------------------------------------------
 
 struct TileEntry {
   int tw, th, waves, ppt;
-  void (*plain)(const ViewDev&, const TablesDev&, const LutDev&, hipStream_t);
-  void (*batch)(const ViewDev*, const TileRun*, int, int, int*, const TablesDev&,
-                const LutDev&, int grid, hipStream_t);
-  void (*list)(const ViewDev*, const TileRun*, int, int, const TablesDev&, const LutDev&,
-               hipStream_t);
+  // index 0: static disc, 1: views that may carry a particle disc
+  void (*plain[2])(const ViewDev&, const TablesDev&, const LutDev&, hipStream_t);
+  void (*batch[2])(const ViewDev*, const TileRun*, int, int, int*, const TablesDev&,
+                   const LutDev&, int grid, hipStream_t);
+  void (*list[2])(const ViewDev*, const TileRun*, int, int, const TablesDev&, const LutDev&,
+                  hipStream_t);
 };
 
-template <int TW, int TH, int PPT>
+template <int TW, int TH, int PPT, bool ANIM>
 static void launch_plain(const ViewDev& v, const TablesDev& T, const LutDev& L, hipStream_t s) {
   using C = TileCfg<TW, TH, PPT>;
   int tiles_x = (v.width + TW - 1) / TW, tiles_y = (v.height + TH - 1) / TH;
   int ntiles = tiles_x * tiles_y;
   int per_xcd = (ntiles + 7) / 8;
-  hipLaunchKernelGGL((k_render<TW, TH, PPT>), dim3(8 * per_xcd), dim3(C::kThreads), 0, s, v, T,
-                     L, tiles_x, ntiles, per_xcd);
+  hipLaunchKernelGGL((k_render<TW, TH, PPT, ANIM>), dim3(8 * per_xcd), dim3(C::kThreads), 0, s,
+                     v, T, L, tiles_x, ntiles, per_xcd);
 }
 
-template <int TW, int TH, int PPT>
+template <int TW, int TH, int PPT, bool ANIM>
 static void launch_batch(const ViewDev* views, const TileRun* runs, int nruns, int ntiles,
                          int* counter, const TablesDev& T, const LutDev& L, int grid,
                          hipStream_t s) {
   using C = TileCfg<TW, TH, PPT>;
   hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, counter);
-  hipLaunchKernelGGL((k_render_batch<TW, TH, PPT>), dim3(grid), dim3(C::kThreads), 0, s, views,
-                     runs, nruns, ntiles, counter, T, L);
+  hipLaunchKernelGGL((k_render_batch<TW, TH, PPT, ANIM>), dim3(grid), dim3(C::kThreads), 0, s,
+                     views, runs, nruns, ntiles, counter, T, L);
 }
 
-template <int TW, int TH, int PPT>
+template <int TW, int TH, int PPT, bool ANIM>
 static void launch_list(const ViewDev* views, const TileRun* runs, int nruns, int ntiles,
                         const TablesDev& T, const LutDev& L, hipStream_t s) {
   using C = TileCfg<TW, TH, PPT>;
   int per_xcd = (ntiles + 7) / 8;
-  hipLaunchKernelGGL((k_render_list<TW, TH, PPT>), dim3(8 * per_xcd), dim3(C::kThreads), 0, s,
-                     views, runs, nruns, ntiles, per_xcd, T, L);
+  hipLaunchKernelGGL((k_render_list<TW, TH, PPT, ANIM>), dim3(8 * per_xcd), dim3(C::kThreads),
+                     0, s, views, runs, nruns, ntiles, per_xcd, T, L);
 }
 
-#define BH_TILE(TW, TH, PPT)                                                         \
-  {TW, TH, TileCfg<TW, TH, PPT>::kWaves, PPT, launch_plain<TW, TH, PPT>,             \
-   launch_batch<TW, TH, PPT>, launch_list<TW, TH, PPT>}
+#define BH_TILE(TW, TH, PPT)                                                                \
+  {TW, TH, TileCfg<TW, TH, PPT>::kWaves, PPT,                                               \
+   {launch_plain<TW, TH, PPT, false>, launch_plain<TW, TH, PPT, true>},                     \
+   {launch_batch<TW, TH, PPT, false>, launch_batch<TW, TH, PPT, true>},                     \
+   {launch_list<TW, TH, PPT, false>, launch_list<TW, TH, PPT, true>}}
 
 static const TileEntry kTiles[] = {
     BH_TILE(16, 16, 1), BH_TILE(32, 8, 1), BH_TILE(16, 8, 1), BH_TILE(8, 8, 1),
@@ -598,20 +687,21 @@ void tile_config(int i, int* tw, int* th, int* waves, int* ppt) {
 
 hipError_t launch_render(int cfg, const ViewDev& v, const TablesDev& T, const LutDev& L,
                          hipStream_t s) {
-  kTiles[cfg].plain(v, T, L, s);
+  kTiles[cfg].plain[v.density_mode != 0](v, T, L, s);
   return hipGetLastError();
 }
 
 // persistent != 0: `grid` persistent workgroups pulling tiles from an atomic counter;
 // otherwise one workgroup per tile.
-hipError_t launch_render_batch(int cfg, int persistent, const ViewDev* views,
+hipError_t launch_render_batch(int cfg, int persistent, int anim, const ViewDev* views,
                                const TileRun* runs, int nruns, int ntiles, int* counter,
                                const TablesDev& T, const LutDev& L, int grid, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
+  int a = anim != 0;
   if (persistent)
-    kTiles[cfg].batch(views, runs, nruns, ntiles, counter, T, L, grid, s);
+    kTiles[cfg].batch[a](views, runs, nruns, ntiles, counter, T, L, grid, s);
   else
-    kTiles[cfg].list(views, runs, nruns, ntiles, T, L, s);
+    kTiles[cfg].list[a](views, runs, nruns, ntiles, T, L, s);
   return hipGetLastError();
 }
 
@@ -627,10 +717,13 @@ hipError_t launch_render_count(const ViewDev& v, const TablesDev& T, const LutDe
 }
 
 hipError_t launch_trace_rays(const TablesDev& T, const float* rays, int64_t n, float4* out,
-                             hipStream_t s) {
+                             float4* out_time, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_trace_rays, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, T, rays,
-                     n, out);
+  dim3 grid((unsigned)((n + 255) / 256));
+  if (out_time)
+    hipLaunchKernelGGL(k_trace_rays<true>, grid, dim3(256), 0, s, T, rays, n, out, out_time);
+  else
+    hipLaunchKernelGGL(k_trace_rays<false>, grid, dim3(256), 0, s, T, rays, n, out, out_time);
   return hipGetLastError();
 }
 

@@ -43,10 +43,32 @@ def test_tile_configs_are_wave_multiples(lib):
         bh.bh_tile_config_get(n)
 
 
-def test_structs_match_header_layout(lib):
+def _c_layout(tmp_path, struct, fields):
+    """sizeof and offsetof of a bh.h record, from a C program compiled against the header."""
+    import subprocess
+    src = tmp_path / "layout.c"
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "bh.h"', "int main(void) {",
+             '  printf("%%zu\\n", sizeof(%s));' % struct]
+    lines += ['  printf("%%zu\\n", offsetof(%s, %s));' % (struct, f) for f in fields]
+    lines += ["  return 0;", "}"]
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True)
+    vals = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True,
+                                            text=True).stdout.split()]
+    return vals[0], dict(zip(fields, vals[1:]))
+
+
+@pytest.mark.parametrize("name", ["View", "TableParams", "StarField", "TileConfig", "ServeParams"])
+def test_structs_match_header_layout(tmp_path, name):
+    """The ctypes records of the binding have the C layout of include/bh.h, field by field."""
     import ctypes as C
-    # bh_view: 3 doubles of position ... stars pointer last; 8-byte aligned record
-    assert C.sizeof(bh.View) % 8 == 0
-    assert bh.View.stars.offset == C.sizeof(bh.View) - 8
-    assert C.sizeof(bh.TableParams) == 32
-    assert C.sizeof(bh.StarField) == 48
+    cls = getattr(bh, name)
+    cname = {"View": "bh_view", "TableParams": "bh_table_params", "StarField": "bh_star_field",
+             "TileConfig": "bh_tile_config", "ServeParams": "bh_serve_params"}[name]
+    fields = [f[0] for f in cls._fields_]
+    size, offs = _c_layout(tmp_path, cname, fields)
+    assert C.sizeof(cls) == size
+    for f in fields:
+        assert getattr(cls, f).offset == offs[f], f
