@@ -224,7 +224,10 @@ bh_status bh_serve_start(bh_ctx* ctx, const bh_serve_params* p);
  * bh_poll returns it; it is freed by bh_ticket_free. */
 bh_status bh_submit(bh_ctx* ctx, const bh_tables* t, const bh_view* v, float* out_rgba_dev,
                     uint64_t* ticket);
-/* done = 1 when the frame is complete on the device; latency_s = completion - submit. */
+/* done = 1 when the frame is complete on the device (or has failed); latency_s =
+ * completion - submit.  Returns the request's status: BH_OK, BH_ENOMEM (its library image
+ * can never fit: nothing else holds or pools budget), BH_EDEVICE (its launch failed) or
+ * BH_ECANCELED (the context was destroyed first); BH_ENOTFOUND for an unknown ticket. */
 bh_status bh_poll(bh_ctx* ctx, uint64_t ticket, int32_t* done, double* latency_s);
 /* Image of a finished ticket that was submitted with out_rgba_dev = NULL. */
 bh_status bh_ticket_image(bh_ctx* ctx, uint64_t ticket, float** out_rgba_dev);

@@ -151,6 +151,7 @@ struct bh_ctx {
   int persistent = 0;  // batched launches: 1 = persistent workgroups, 0 = one per tile
   // recycled library-allocated images (serving), counted in `used`
   std::multimap<size_t, void*> pool;
+  int64_t owned_live = 0;  // library-allocated images held by requests (not yet freed)
   // stream-ordered memory pool of the library-allocated images: allocation and release on
   // the serving stream never wait for the device
   hipMemPool_t img_pool = nullptr;
@@ -408,6 +409,18 @@ extern "C" bh_status bh_create_particles(bh_ctx* c, const double* tr, int32_t n,
                              (float)std::sqrt(ubar * ubar * ubar / 2.0));
     rec[2 * j + 1] = make_float4((float)ph0, (float)(rp - 1.0), (float)(ra + 1.0), 0.0f);
   }
+  // sorted by the inner end of their radial reach, so a crossing stops at the first
+  // particle that starts beyond it
+  std::vector<int> order(n);
+  for (int32_t j = 0; j < n; ++j) order[j] = j;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return rec[2 * a + 1].y < rec[2 * b + 1].y; });
+  std::vector<float4> sorted(rec.size());
+  for (int32_t j = 0; j < n; ++j) {
+    sorted[2 * j] = rec[2 * order[j]];
+    sorted[2 * j + 1] = rec[2 * order[j] + 1];
+  }
+  rec.swap(sorted);
   HIPCHK(hipSetDevice(c->device));
   std::lock_guard<std::mutex> g(c->mu);
   auto* p = new bh_particles;
@@ -1075,9 +1088,20 @@ static void serve_loop(bh_ctx* c) {
         ServeReq* r = c->queue.front();
         if (!r->out) {
           void* p = pool_get(c, r->out_bytes);
-          if (!p) break;
+          if (!p) {
+            if (c->owned_live > 0) break;  // wait for the client to free an image
+            // nothing held and nothing pooled: the image can never be allocated
+            r->status = BH_ENOMEM;
+            r->done = true;
+            r->t_done = now_s();
+            c->pending--;
+            c->queue.pop_front();
+            c->done_cv.notify_all();
+            continue;
+          }
           r->out = (float*)p;
           r->owned = true;
+          c->owned_live++;
         }
         r->admitted = true;
         c->queue.pop_front();
@@ -1259,6 +1283,7 @@ static void serve_stop(bh_ctx* c) {
     if (kv.second->owned) {
       (void)hipFreeAsync(kv.second->out, c->serve_stream);
       c->used -= kv.second->out_bytes;
+      c->owned_live--;
     }
     delete kv.second;
   }
@@ -1330,7 +1355,10 @@ extern "C" bh_status bh_ticket_free(bh_ctx* c, uint64_t ticket) {
   auto it = c->reqs.find(ticket);
   if (it == c->reqs.end()) return fail(BH_ENOTFOUND, "unknown ticket");
   if (!it->second->done) return fail(BH_EAGAIN, "not finished");
-  if (it->second->owned) pool_put(c, it->second->out, it->second->out_bytes);
+  if (it->second->owned) {
+    pool_put(c, it->second->out, it->second->out_bytes);
+    c->owned_live--;
+  }
   delete it->second;
   c->reqs.erase(it);
   c->scv.notify_all();  // freed budget may admit queued requests

@@ -241,14 +241,15 @@ __device__ __forceinline__ float fatan2_any(float y, float x) {
 // particle j's point a = (hphi - phi_j(ht)) mod 2 pi, phi_j(t) = omega_j t + phi0_j, has
 // u_a = u1 + (u2 - u1) sin^2(c_j (a + phi_j(ht))); d^2 = (a/pi - 1)^2 + (hr - 1/u_a)^2 and
 // the particle adds (1 - d^2)^2 inside d < 1.  Particle records (two float4 each):
-// (u1, u2 - u1, c, omega), (phi0, r_peri - 1, r_apo + 1, 0); the radial bounds skip
-// particles that cannot reach d < 1.
+// (u1, u2 - u1, c, omega), (phi0, r_peri - 1, r_apo + 1, 0), sorted by r_peri - 1; the
+// radial bounds skip particles that cannot reach d < 1.
 __device__ __forceinline__ float disc_density(const ViewDev& v, float ht, float hr, float hphi) {
   const float k2Pi = 2.0f * kPi;
   float rho = 0.0f;
   for (int j = 0; j < v.nparts; ++j) {
     float4 p0 = v.parts[2 * j], p1 = v.parts[2 * j + 1];
-    if (hr < p1.y || hr > p1.z) continue;
+    if (hr < p1.y) break;  // this and every later particle starts beyond hr
+    if (hr > p1.z) continue;
     float ph = fmaf(p0.w, ht, p1.x);
     float a = hphi - ph;
     a -= k2Pi * floorf(a * (1.0f / k2Pi));

@@ -249,3 +249,36 @@ def test_serving_admits_by_hbm_budget(gpu_ctx, gpu_tables):
     for t, v in zip(tickets, views):
         ref, _ = parity.render_gpu(gpu_ctx, gpu_tables, v, None, aov=False)
         assert np.array_equal(images[t], ref)
+
+
+def test_serving_fails_a_frame_that_can_never_fit(gpu_tables):
+    """A library-allocated image that fits the budget on paper but not beside the resident
+    resources, with nothing else holding budget: the request fails with BH_ENOMEM instead of
+    waiting forever, and the server keeps serving frames with caller-owned images."""
+    import torch
+    probe = bh.bh_create(0, 0)
+    try:
+        bh.bh_precompute_tables(probe, 512, 64, 32, bh.BH_TAB_FP64_BAND, 0.05)
+        base = bh.bh_bytes_in_use(probe)
+    finally:
+        bh.bh_destroy(probe)
+    ctx = bh.bh_create(0, base + 2048)
+    try:
+        tables = bh.bh_precompute_tables(ctx, 512, 64, 32, bh.BH_TAB_FP64_BAND, 0.05)
+        bh.bh_serve_start(ctx, 0, 2, 64)
+        v = scenes.small_static_view()
+        v.width, v.height = 16, 16           # 4 KiB image: within the budget by itself
+        t = bh.bh_submit(ctx, tables, bh.make_view(v), None)
+        out = torch.zeros((16, 16, 4), dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        t2 = bh.bh_submit(ctx, tables, bh.make_view(v), out.data_ptr())
+        bh.bh_serve_drain(ctx)
+        with pytest.raises(bh.BhError) as ei:
+            bh.bh_poll(ctx, t)
+        assert ei.value.status == bh.BH_ENOMEM
+        assert bh.bh_poll(ctx, t2)[0]
+        bh.bh_ticket_free(ctx, t)
+        bh.bh_ticket_free(ctx, t2)
+        assert np.isfinite(out.cpu().numpy()).all()
+    finally:
+        bh.bh_destroy(ctx)
