@@ -517,15 +517,35 @@ __device__ __forceinline__ void render_tile(const ViewDev& v, const TablesDev& T
   }
 }
 
-// One launch per view: blocks map to tiles in an XCD-aware order (consecutive tile rows go
-// to the same XCD, whose L2 then holds the cube-map region they share).
+// XCD-aware tile order.  Workgroup b runs on XCD b % 8.  The image's tiles are grouped in
+// blocks of kXBW x kXBH tiles that stay on one XCD (neighbouring tiles share that XCD's L2),
+// and the blocks are dealt to the 8 XCDs in turn, so every XCD gets work from all over the
+// image: per-tile cost varies strongly across a frame (shadow, disc, star field), and one
+// band of rows per XCD left the lightest XCDs idle for ~10% of the frame.
+constexpr int kXBW = 4, kXBH = 2;
+
+__device__ __forceinline__ bool xcd_tile(int b, int tiles_x, int tiles_y, int* col, int* row) {
+  int x = b & 7, k = b >> 3;
+  int bx = (tiles_x + kXBW - 1) / kXBW;
+  int blk = x + 8 * (k / (kXBW * kXBH)), q = k % (kXBW * kXBH);
+  *row = (blk / bx) * kXBH + q / kXBW;
+  *col = (blk % bx) * kXBW + q % kXBW;
+  return *col < tiles_x && *row < tiles_y;
+}
+
+// workgroups of a plain launch over tiles_x x tiles_y tiles (a multiple of 8)
+static inline int xcd_grid(int tiles_x, int tiles_y) {
+  int nblk = ((tiles_x + kXBW - 1) / kXBW) * ((tiles_y + kXBH - 1) / kXBH);
+  return ((nblk + 7) / 8) * 8 * kXBW * kXBH;
+}
+
+// One launch per view, tiles in the XCD-aware order above.
 template <int TW, int TH, int PPT, bool ANIM>
 __global__ void __launch_bounds__((TW / 8) * (TH / 8) * 64 / PPT)
-    k_render(ViewDev v, TablesDev T, LutDev L, int tiles_x, int ntiles, int per_xcd) {
-  int b = blockIdx.x;
-  int tile = (b & 7) * per_xcd + (b >> 3);
-  if (tile >= ntiles) return;
-  render_tile<TW, TH, PPT, false, ANIM>(v, T, L, (tile % tiles_x) * TW, (tile / tiles_x) * TH);
+    k_render(ViewDev v, TablesDev T, LutDev L, int tiles_x, int tiles_y) {
+  int col, row;
+  if (!xcd_tile(blockIdx.x, tiles_x, tiles_y, &col, &row)) return;
+  render_tile<TW, TH, PPT, false, ANIM>(v, T, L, col * TW, row * TH);
 }
 
 // The run holding flat tile index `it` (wave-uniform): the last run whose start is <= it.
@@ -575,14 +595,18 @@ __global__ void __launch_bounds__((TW / 8) * (TH / 8) * 64 / PPT)
   }
 }
 
-// Tiles of many views without persistence: one workgroup per flat tile index, XCD-aware
-// order.
+// Tiles of many views without persistence: one workgroup per flat tile index.  Chunks of
+// kXChunk consecutive flat tiles (a row segment of one view) stay on one XCD and the chunks
+// are dealt to the 8 XCDs in turn, as in the plain launch.
+constexpr int kXChunk = kXBW * kXBH;
+
 template <int TW, int TH, int PPT, bool ANIM>
 __global__ void __launch_bounds__((TW / 8) * (TH / 8) * 64 / PPT)
     k_render_list(const ViewDev* __restrict__ views, const TileRun* __restrict__ runs,
-                  int nruns, int ntiles, int per_xcd, TablesDev T, LutDev L) {
+                  int nruns, int ntiles, TablesDev T, LutDev L) {
   int b = blockIdx.x;
-  int it = (b & 7) * per_xcd + (b >> 3);
+  int k = b >> 3;
+  int it = (k / kXChunk) * (8 * kXChunk) + (b & 7) * kXChunk + k % kXChunk;
   if (it >= ntiles) return;
   render_flat_tile<TW, TH, PPT, ANIM>(views, runs, nruns, it, T, L);
 }
@@ -642,10 +666,8 @@ template <int TW, int TH, int PPT, bool ANIM>
 static void launch_plain(const ViewDev& v, const TablesDev& T, const LutDev& L, hipStream_t s) {
   using C = TileCfg<TW, TH, PPT>;
   int tiles_x = (v.width + TW - 1) / TW, tiles_y = (v.height + TH - 1) / TH;
-  int ntiles = tiles_x * tiles_y;
-  int per_xcd = (ntiles + 7) / 8;
-  hipLaunchKernelGGL((k_render<TW, TH, PPT, ANIM>), dim3(8 * per_xcd), dim3(C::kThreads), 0, s,
-                     v, T, L, tiles_x, ntiles, per_xcd);
+  hipLaunchKernelGGL((k_render<TW, TH, PPT, ANIM>), dim3(xcd_grid(tiles_x, tiles_y)),
+                     dim3(C::kThreads), 0, s, v, T, L, tiles_x, tiles_y);
 }
 
 template <int TW, int TH, int PPT, bool ANIM>
@@ -662,9 +684,9 @@ template <int TW, int TH, int PPT, bool ANIM>
 static void launch_list(const ViewDev* views, const TileRun* runs, int nruns, int ntiles,
                         const TablesDev& T, const LutDev& L, hipStream_t s) {
   using C = TileCfg<TW, TH, PPT>;
-  int per_xcd = (ntiles + 7) / 8;
-  hipLaunchKernelGGL((k_render_list<TW, TH, PPT, ANIM>), dim3(8 * per_xcd), dim3(C::kThreads),
-                     0, s, views, runs, nruns, ntiles, per_xcd, T, L);
+  int grid = (ntiles + 8 * kXChunk - 1) / (8 * kXChunk) * (8 * kXChunk);
+  hipLaunchKernelGGL((k_render_list<TW, TH, PPT, ANIM>), dim3(grid), dim3(C::kThreads), 0, s,
+                     views, runs, nruns, ntiles, T, L);
 }
 
 #define BH_TILE(TW, TH, PPT)                                                                \
