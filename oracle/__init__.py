@@ -31,7 +31,7 @@ class OrcView(C.Structure):
 class OrcRay(C.Structure):
     _fields_ = [("delta_prime", C.c_double), ("captured", C.c_int32), ("n_cross", C.c_int32),
                 ("u_cross", C.c_double * 4), ("phi_cross", C.c_double * 4),
-                ("branch", C.c_int32 * 4), ("steps", C.c_int32), ("pad0", C.c_int32),
+                ("branch", C.c_int32 * 4), ("steps", C.c_int32), ("unfinished", C.c_int32),
                 ("t_cross", C.c_double * 4)]
 
 
@@ -100,6 +100,15 @@ def lib():
         L.orc_particle_u.argtypes = [dp, C.c_double, C.c_double]
         L.orc_disc_density.restype = C.c_double
         L.orc_disc_density.argtypes = [dp, C.c_int32, C.c_double, C.c_double, C.c_double]
+        L.orc_march_ray.argtypes = [C.c_double] * 5 + [C.c_int32, C.c_double, C.POINTER(OrcRay)]
+        L.orc_march_state.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int32, C.c_double,
+                                      dp, dp]
+        L.orc_hermite.restype = C.c_double
+        L.orc_hermite.argtypes = [C.c_double] * 6
+        L.orc_hermite_first_root.restype = C.c_double
+        L.orc_hermite_first_root.argtypes = [C.c_double] * 5
+        L.orc_render_quads_m.argtypes = [C.POINTER(OrcView), dp, C.c_int32, C.c_int32,
+                                         C.POINTER(C.c_int32), C.c_int64, C.c_void_p, C.c_int]
         for f in ("orc_sizeof_pixel", "orc_sizeof_ray", "orc_sizeof_view"):
             getattr(L, f).restype = C.c_int64
         _check_layout(L)
@@ -134,6 +143,7 @@ def _ray_dict(r: OrcRay):
     return {"delta_prime": r.delta_prime, "captured": bool(r.captured), "n_cross": n,
             "u": [r.u_cross[k] for k in range(n)], "phi": [r.phi_cross[k] for k in range(n)],
             "branch": [r.branch[k] for k in range(n)], "steps": r.steps,
+            "unfinished": bool(r.unfinished),
             "t": [r.t_cross[k] for k in range(n)]}
 
 
@@ -141,6 +151,28 @@ def trace_exact(u_c, delta, alpha, u_ic, u_oc, gr=1.0):
     r = OrcRay()
     lib().orc_trace_exact(u_c, delta, alpha, u_ic, u_oc, gr, C.byref(r))
     return _ray_dict(r)
+
+
+def march(u_c, delta, alpha, u_ic, u_oc, nsteps, gr=1.0):
+    """Ray marching (fixed-step RK4, h = 2 pi / nsteps) in place of TraceRay."""
+    r = OrcRay()
+    if lib().orc_march_ray(u_c, delta, alpha, u_ic, u_oc, nsteps, gr, C.byref(r)):
+        raise ValueError("bad step count")
+    return _ray_dict(r)
+
+
+def march_state(u0, w0, h, k, gr=1.0):
+    u, w = C.c_double(), C.c_double()
+    lib().orc_march_state(u0, w0, h, k, gr, C.byref(u), C.byref(w))
+    return u.value, w.value
+
+
+def hermite(p0, m0, p1, m1, h, s):
+    return lib().orc_hermite(p0, m0, p1, m1, h, s)
+
+
+def hermite_first_root(p0, m0, p1, m1, h):
+    return lib().orc_hermite_first_root(p0, m0, p1, m1, h)
 
 
 class Tables:
@@ -263,12 +295,20 @@ def to_orc_view(v) -> OrcView:
 
 
 def render_quads(view, quads: np.ndarray, cube: np.ndarray = None, n0: int = 0,
-                 tables: Tables = None, nthreads: int = None) -> np.ndarray:
-    """Render the 4 pixels of every quad (x0, y0); returns a PIXEL_DTYPE array (4 per quad)."""
+                 tables: Tables = None, nthreads: int = None, march: int = 0) -> np.ndarray:
+    """Render the 4 pixels of every quad (x0, y0); returns a PIXEL_DTYPE array (4 per quad).
+    march > 0 replaces TraceRay by ray marching with at most that many steps."""
     q = np.ascontiguousarray(quads, np.int32)
     nq = q.shape[0]
     out = np.zeros(4 * nq, PIXEL_DTYPE)
     ov = to_orc_view(view)
+    if march > 0:
+        rc = lib().orc_render_quads_m(C.byref(ov), _dp(cube) if cube is not None else None, n0,
+                                      march, q.ctypes.data_as(C.POINTER(C.c_int32)), nq,
+                                      out.ctypes.data, nthreads or threads())
+        if rc:
+            raise ValueError("orc_render_quads_m rejected the view")
+        return out
     D = U = Dt = Ut = None
     dn = une = unphi = 0
     if tables is not None:

@@ -59,8 +59,9 @@ typedef struct {
   double u_cross[4];
   double phi_cross[4];    /* rotated azimuth of each crossing                           */
   int32_t branch[4];      /* 0: before the apsis of the backward ray, 1: after it       */
-  int32_t steps;          /* accepted integrator steps (exact mode), 0 in table mode    */
-  int32_t pad0;
+  int32_t steps;          /* accepted integrator steps (exact mode, marching), 0 in
+                             table mode                                                  */
+  int32_t unfinished;     /* marching: the step budget ran out (drawn as captured)      */
   double t_cross[4];      /* retarded time: coordinate time from the crossing to the
                              camera (exact mode; table mode with time channels)          */
 } orc_ray;
@@ -97,6 +98,17 @@ int orc_trace_exact(double u_c, double delta, double alpha, double u_ic, double 
                     double gr, orc_ray* out);        /* gr = 1: Schwarzschild, 0: flat */
 double orc_deflection(double e);                     /* 2 phi_a - pi for a ray from infinity */
 double orc_u_at_phi(double u0, double w0, double phi, double gr); /* u(phi) along a ray */
+
+/* ---- ray marching (the ablation of Section 6, method M3 of Table 1) ----------------- */
+/* fixed-step fourth-order Runge-Kutta in phi, h = 2 pi / nsteps, at most nsteps steps;
+ * events from the cubic Hermite interpolant of each step (see march.c) */
+int orc_march_ray(double u_c, double delta, double alpha, double u_ic, double u_oc,
+                  int32_t nsteps, double gr, orc_ray* out);
+/* the bare integrator: k steps of size h from (u0, w0) */
+void orc_march_state(double u0, double w0, double h, int32_t k, double gr, double* u,
+                     double* w);
+double orc_hermite(double p0, double m0, double p1, double m1, double h, double s);
+double orc_hermite_first_root(double p0, double m0, double p1, double m1, double h);
 
 /* ---- tables by quadrature (table mode) ---------------------------------------------- */
 int orc_tables(int32_t d_n, int32_t u_ne, int32_t u_nphi, double* D, double* U, int nthreads);
@@ -136,6 +148,11 @@ int orc_render_quads_t(const orc_view* v, const double* cubemap, int32_t n0,
                        const double* D, const double* Dt, int32_t d_n, const double* U,
                        const double* Ut, int32_t u_ne, int32_t u_nphi, const int32_t* quads,
                        int64_t nq, orc_pixel* out, int nthreads);
+
+/* the same with TraceRay replaced by ray marching with at most march_steps steps */
+int orc_render_quads_m(const orc_view* v, const double* cubemap, int32_t n0,
+                       int32_t march_steps, const int32_t* quads, int64_t nq, orc_pixel* out,
+                       int nthreads);
 
 /* ---- animated disc (Appendix B) ------------------------------------------------------- */
 double orc_ellipk(double kappa);                     /* complete elliptic integral K */

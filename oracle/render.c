@@ -102,6 +102,7 @@ typedef struct {
   int32_t n0, nl;
   const double *D, *U, *Dt, *Ut;
   int32_t d_n, u_ne, u_nphi;
+  int32_t march; /* > 0: ray marching with at most this many steps instead of TraceRay */
 } ctx_t;
 
 static void trace_pixel(const ctx_t* c, int32_t x, int32_t y, ray_out* o) {
@@ -136,7 +137,10 @@ static void trace_pixel(const ctx_t* c, int32_t x, int32_t y, ray_out* o) {
   o->delta = delta;
   if (ncz < 1e-14 * norm3(d)) {
     o->degenerate = 1;
-    orc_trace_exact(s->u_c, delta, 0.0, -1.0, 2.0, 1.0, &o->ray);
+    if (c->march > 0)
+      orc_march_ray(s->u_c, delta, 0.0, -1.0, 2.0, c->march, 1.0, &o->ray);
+    else
+      orc_trace_exact(s->u_c, delta, 0.0, -1.0, 2.0, 1.0, &o->ray);
     o->captured = o->ray.captured;
     o->e2 = s->u_c * s->u_c * (1.0 - s->u_c);
     for (int i = 0; i < 3; ++i) o->dprime[i] = cos(o->ray.delta_prime) * s->rhat[i];
@@ -166,7 +170,9 @@ static void trace_pixel(const ctx_t* c, int32_t x, int32_t y, ray_out* o) {
   o->zeta = ez[2];
   double cot = dot3(s->rhat, d) / ncz;
   o->e2 = s->u_c * s->u_c * cot * cot + s->u_c * s->u_c * (1.0 - s->u_c);
-  if (c->D)
+  if (c->march > 0)
+    orc_march_ray(s->u_c, delta, alpha, u_ic, u_oc, c->march, 1.0, &o->ray);
+  else if (c->D)
     orc_trace_table_t(c->D, c->Dt, c->d_n, c->U, c->Ut, c->u_ne, c->u_nphi, s->u_c, delta,
                       alpha, u_ic, u_oc, &o->ray);
   else
@@ -362,10 +368,30 @@ int orc_render_quads(const orc_view* v, const double* cube, int32_t n0, const do
                             nthreads);
 }
 
+static int render_quads(const orc_view* v, const double* cube, int32_t n0, const double* D,
+                        const double* Dt, int32_t d_n, const double* U, const double* Ut,
+                        int32_t u_ne, int32_t u_nphi, int32_t march, const int32_t* quads,
+                        int64_t nq, orc_pixel* out, int nthreads);
+
 int orc_render_quads_t(const orc_view* v, const double* cube, int32_t n0, const double* D,
                        const double* Dt, int32_t d_n, const double* U, const double* Ut,
                        int32_t u_ne, int32_t u_nphi, const int32_t* quads, int64_t nq,
                        orc_pixel* out, int nthreads) {
+  return render_quads(v, cube, n0, D, Dt, d_n, U, Ut, u_ne, u_nphi, 0, quads, nq, out,
+                      nthreads);
+}
+
+int orc_render_quads_m(const orc_view* v, const double* cube, int32_t n0, int32_t march_steps,
+                       const int32_t* quads, int64_t nq, orc_pixel* out, int nthreads) {
+  if (march_steps < 1 || v->disc_density != 0) return 1;
+  return render_quads(v, cube, n0, NULL, NULL, 0, NULL, NULL, 0, 0, march_steps, quads, nq,
+                      out, nthreads);
+}
+
+static int render_quads(const orc_view* v, const double* cube, int32_t n0, const double* D,
+                        const double* Dt, int32_t d_n, const double* U, const double* Ut,
+                        int32_t u_ne, int32_t u_nphi, int32_t march, const int32_t* quads,
+                        int64_t nq, orc_pixel* out, int nthreads) {
   if (!(v->r_s > 0) || v->width < 1 || v->height < 1) return 1;
   if (v->disc_density == 1 && (v->n_particles < 0 || (v->n_particles > 0 && !v->particles) ||
                                (D && (!Dt || !Ut))))
@@ -387,6 +413,7 @@ int orc_render_quads_t(const orc_view* v, const double* cube, int32_t n0, const 
   c.d_n = d_n;
   c.u_ne = u_ne;
   c.u_nphi = u_nphi;
+  c.march = march;
   if (nthreads < 1) nthreads = 1;
   if (nthreads > 256) nthreads = 256;
   rjob j = {&c, quads, nq, out, 0, PTHREAD_MUTEX_INITIALIZER};
