@@ -7,10 +7,12 @@ integrated on the GPU with the FP64 photon-sphere band; FP32 trace.  A step is o
 the whole per-pixel path (beam init, TraceRay, disc, derivatives, star gather, compose) on
 device-resident inputs; tables and star map are built once, before timing.
 
-Also reported: the batched form (64 uneven views in one persistent launch) and the served
-form (Poisson arrivals, continuous batching) against one launch per frame, the roofline of
-the render kernel (algorithmic HBM bytes from a footprint-counting pass, kernel duration
-from HIP events on the launch stream) and the FP64 CPU oracle on one full frame.
+Also reported: the ablation of Section 6 (TraceRay replaced by RK4 ray marching at several
+step budgets: frame time and escape-angle accuracy), the batched form (64 uneven views in
+one persistent launch) and the served form (Poisson arrivals, continuous batching) against
+one launch per frame, the roofline of the render kernel (algorithmic HBM bytes from a
+footprint-counting pass, kernel duration from HIP events on the launch stream) and the FP64
+CPU oracle on one full frame.
 """
 import argparse
 import json
@@ -233,13 +235,63 @@ def cpu_baseline(view_obj, field, n0, min_seconds=10.0):
             "seconds": dt}
 
 
+def march_leg(bh, view, ctx, tables, W, H, reps=30):
+    """The ablation of Section 6 (method M3 of Table 1): the same frame with TraceRay
+    replaced by RK4 ray marching at several step budgets.  Frame time from HIP events on
+    the launch stream; accuracy of the escape angle delta' (from the AOV) of the tables and of
+    each budget against a 4096-step march, over pixels that escape on both sides."""
+    import numpy as np
+    import torch
+    st = bh.current_stream()
+    out = torch.empty((H, W, 4), dtype=torch.float32, device="cuda")
+
+    def frame_us(fn):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return 1e3 * e0.elapsed_time(e1) / reps
+
+    def aov_of(fn):
+        a = torch.empty((H, W, 4), dtype=torch.float32, device="cuda")
+        fn(a.data_ptr())
+        torch.cuda.synchronize()
+        return a.cpu().numpy().reshape(-1, 4)
+
+    ref = aov_of(lambda a: bh.bh_render_march(ctx, view, 4096, out.data_ptr(), a, st))
+    bad = bh.BH_AOV_CAPTURED | bh.BH_AOV_DEGENERATE | bh.BH_AOV_UNFINISHED
+
+    def err(a):
+        ok = ((a[:, 3].copy().view(np.uint32) | ref[:, 3].copy().view(np.uint32)) & bad) == 0
+        d = np.abs(a[ok, 0].astype(np.float64) - ref[ok, 0])
+        return {"dprime_p50": float(np.percentile(d, 50)), "dprime_p99": float(np.percentile(d, 99)),
+                "pixels": int(ok.sum())}
+
+    res = {"reference": "4096-step march", "tables": {
+        "us_per_frame": frame_us(lambda: bh.bh_render(ctx, tables, view, out.data_ptr(), None, st)),
+        **err(aov_of(lambda a: bh.bh_render(ctx, tables, view, out.data_ptr(), a, st)))}}
+    for n in (16, 25, 50, 100):
+        res["march%d" % n] = {
+            "us_per_frame": frame_us(lambda: bh.bh_render_march(ctx, view, n, out.data_ptr(), None, st)),
+            **err(aov_of(lambda a: bh.bh_render_march(ctx, view, n, out.data_ptr(), a, st)))}
+    for k, v in res.items():
+        if isinstance(v, dict):
+            v["mpx_per_s"] = W * H / v["us_per_frame"]
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--legs", default="plain,anim,batch,serve,cpu",
-                    help="comma list of plain, anim, batch, serve, cpu")
+    ap.add_argument("--legs", default="plain,anim,march,batch,serve,cpu",
+                    help="comma list of plain, anim, march, batch, serve, cpu")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--serve-tiles", type=int, default=262144,
                     help="most 16x16 tiles in one serving launch")
@@ -339,6 +391,9 @@ def main():
                              "mpx_per_s": W * H * n_a / awall / 1e6}
         bh.bh_release_particles(ph)
         log("animated:", json.dumps(extra["animated"]))
+    if "march" in legs:
+        extra["ablation_march"] = march_leg(bh, view, ctx, tables, W, H)
+        log("march ablation:", json.dumps(extra["ablation_march"]))
     if "batch" in legs:
         views = [bh.make_view(v, stars) for v in scenes.batch_views(64, 3)]
         extra["batched"] = batch_leg(bh, ctx, tables, views, reps=3)

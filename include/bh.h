@@ -172,18 +172,33 @@ typedef struct {
  *   [2] u of the second disc crossing (0 if none)
  *   [3] bit pattern (reinterpret as uint32): bit0 captured, bit1 crossing before the
  *       apsis, bit2 crossing after the apsis, bit3 star term zeroed (a member of the 2x2
- *       quad is captured), bit4 degenerate beam plane, bits 8-15 mip level (255: none). */
+ *       quad is captured), bit4 degenerate beam plane, bit5 ray marching ran out of steps
+ *       (the beam is drawn as captured), bits 8-15 mip level (255: none). */
 #define BH_AOV_CAPTURED 1u
 #define BH_AOV_CROSS0 2u
 #define BH_AOV_CROSS1 4u
 #define BH_AOV_STAR_ZEROED 8u
 #define BH_AOV_DEGENERATE 16u
+#define BH_AOV_UNFINISHED 32u
 
 /* Render one view: out_rgba_dev receives width*height float4 (R, G, B, 1) in row-major
  * order, row 0 at the top; colour = k_disc x disc band radiances composited front to back
  * over k_star x lensed, Doppler-shifted star light.  aov_dev may be NULL. */
 bh_status bh_render(bh_ctx* ctx, const bh_tables* t, const bh_view* v, float* out_rgba_dev,
                     float* aov_dev, void* hip_stream);
+
+/* The ablation of Section 6 (method M3 of Table 1): render v with TraceRay replaced by a
+ * numerical integration of the orbit equation u'' = 3/2 u^2 - u (eq. rayequation), and
+ * everything else unchanged.  Classic fourth-order Runge-Kutta in phi with the constant
+ * step 2 pi / max_steps and at most max_steps steps (one full turn of the beam plane);
+ * inside a step u(phi) is the cubic Hermite interpolant of the end states, which places the
+ * escape angle (its first root) and the disc crossings (its value at alpha + m pi).  A beam
+ * still travelling after max_steps steps is drawn as captured and flagged
+ * BH_AOV_UNFINISHED.  Needs no tables.  max_steps in [3, 1048576]; the view's disc must be
+ * BH_DENSITY_UNIFORM (marching carries no time channels).  Same output layout as
+ * bh_render. */
+bh_status bh_render_march(bh_ctx* ctx, const bh_view* v, int32_t max_steps, float* out_rgba_dev,
+                          float* aov_dev, void* hip_stream);
 
 /* Render n views of any sizes in one persistent launch (work list of tiles, replayed as
  * a HIP graph when the same shapes repeat).  outs_dev[i] has views[i].width*height float4.
@@ -250,6 +265,9 @@ bh_status bh_trace_rays(bh_ctx* ctx, const bh_tables* t, const float* rays_dev, 
  * alpha + m pi (0 where there is no crossing). */
 bh_status bh_trace_rays_timed(bh_ctx* ctx, const bh_tables* t, const float* rays_dev, int64_t n,
                               float* out_dev, float* out_time_dev, void* hip_stream);
+/* The ray marching of bh_render_march alone for n rays in the bh_trace_rays layout. */
+bh_status bh_march_rays(bh_ctx* ctx, const float* rays_dev, int64_t n, int32_t max_steps,
+                        float* out_dev, void* hip_stream);
 /* Measurement: render v once (into out_rgba_dev) with a variant of the render kernel that
  * marks every star-map texel the footprints visit, and return how many distinct texels were
  * visited (the star-map bytes one frame must read at least once).  Blocking. */

@@ -16,7 +16,8 @@
  *      capture -- u ends a step at or above 1 (the horizon);
  *      disc    -- at each disc-plane angle alpha + m pi the step passes (m = 0, 1, ...,
  *                 strictly ahead of the camera, as in exact mode) the cubic gives u; the
- *                 crossing counts when u_oc <= u <= u_ic;
+ *                 crossing counts when u_oc <= u <= u_ic; it lies after the apsis
+ *                 when the beam started inward and the cubic's slope there is negative;
  *  - a ray that has neither escaped nor been captured after N steps is unfinished and is
  *    drawn as captured (it wound more than once around the hole).
  * There is no shortcut for rays that cannot escape: every ray is integrated.
@@ -51,6 +52,13 @@ static double herm(double p0, double m0, double p1, double m1, double h, double 
   double t = s / h, t2 = t * t, t3 = t2 * t;
   return (2 * t3 - 3 * t2 + 1) * p0 + (t3 - 2 * t2 + t) * h * m0 + (-2 * t3 + 3 * t2) * p1 +
          (t3 - t2) * h * m1;
+}
+
+/* its slope d/ds */
+static double hermd(double p0, double m0, double p1, double m1, double h, double s) {
+  double t = s / h, t2 = t * t;
+  return ((6 * t2 - 6 * t) * p0 + (-6 * t2 + 6 * t) * p1) / h + (3 * t2 - 4 * t + 1) * m0 +
+         (3 * t2 - 2 * t) * m1;
 }
 
 double orc_hermite(double p0, double m0, double p1, double m1, double h, double s) {
@@ -127,6 +135,7 @@ int orc_march_ray(double u_c, double delta, double alpha, double u_ic, double u_
   }
   w = -u_c * cd / sd;
   const double h = 2.0 * M_PI / nsteps;
+  const int inward = w > 0.0; /* an apsis (largest u) can lie ahead */
   int m = 0;
   double phi_d = alpha;
   if (!(phi_d > 0.0)) {
@@ -145,6 +154,8 @@ int orc_march_ray(double u_c, double delta, double alpha, double u_ic, double u_
       if (ud >= u_oc && ud <= u_ic && o->n_cross < 4) {
         o->u_cross[o->n_cross] = ud;
         o->phi_cross[o->n_cross] = phi_d;
+        /* after the apsis: the beam started inward and u now decreases */
+        o->branch[o->n_cross] = inward && hermd(u, w, un, wn, h, phi_d - phi) < 0.0;
         o->n_cross++;
       }
       ++m;

@@ -17,7 +17,7 @@ BH_TAB_FP32, BH_TAB_FP64_BAND, BH_TAB_FP64_ALL = 0, 1, 2
 BH_TEXEL_FP16, BH_TEXEL_FP32 = 0, 1
 BH_T_POWER, BH_T_PAPER = 0, 1
 BH_AOV_CAPTURED, BH_AOV_CROSS0, BH_AOV_CROSS1 = 1, 2, 4
-BH_AOV_STAR_ZEROED, BH_AOV_DEGENERATE = 8, 16
+BH_AOV_STAR_ZEROED, BH_AOV_DEGENERATE, BH_AOV_UNFINISHED = 8, 16, 32
 BH_DENSITY_UNIFORM, BH_DENSITY_PARTICLES = 0, 1
 
 # every symbol include/bh.h declares
@@ -26,11 +26,11 @@ EXPORTS = [
     "bh_precompute_tables", "bh_tables_download", "bh_tables_download_time", "bh_release_tables",
     "bh_create_particles", "bh_release_particles",
     "bh_build_stars", "bh_stars_download", "bh_release_stars",
-    "bh_render", "bh_render_batch", "bh_tile_config_count", "bh_tile_config_get",
+    "bh_render", "bh_render_march", "bh_render_batch", "bh_tile_config_count", "bh_tile_config_get",
     "bh_set_tile_config", "bh_autotune",
     "bh_serve_start", "bh_submit", "bh_poll", "bh_ticket_image", "bh_ticket_free",
     "bh_serve_drain",
-    "bh_trace_rays", "bh_trace_rays_timed", "bh_footprint_texels", "bh_band_table_info", "bh_band_table_download", "bh_band_eval",
+    "bh_trace_rays", "bh_trace_rays_timed", "bh_march_rays", "bh_footprint_texels", "bh_band_table_info", "bh_band_table_download", "bh_band_eval",
 ]
 
 
@@ -114,6 +114,8 @@ def lib():
             "bh_serve_drain": ([vp], i32),
             "bh_trace_rays": ([vp, vp, vp, i64, vp, vp], i32),
             "bh_trace_rays_timed": ([vp, vp, vp, i64, vp, vp, vp], i32),
+            "bh_march_rays": ([vp, vp, i64, i32, vp, vp], i32),
+            "bh_render_march": ([vp, C.POINTER(View), i32, vp, vp, vp], i32),
             "bh_footprint_texels": ([vp, vp, C.POINTER(View), vp, C.POINTER(u64)], i32),
             "bh_band_table_info": ([vp, C.POINTER(i32), C.POINTER(C.c_float),
                                     C.POINTER(C.c_float)], i32),
@@ -204,6 +206,10 @@ def bh_render(ctx, tables, view: View, out_ptr, aov_ptr=None, stream=None) -> No
     _check(lib().bh_render(ctx, tables, C.byref(view), out_ptr, aov_ptr, stream))
 
 
+def bh_render_march(ctx, view: View, max_steps: int, out_ptr, aov_ptr=None, stream=None) -> None:
+    _check(lib().bh_render_march(ctx, C.byref(view), max_steps, out_ptr, aov_ptr, stream))
+
+
 def bh_render_batch(ctx, tables, views, out_ptrs, stream=None) -> None:
     n = len(views)
     arr = (View * n)(*views)
@@ -273,6 +279,10 @@ def bh_trace_rays(ctx, tables, rays_ptr, n, out_ptr, stream=None) -> None:
 
 def bh_trace_rays_timed(ctx, tables, rays_ptr, n, out_ptr, out_time_ptr, stream=None) -> None:
     _check(lib().bh_trace_rays_timed(ctx, tables, rays_ptr, n, out_ptr, out_time_ptr, stream))
+
+
+def bh_march_rays(ctx, rays_ptr, n, max_steps, out_ptr, stream=None) -> None:
+    _check(lib().bh_march_rays(ctx, rays_ptr, n, max_steps, out_ptr, stream))
 
 
 def bh_footprint_texels(ctx, tables, view: View, out_ptr) -> int:

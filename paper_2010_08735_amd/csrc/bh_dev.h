@@ -12,6 +12,7 @@
 #define BH_CROSS1_BIT BH_AOV_CROSS1
 #define BH_STAR_ZEROED_BIT BH_AOV_STAR_ZEROED
 #define BH_DEGENERATE_BIT BH_AOV_DEGENERATE
+#define BH_UNFINISHED_BIT BH_AOV_UNFINISHED
 
 namespace bh {
 
@@ -56,14 +57,14 @@ struct ViewDev {
   float vhat[3], vmag;    // camera velocity direction and speed (static frame)
   float half_w, half_h, u_ic, u_oc;
   float inv_sq1mu, T0, T_exp, rho;
-  float k_disc, k_star, T_norm, pad0;
+  float k_disc, k_star, T_norm, march_h;   // march_h: ray-marching step (marching only)
   int width, height, T_law, has_stars;
   StarsDev stars;
   float4* out;
   float4* aov;
   // animated disc: density_mode 1 = particles at the crossings' retarded times
   float time;             // camera coordinate time
-  int density_mode, nparts, pad1;
+  int density_mode, nparts, march_steps;   // march_steps: step budget (marching only)
   const float4* parts;    // 2 float4 per particle (see disc_density)
 };
 

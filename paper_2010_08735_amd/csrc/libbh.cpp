@@ -46,6 +46,9 @@ hipError_t launch_render_batch(int cfg, int persistent, int anim, const ViewDev*
                                const TablesDev& T, const LutDev& L, int grid, hipStream_t s);
 hipError_t launch_trace_rays(const TablesDev& T, const float* rays, int64_t n, float4* out,
                              float4* out_time, hipStream_t s);
+hipError_t launch_render_march(const ViewDev& v, const LutDev& L, hipStream_t s);
+hipError_t launch_march_rays(const float* rays, int64_t n, int nsteps, float h, float4* out,
+                             hipStream_t s);
 hipError_t launch_render_count(const ViewDev& v, const TablesDev& T, const LutDev& L,
                                uint32_t* touched, int64_t words, unsigned long long* total,
                                hipStream_t s);
@@ -727,6 +730,30 @@ extern "C" bh_status bh_render(bh_ctx* c, const bh_tables* t, const bh_view* v, 
   return BH_OK;
 }
 
+// Ray marching in place of TraceRay (the ablation of Section 6): h = 2 pi / max_steps.
+static bh_status check_march_steps(int32_t max_steps) {
+  if (max_steps < 3 || max_steps > (1 << 20))
+    return fail(BH_EINVAL, "max_steps must be in [3, 1048576]");
+  return BH_OK;
+}
+
+extern "C" bh_status bh_render_march(bh_ctx* c, const bh_view* v, int32_t max_steps,
+                                     float* out, float* aov, void* stream) {
+  if (!c) return fail(BH_EINVAL, "NULL context");
+  bh_status st = check_march_steps(max_steps);
+  if (st) return st;
+  ViewDev vd;
+  st = make_view(v, out, aov, &vd);
+  if (st) return st;
+  if (vd.density_mode != 0)
+    return fail(BH_EINVAL, "ray marching carries no time channels: the disc must be uniform");
+  vd.march_steps = max_steps;
+  vd.march_h = (float)(2.0 * M_PI / max_steps);
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(launch_render_march(vd, lut_dev(c), (hipStream_t)stream));
+  return BH_OK;
+}
+
 // ---- batched launches ------------------------------------------------------------------------
 
 extern "C" int32_t bh_tile_config_count(void) { return tile_config_count(); }
@@ -935,6 +962,17 @@ extern "C" bh_status bh_trace_rays(bh_ctx* c, const bh_tables* t, const float* r
   if (!c || !t || (n > 0 && (!rays || !out)) || n < 0) return fail(BH_EINVAL, "bad arguments");
   HIPCHK(hipSetDevice(c->device));
   HIPCHK(launch_trace_rays(tables_dev(t), rays, n, (float4*)out, nullptr, (hipStream_t)stream));
+  return BH_OK;
+}
+
+extern "C" bh_status bh_march_rays(bh_ctx* c, const float* rays, int64_t n, int32_t max_steps,
+                                   float* out, void* stream) {
+  if (!c || (n > 0 && (!rays || !out)) || n < 0) return fail(BH_EINVAL, "bad arguments");
+  bh_status st = check_march_steps(max_steps);
+  if (st) return st;
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(launch_march_rays(rays, n, max_steps, (float)(2.0 * M_PI / max_steps), (float4*)out,
+                           (hipStream_t)stream));
   return BH_OK;
 }
 

@@ -204,6 +204,80 @@ __device__ __forceinline__ TraceOut trace_ray(const TablesDev& T, float u, float
   return o;
 }
 
+// ---- ray marching in place of TraceRay: the ablation of Section 6 (method M3, Table 1)
+// Classic fourth-order Runge-Kutta on (u, w = du/dphi), w' = 3/2 u^2 - u (eq. rayequation),
+// with the constant step h = 2 pi / N and at most N steps.  Inside a step u is the cubic
+// Hermite interpolant of the two end states; in t = s / h, with the slopes scaled by h,
+// p(t) = ((c3 t + c2) t + a) t + p0.  Its first root places the escape (Newton from the
+// secant), its value at alpha + m pi a disc crossing.  h < pi (N >= 3): a step passes at
+// most one disc-plane angle.  A beam still travelling after N steps is drawn as captured.
+__device__ __forceinline__ float march_acc(float u) { return u * fmaf(1.5f, u, -1.0f); }
+
+__device__ __forceinline__ TraceOut march_ray(float u, float alpha, float cotd, float u_ic,
+                                              float u_oc, int nsteps, float h) {
+  TraceOut o;
+  o.ncross = 0;
+  o.ucr[0] = o.ucr[1] = 0.0f;
+  o.tret[0] = o.tret[1] = 0.0f;
+  o.mcr[0] = o.mcr[1] = 0;
+  o.bits = 0;
+  o.dprime = 0.0f;
+  float w = -u * cotd;
+  o.e = fsqrt(w * w + u * u * (1.0f - u));
+  const bool inward = w > 0.0f;  // an apsis (largest u) can lie ahead
+  const float hh = 0.5f * h, h6 = h * (1.0f / 6.0f), ih = fdiv(1.0f, h);
+  float phid = alpha > 0.0f ? alpha : alpha + kPi;  // next disc-plane angle ahead
+  for (int n = 0; n < nsteps; ++n) {
+    const float a1 = march_acc(u);
+    const float u2 = fmaf(hh, w, u), w2 = fmaf(hh, a1, w), a2 = march_acc(u2);
+    const float u3 = fmaf(hh, w2, u), w3 = fmaf(hh, a2, w), a3 = march_acc(u3);
+    const float u4 = fmaf(h, w3, u), w4 = fmaf(h, a3, w), a4 = march_acc(u4);
+    const float un = fmaf(h6, fmaf(2.0f, w2 + w3, w + w4), u);
+    const float wn = fmaf(h6, fmaf(2.0f, a2 + a3, a1 + a4), w);
+    const float phi = (float)n * h;
+    const bool esc = un < 0.0f;
+    const float td = (phid - phi) * ih;
+    if (esc || td <= 1.0f) {
+      const float A = h * w, B = h * wn;
+      const float c3 = 2.0f * (u - un) + A + B, c2 = 3.0f * (un - u) - 2.0f * A - B;
+      float tend = 1.0f;
+      if (esc) {
+        float t = fdiv(u, u - un);
+#pragma unroll
+        for (int it = 0; it < 3; ++it) {
+          float p = fmaf(fmaf(fmaf(c3, t, c2), t, A), t, u);
+          float dp = fmaf(fmaf(3.0f * c3, t, 2.0f * c2), t, A);
+          t = clampf(t - fdiv(p, dp), 0.0f, 1.0f);
+        }
+        tend = t;
+      }
+      if (td <= tend) {
+        const float ud = fmaf(fmaf(fmaf(c3, td, c2), td, A), td, u);
+        if (ud >= u_oc && ud <= u_ic) {
+          const float slope = fmaf(fmaf(3.0f * c3, td, 2.0f * c2), td, A);
+          o.bits |= inward && slope < 0.0f ? BH_CROSS1_BIT : BH_CROSS0_BIT;
+          if (o.ncross == 0) o.ucr[0] = ud;
+          else o.ucr[1] = ud;
+          o.ncross = min(o.ncross + 1, 2);
+        }
+        phid += kPi;
+      }
+      if (esc) {
+        o.dprime = fmaf(tend, h, phi);
+        return o;
+      }
+    }
+    u = un;
+    w = wn;
+    if (u >= 1.0f) {
+      o.bits |= BH_CAPTURED_BIT;
+      return o;
+    }
+  }
+  o.bits |= BH_CAPTURED_BIT | BH_UNFINISHED_BIT;
+  return o;
+}
+
 __device__ __forceinline__ float disc_temperature(const ViewDev& v, float u) {
   if (v.T_law == 1) {
     float f = u * u * u * (1.0f - sqrtf(3.0f * u));
@@ -267,7 +341,8 @@ __device__ __forceinline__ float disc_density(const ViewDev& v, float ht, float 
 // One pixel; every lane of the wave must call this together (quad exchanges).
 // COUNT: also mark every star-map texel the footprint visits in `touched` (one bit per
 // texel, measurement only).  ANIM: views may have a particle disc (retarded times).
-template <bool COUNT, bool ANIM = false>
+// MARCH: ray marching (march_ray) in place of TraceRay; no tables are read.
+template <bool COUNT, bool ANIM = false, bool MARCH = false>
 __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& T,
                                              const LutDev& L, int px, int py,
                                              uint32_t* touched) {
@@ -337,7 +412,11 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
   float zeta = cz2;
 
   // ---- TraceRay (Algorithm 1)
-  TraceOut tr = trace_ray<ANIM>(T, v.u_c, delta, alpha, dr / ncz, u_ic, u_oc);
+  TraceOut tr;
+  if constexpr (MARCH)
+    tr = march_ray(v.u_c, alpha, dr / ncz, u_ic, u_oc, v.march_steps, v.march_h);
+  else
+    tr = trace_ray<ANIM>(T, v.u_c, delta, alpha, dr / ncz, u_ic, u_oc);
   bits |= tr.bits;
   const bool captured = (tr.bits & BH_CAPTURED_BIT) != 0;
 
@@ -499,7 +578,7 @@ struct TileCfg {
   static_assert(kBX * kBY % PPT == 0, "blocks must divide by pixels per thread");
 };
 
-template <int TW, int TH, int PPT, bool COUNT = false, bool ANIM = false>
+template <int TW, int TH, int PPT, bool COUNT = false, bool ANIM = false, bool MARCH = false>
 __device__ __forceinline__ void render_tile(const ViewDev& v, const TablesDev& T, const LutDev& L,
                                             int tx0, int ty0, uint32_t* touched = nullptr) {
   using C = TileCfg<TW, TH, PPT>;
@@ -513,7 +592,7 @@ __device__ __forceinline__ void render_tile(const ViewDev& v, const TablesDev& T
     int px = tx0 + 8 * bx + ox, py = ty0 + 8 * by + oy;
     // skip 8x8 blocks entirely outside the image (uniform per wave)
     if (tx0 + 8 * bx >= v.width || ty0 + 8 * by >= v.height) continue;
-    render_pixel<COUNT, ANIM>(v, T, L, px, py, touched);
+    render_pixel<COUNT, ANIM, MARCH>(v, T, L, px, py, touched);
   }
 }
 
@@ -546,6 +625,15 @@ __global__ void __launch_bounds__((TW / 8) * (TH / 8) * 64 / PPT)
   int col, row;
   if (!xcd_tile(blockIdx.x, tiles_x, tiles_y, &col, &row)) return;
   render_tile<TW, TH, PPT, false, ANIM>(v, T, L, col * TW, row * TH);
+}
+
+// The render with ray marching in place of TraceRay (16x16 tiles, one pixel per thread).
+__global__ void __launch_bounds__(256)
+    k_render_march(ViewDev v, LutDev L, int tiles_x, int tiles_y) {
+  int col, row;
+  if (!xcd_tile(blockIdx.x, tiles_x, tiles_y, &col, &row)) return;
+  TablesDev none{};
+  render_tile<16, 16, 1, false, false, true>(v, none, L, col * 16, row * 16);
 }
 
 // The run holding flat tile index `it` (wave-uniform): the last run whose start is <= it.
@@ -650,6 +738,20 @@ __global__ void k_trace_rays(TablesDev T, const float* __restrict__ rays, int64_
     out_time[i] = make_float4(t.tret[0], t.tret[1], (float)t.mcr[0], (float)t.mcr[1]);
 }
 
+__global__ void __launch_bounds__(256)
+    k_march_rays(const float* __restrict__ rays, int64_t n, int nsteps, float h,
+                 float4* __restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float* r = rays + 5 * i;
+  float sd, cd;
+  sincosf(r[1], &sd, &cd);
+  TraceOut t = march_ray(r[0], r[2], cd / sd, r[3], r[4], nsteps, h);
+  bool cap = (t.bits & BH_CAPTURED_BIT) != 0;
+  out[i] = make_float4(cap ? __builtin_inff() : t.dprime, t.ucr[0], t.ucr[1],
+                       __uint_as_float(t.bits));
+}
+
 // ---- host-side launchers ------------------------------------------------------------------
 
 struct TileEntry {
@@ -736,6 +838,21 @@ hipError_t launch_render_count(const ViewDev& v, const TablesDev& T, const LutDe
                      touched);
   hipLaunchKernelGGL(k_popcount, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, s, touched,
                      words, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_render_march(const ViewDev& v, const LutDev& L, hipStream_t s) {
+  int tiles_x = (v.width + 15) / 16, tiles_y = (v.height + 15) / 16;
+  hipLaunchKernelGGL(k_render_march, dim3(xcd_grid(tiles_x, tiles_y)), dim3(256), 0, s, v, L,
+                     tiles_x, tiles_y);
+  return hipGetLastError();
+}
+
+hipError_t launch_march_rays(const float* rays, int64_t n, int nsteps, float h, float4* out,
+                             hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_march_rays, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, rays, n,
+                     nsteps, h, out);
   return hipGetLastError();
 }
 

@@ -123,6 +123,7 @@ def test_march_agrees_with_exact_mode_at_small_steps(orc):
         for k in keep:
             assert abs(mr["u"][k] - ex["u"][k]) < 1e-10
             assert abs(mr["phi"][k] - ex["phi"][k]) < 1e-12
+            assert mr["branch"][k] == ex["branch"][k]
         n += 1
     assert n > 200
 
