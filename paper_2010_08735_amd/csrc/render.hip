@@ -280,8 +280,8 @@ __device__ __forceinline__ TraceOut march_ray(float u, float alpha, float cotd, 
 
 __device__ __forceinline__ float disc_temperature(const ViewDev& v, float u) {
   if (v.T_law == 1) {
-    float f = u * u * u * (1.0f - sqrtf(3.0f * u));
-    return f > 0.0f ? v.T0 * sqrtf(sqrtf(f * v.T_norm)) : 0.0f;
+    float f = u * u * u * (1.0f - fsqrt(3.0f * u));
+    return f > 0.0f ? v.T0 * fsqrt(fsqrt(f * v.T_norm)) : 0.0f;
   }
   return v.T0 * __builtin_amdgcn_exp2f(-v.T_exp * __log2f(3.0f * u));
 }
@@ -350,7 +350,7 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
   // ---- beam initialisation (Section 3.2)
   float qw = (float)px + 0.5f - v.half_w;
   float qh = v.half_h - (float)py - 0.5f;
-  float inq = rsqrtf(qw * qw + qh * qh + v.f * v.f);
+  float inq = __builtin_amdgcn_rsqf(qw * qw + qh * qh + v.f * v.f);  // argument >= f^2 > 0
   float q0 = qw * inq, q1 = qh * inq, q2 = -v.f * inq;
   float nc0 = q0 * v.ew[0] + q1 * v.eh[0] + q2 * v.ed[0];
   float nc1 = q0 * v.ew[1] + q1 * v.eh[1] + q2 * v.ed[1];
@@ -365,7 +365,7 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
   float cz0 = v.rhat[1] * d2 - v.rhat[2] * d1;
   float cz1 = v.rhat[2] * d0 - v.rhat[0] * d2;
   float cz2 = v.rhat[0] * d1 - v.rhat[1] * d0;
-  float ncz = sqrtf(cz0 * cz0 + cz1 * cz1 + cz2 * cz2);
+  float ncz = fsqrt(cz0 * cz0 + cz1 * cz1 + cz2 * cz2);
   float dr = d0 * v.rhat[0] + d1 * v.rhat[1] + d2 * v.rhat[2];
   float dn = fsqrt(d0 * d0 + d1 * d1 + d2 * d2);
   unsigned bits = 0;
@@ -377,7 +377,7 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
     cz0 = v.rhat[1] * 0.0f - v.rhat[2] * ax1;
     cz1 = v.rhat[2] * ax0 - v.rhat[0] * 0.0f;
     cz2 = v.rhat[0] * ax1 - v.rhat[1] * ax0;
-    float n2 = fdiv(1.0f, sqrtf(cz0 * cz0 + cz1 * cz1 + cz2 * cz2));
+    float n2 = __builtin_amdgcn_rsqf(cz0 * cz0 + cz1 * cz1 + cz2 * cz2);
     cz0 *= n2; cz1 *= n2; cz2 *= n2;
     ncz = fmaxf(ncz, 1e-7f * dn);
     u_ic = -1.0f;
@@ -412,11 +412,12 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
   float zeta = cz2;
 
   // ---- TraceRay (Algorithm 1)
+  const float cotd = fdiv(dr, ncz);
   TraceOut tr;
   if constexpr (MARCH)
-    tr = march_ray(v.u_c, alpha, dr / ncz, u_ic, u_oc, v.march_steps, v.march_h);
+    tr = march_ray(v.u_c, alpha, cotd, u_ic, u_oc, v.march_steps, v.march_h);
   else
-    tr = trace_ray<ANIM>(T, v.u_c, delta, alpha, dr / ncz, u_ic, u_oc);
+    tr = trace_ray<ANIM>(T, v.u_c, delta, alpha, cotd, u_ic, u_oc);
   bits |= tr.bits;
   const bool captured = (tr.bits & BH_CAPTURED_BIT) != 0;
 
