@@ -45,7 +45,10 @@ struct StarsDev {
   const uint32_t* level_off;  // texel offset of each level (<= 2^32 texels)
   const uint32_t* occ;    // occupancy bits, level L at word offset occ_off[L]
   const uint32_t* occ_off;
-  int n0, levels, fp16, pad;
+  int n0, levels, fp16;
+  float one;              // 1.0 (a run-time constant, see the gather)
+  float tw0;              // 2 / n0: width of a level-0 texel in face coordinates (n0 = 2^k)
+  int pad[3];
 };
 
 // ---- per-view constant block (host computes it in FP64 from bh_view) -----------------

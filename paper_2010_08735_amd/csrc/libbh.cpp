@@ -690,6 +690,8 @@ static bh_status make_view(const bh_view* v, float* out, float* aov, ViewDev* o)
     o->stars.n0 = s->n0;
     o->stars.levels = s->levels;
     o->stars.fp16 = s->fp16;
+    o->stars.one = 1.0f;
+    o->stars.tw0 = 2.0f / (float)s->n0;
   }
   o->out = (float4*)out;
   o->aov = (float4*)aov;

@@ -40,39 +40,45 @@ struct Footprint {
   const uint32_t* occ;   // occupancy word holding (x0, y0)
   int nL, wpr, sh, ny;
   uint32_t span;         // bit mask of the footprint's columns, shifted to bit 0
-  float cu, cv, tw;      // du = (c + p_u) tw + cu, dv = (r + p_v) tw + cv
-  float i00, i01, i10, i11;  // inverse face Jacobian
+  // screen-space coordinates (w, h) of a star at (c + p_u, r + p_v) texels from the
+  // footprint's corner: w = W0 + Wc (c + p_u) + Wr (r + p_v), h = H0 + Hc (..) + Hr (..)
+  float W0, Wc, Wr, H0, Hc, Hr;
+  float one;             // 1, not known to the compiler: p_u + c stays one mixed-precision FMA
 };
 
 template <bool FP16, bool COUNT>
 __device__ __forceinline__ void gather(const void* tex, const Footprint& F, uint32_t* touched,
                                        float& A, float& B) {
-  uint64_t lo = 0;
-  uint32_t hi = 0;
+  uint32_t w0 = 0, w1 = 0, hi = 0;  // lo = w0 + 2^32 w1
   uint32_t off = 0;
   for (int r = 0; r <= F.ny; ++r, off += (uint32_t)F.wpr) {
     const uint32_t* orow = F.occ + off;
-    uint64_t two = (uint64_t)orow[0] | ((uint64_t)orow[1] << 32);
-    uint64_t b = (two >> F.sh) & F.span;
-    if (r < 7)
-      lo |= b << (9 * r);
-    else
-      hi |= (uint32_t)b << (9 * (r - 7));
+    // the row's 9 columns from bit x0 & 31 of two consecutive words (a funnel shift)
+    uint32_t b = __builtin_amdgcn_alignbit(orow[1], orow[0], (uint32_t)F.sh) & F.span;
+    if (r < 3) {
+      w0 |= b << (9 * r);
+    } else if (r == 3) {
+      w0 |= b << 27;
+      w1 |= b >> 5;
+    } else if (r < 7) {
+      w1 |= b << (9 * r - 32);
+    } else {
+      hi |= b << (9 * (r - 7));
+    }
   }
+  uint64_t lo = (uint64_t)w0 | ((uint64_t)w1 << 32);
   auto tap = [&](int idx) {
     int r = (idx * 57) >> 9;  // idx / 9 for idx < 81
     int c = idx - 9 * r;
     uint32_t t = F.texel0 + __umul24((unsigned)r, (unsigned)F.nL) + (uint32_t)c;  // nL < 2^24
     if (COUNT) atomicOr(&touched[t >> 5], 1u << (t & 31));
-    float cu = fmaf((float)c, F.tw, F.cu), cv = fmaf((float)r, F.tw, F.cv);
-    float du, dv;
+    const float fc = (float)c, fr = (float)r;
     if (FP16) {
       // half operands go straight into mixed-precision multiply-adds
       Half4r hx = ((const Half4r*)tex)[t];
-      du = fmaf((float)hx.z, F.tw, cu);
-      dv = fmaf((float)hx.w, F.tw, cv);
-      float w = F.i00 * du + F.i01 * dv;
-      float h = F.i10 * du + F.i11 * dv;
+      float a = fmaf((float)hx.z, F.one, fc), b = fmaf((float)hx.w, F.one, fr);
+      float w = fmaf(F.Wc, a, fmaf(F.Wr, b, F.W0));
+      float h = fmaf(F.Hc, a, fmaf(F.Hr, b, F.H0));
       float wt = __builtin_amdgcn_fmed3f(1.0f - fabsf(w), 0.0f, 1.0f) *
                  __builtin_amdgcn_fmed3f(1.0f - fabsf(h), 0.0f, 1.0f);  // max(1 - |x|, 0)
       float wi = fmaf(wt, (float)hx.x, 0.0f);
@@ -80,10 +86,9 @@ __device__ __forceinline__ void gather(const void* tex, const Footprint& F, uint
       B = fmaf(wi, (float)hx.y, B);
     } else {
       float4 x = ((const float4*)tex)[t];
-      du = fmaf(x.z, F.tw, cu);
-      dv = fmaf(x.w, F.tw, cv);
-      float w = F.i00 * du + F.i01 * dv;
-      float h = F.i10 * du + F.i11 * dv;
+      float a = fc + x.z, b = fr + x.w;
+      float w = fmaf(F.Wc, a, fmaf(F.Wr, b, F.W0));
+      float h = fmaf(F.Hc, a, fmaf(F.Hr, b, F.H0));
       float wt = __builtin_amdgcn_fmed3f(1.0f - fabsf(w), 0.0f, 1.0f) *
                  __builtin_amdgcn_fmed3f(1.0f - fabsf(h), 0.0f, 1.0f);  // max(1 - |x|, 0)
       float wi = wt * x.x;
@@ -365,12 +370,13 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
   float cz0 = v.rhat[1] * d2 - v.rhat[2] * d1;
   float cz1 = v.rhat[2] * d0 - v.rhat[0] * d2;
   float cz2 = v.rhat[0] * d1 - v.rhat[1] * d0;
-  float ncz = fsqrt(cz0 * cz0 + cz1 * cz1 + cz2 * cz2);
+  const float ncz2 = cz0 * cz0 + cz1 * cz1 + cz2 * cz2;
   float dr = d0 * v.rhat[0] + d1 * v.rhat[1] + d2 * v.rhat[2];
-  float dn = fsqrt(d0 * d0 + d1 * d1 + d2 * d2);
+  const float dn2 = d0 * d0 + d1 * d1 + d2 * d2;
+  float ncz, inv_ncz;  // |e_x' x d| and its inverse
   unsigned bits = 0;
   float u_ic = v.u_ic, u_oc = v.u_oc;
-  if (!(ncz > 1e-7f * dn)) {
+  if (!(ncz2 > 1e-14f * dn2)) {
     // radial beam: any plane through it; pick one containing a fixed axis
     bits |= BH_DEGENERATE_BIT;
     float ax0 = fabsf(v.rhat[0]) < 0.9f ? 1.0f : 0.0f, ax1 = 1.0f - ax0;
@@ -379,11 +385,13 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
     cz2 = v.rhat[0] * ax1 - v.rhat[1] * ax0;
     float n2 = __builtin_amdgcn_rsqf(cz0 * cz0 + cz1 * cz1 + cz2 * cz2);
     cz0 *= n2; cz1 *= n2; cz2 *= n2;
-    ncz = fmaxf(ncz, 1e-7f * dn);
+    ncz = fmaxf(fsqrt(ncz2), 1e-7f * fsqrt(dn2));
+    inv_ncz = fdiv(1.0f, ncz);
     u_ic = -1.0f;
   } else {
-    float inv = fdiv(1.0f, ncz);
-    cz0 *= inv; cz1 *= inv; cz2 *= inv;
+    inv_ncz = __builtin_amdgcn_rsqf(ncz2);
+    ncz = ncz2 * inv_ncz;
+    cz0 *= inv_ncz; cz1 *= inv_ncz; cz2 *= inv_ncz;
   }
   float delta = fatan2_pos(ncz, dr);
   // e_y' = e_z' x e_x'
@@ -412,7 +420,7 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
   float zeta = cz2;
 
   // ---- TraceRay (Algorithm 1)
-  const float cotd = fdiv(dr, ncz);
+  const float cotd = dr * inv_ncz;
   TraceOut tr;
   if constexpr (MARCH)
     tr = march_ray(v.u_c, alpha, cotd, u_ic, u_oc, v.march_steps, v.march_h);
@@ -511,12 +519,10 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
     if (fabsf(det) >= 1e-20f) {
       float idet = fdiv(1.0f, det);
       Footprint F;
-      F.i00 = J11 * idet;
-      F.i01 = -J01 * idet;
-      F.i10 = -J10 * idet;
-      F.i11 = J00 * idet;
+      // inverse face Jacobian
+      const float i00 = J11 * idet, i01 = -J01 * idet, i10 = -J10 * idet, i11 = J00 * idet;
       const int nL = S.n0 >> Lv;
-      const float fn = (float)nL;  // power of two: 2 / fn below is exact
+      const float fn = (float)nL;
       // clamp before the integer conversion (equal to floor-then-clamp for in-range values)
       const float top = fn - 1.0f;
       int x0 = (int)clampf(0.5f * (U - hu + 1.0f) * fn, 0.0f, top);
@@ -534,9 +540,17 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
                  (uint32_t)x0;
       F.occ = S.occ + S.occ_off[Lv] +
               ((uint32_t)face * (uint32_t)nL + (uint32_t)y0) * (uint32_t)F.wpr + (uint32_t)(x0 >> 5);
-      F.tw = fdiv(2.0f, fn);
-      F.cu = (float)x0 * F.tw - 1.0f - U;
-      F.cv = (float)y0 * F.tw - 1.0f - V;
+      // a level-L texel is tw = 2 / nL wide in face coordinates; the corner (x0, y0) lies at
+      // (cu, cv) from the centre direction (U, V)
+      const float tw = __builtin_ldexpf(S.tw0, Lv);  // nL = n0 / 2^L: 2 / nL exactly
+      const float cu = (float)x0 * tw - 1.0f - U, cv = (float)y0 * tw - 1.0f - V;
+      F.Wc = i00 * tw;
+      F.Wr = i01 * tw;
+      F.W0 = fmaf(i00, cu, i01 * cv);
+      F.Hc = i10 * tw;
+      F.Hr = i11 * tw;
+      F.H0 = fmaf(i10, cu, i11 * cv);
+      F.one = S.one;
       if (S.fp16)
         gather<true, COUNT>(S.tex, F, touched, A, B);
       else
@@ -547,13 +561,14 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
     }
     float cqx = qw1 * qh2 - qw2 * qh1, cqy = qw2 * qh0 - qw0 * qh2, cqz = qw0 * qh1 - qw1 * qh0;
     float cdx = dw1 * dh2 - dw2 * dh1, cdy = dw2 * dh0 - dw0 * dh2, cdz = dw0 * dh1 - dw1 * dh0;
-    float om = fsqrt(cqx * cqx + cqy * cqy + cqz * cqz);
-    float omp = fsqrt(cdx * cdx + cdy * cdy + cdz * cdz);
-    if (A > 0.0f && omp > 0.0f) {
+    // Omega / Omega' = |q_w x q_h| / |d'_w x d'_h|
+    const float om2 = cqx * cqx + cqy * cqy + cqz * cqz;
+    const float omp2 = cdx * cdx + cdy * cdy + cdz * cdz;
+    if (A > 0.0f && omp2 > 0.0f) {
       float Tpix = fdiv(B, A);
       float4 Lr = band_lookup(L, dcam * Tpix);
       float4 Ln = band_lookup(L, Tpix);
-      float sc = trans * v.k_star * fdiv(om, omp) * fdiv(A, Ln.w);
+      float sc = trans * v.k_star * fsqrt(om2) * __builtin_amdgcn_rsqf(omp2) * fdiv(A, Ln.w);
       cr += sc * Lr.x;
       cg += sc * Lr.y;
       cb += sc * Lr.z;
