@@ -7,7 +7,7 @@ integrated on the GPU with the FP64 photon-sphere band; FP32 trace.  A step is o
 the whole per-pixel path (beam init, TraceRay, disc, derivatives, star gather, compose) on
 device-resident inputs; tables and star map are built once, before timing.
 
-Also reported: the ablation of Section 6 (TraceRay replaced by RK4 ray marching at several
+Also reported: the ablation of Section 5 (TraceRay replaced by RK4 ray marching at several
 step budgets: frame time and escape-angle accuracy), the batched form (64 uneven views in
 one persistent launch) and the served form (Poisson arrivals, continuous batching) against
 one launch per frame, the roofline of the render kernel (algorithmic HBM bytes from a
@@ -236,7 +236,7 @@ def cpu_baseline(view_obj, field, n0, min_seconds=10.0):
 
 
 def march_leg(bh, view, ctx, tables, W, H, reps=30):
-    """The ablation of Section 6 (method M3 of Table 1): the same frame with TraceRay
+    """The ablation of Section 5 (method M3 of Table 1): the same frame with TraceRay
     replaced by RK4 ray marching at several step budgets.  Frame time from HIP events on
     the launch stream; accuracy of the escape angle delta' (from the AOV) of the tables and of
     each budget against a 4096-step march, over pixels that escape on both sides."""

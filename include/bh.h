@@ -187,7 +187,7 @@ typedef struct {
 bh_status bh_render(bh_ctx* ctx, const bh_tables* t, const bh_view* v, float* out_rgba_dev,
                     float* aov_dev, void* hip_stream);
 
-/* The ablation of Section 6 (method M3 of Table 1): render v with TraceRay replaced by a
+/* The ablation of Section 5 (method M3 of Table 1): render v with TraceRay replaced by a
  * numerical integration of the orbit equation u'' = 3/2 u^2 - u (eq. rayequation), and
  * everything else unchanged.  Classic fourth-order Runge-Kutta in phi with the constant
  * step 2 pi / max_steps and at most max_steps steps (one full turn of the beam plane);

@@ -109,6 +109,7 @@ def lib():
         L.orc_hermite_first_root.argtypes = [C.c_double] * 5
         L.orc_render_quads_m.argtypes = [C.POINTER(OrcView), dp, C.c_int32, C.c_int32,
                                          C.POINTER(C.c_int32), C.c_int64, C.c_void_p, C.c_int]
+        L.orc_bloom.argtypes = [dp, C.c_int32, C.c_int32, C.c_int32, dp, dp]
         for f in ("orc_sizeof_pixel", "orc_sizeof_ray", "orc_sizeof_view"):
             getattr(L, f).restype = C.c_int64
         _check_layout(L)
@@ -173,6 +174,19 @@ def hermite(p0, m0, p1, m1, h, s):
 
 def hermite_first_root(p0, m0, p1, m1, h):
     return lib().orc_hermite_first_root(p0, m0, p1, m1, h)
+
+
+def bloom(image, levels, weights):
+    """Bloom of an (H, W, 4) image with mipmap levels 1..levels and weights w_0..w_levels."""
+    img = np.ascontiguousarray(image, np.float64)
+    h, w = img.shape[:2]
+    wt = np.ascontiguousarray(weights, np.float64)
+    if len(wt) != levels + 1:
+        raise ValueError("need levels + 1 weights")
+    out = np.zeros_like(img)
+    if lib().orc_bloom(_dp(img), w, h, levels, _dp(wt), _dp(out)):
+        raise ValueError("orc_bloom rejected its arguments")
+    return out
 
 
 class Tables:

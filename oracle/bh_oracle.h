@@ -99,7 +99,7 @@ int orc_trace_exact(double u_c, double delta, double alpha, double u_ic, double 
 double orc_deflection(double e);                     /* 2 phi_a - pi for a ray from infinity */
 double orc_u_at_phi(double u0, double w0, double phi, double gr); /* u(phi) along a ray */
 
-/* ---- ray marching (the ablation of Section 6, method M3 of Table 1) ----------------- */
+/* ---- ray marching (the ablation of Section 5, method M3 of Table 1) ----------------- */
 /* fixed-step fourth-order Runge-Kutta in phi, h = 2 pi / nsteps, at most nsteps steps;
  * events from the cubic Hermite interpolant of each step (see march.c) */
 int orc_march_ray(double u_c, double delta, double alpha, double u_ic, double u_oc,
@@ -153,6 +153,11 @@ int orc_render_quads_t(const orc_view* v, const double* cubemap, int32_t n0,
 int orc_render_quads_m(const orc_view* v, const double* cubemap, int32_t n0,
                        int32_t march_steps, const int32_t* quads, int64_t nq, orc_pixel* out,
                        int nthreads);
+
+/* ---- bloom (Section 3.4.3): mipmap filters applied to the final image --------------- */
+/* in, out: width x height x 4 doubles (row-major); weights[0 .. levels]; levels <= 16 */
+int orc_bloom(const double* in, int32_t width, int32_t height, int32_t levels,
+              const double* weights, double* out);
 
 /* ---- animated disc (Appendix B) ------------------------------------------------------- */
 double orc_ellipk(double kappa);                     /* complete elliptic integral K */

@@ -1,5 +1,5 @@
 /*
- * Ray marching: the ablation the paper measures its tables against (Section 6, method M3
+ * Ray marching: the ablation the paper measures its tables against (Section 5, method M3
  * of Table 1): TraceRay is replaced by a numerical integration of the orbit equation
  * u'' = 3/2 u^2 - u (Section 3.3, eq. rayequation) with a bounded number of steps, and
  * everything else is left as it is.  TEST INFRASTRUCTURE ONLY (see bh_oracle.h).

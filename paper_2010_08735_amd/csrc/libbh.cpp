@@ -732,7 +732,7 @@ extern "C" bh_status bh_render(bh_ctx* c, const bh_tables* t, const bh_view* v, 
   return BH_OK;
 }
 
-// Ray marching in place of TraceRay (the ablation of Section 6): h = 2 pi / max_steps.
+// Ray marching in place of TraceRay (the ablation of Section 5): h = 2 pi / max_steps.
 static bh_status check_march_steps(int32_t max_steps) {
   if (max_steps < 3 || max_steps > (1 << 20))
     return fail(BH_EINVAL, "max_steps must be in [3, 1048576]");

@@ -209,7 +209,7 @@ __device__ __forceinline__ TraceOut trace_ray(const TablesDev& T, float u, float
   return o;
 }
 
-// ---- ray marching in place of TraceRay: the ablation of Section 6 (method M3, Table 1)
+// ---- ray marching in place of TraceRay: the ablation of Section 5 (method M3, Table 1)
 // Classic fourth-order Runge-Kutta on (u, w = du/dphi), w' = 3/2 u^2 - u (eq. rayequation),
 // with the constant step h = 2 pi / N and at most N steps.  Inside a step u is the cubic
 // Hermite interpolant of the two end states; in t = s / h, with the slopes scaled by h,

@@ -1,4 +1,4 @@
-"""Ray marching in place of TraceRay (the ablation of Section 6, method M3 of Table 1) on
+"""Ray marching in place of TraceRay (the ablation of Section 5, method M3 of Table 1) on
 the GPU, through the C ABI, against the oracle's marcher (same steps, FP64) and against
 exact geodesics.
 

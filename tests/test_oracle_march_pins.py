@@ -1,4 +1,4 @@
-"""Pins of the oracle's ray marcher, the foil of the paper's ablation (Section 6, method M3
+"""Pins of the oracle's ray marcher, the foil of the paper's ablation (Section 5, method M3
 of Table 1: TraceRay replaced by numerical integration of the orbit equation).
 
 Expected values come from the closed-form one-step map of the Runge-Kutta method on the
