@@ -8,7 +8,8 @@ the whole per-pixel path (beam init, TraceRay, disc, derivatives, star gather, c
 device-resident inputs; tables and star map are built once, before timing.
 
 Also reported: the ablation of Section 5 (TraceRay replaced by RK4 ray marching at several
-step budgets: frame time and escape-angle accuracy), the batched form (64 uneven views in
+step budgets: frame time and escape-angle accuracy), the bloom pass of Section 3.4.3 on the
+rendered frame, the batched form (64 uneven views in
 one persistent launch) and the served form (Poisson arrivals, continuous batching) against
 one launch per frame, the roofline of the render kernel (algorithmic HBM bytes from a
 footprint-counting pass, kernel duration from HIP events on the launch stream) and the FP64
@@ -285,13 +286,43 @@ def march_leg(bh, view, ctx, tables, W, H, reps=30):
     return res
 
 
+def bloom_leg(bh, scenes, ctx, img, W, H, levels=7, reps=50):
+    """Bloom (Section 3.4.3) of the rendered frame: HIP-event time per pass on the launch
+    stream, and the HBM bytes it must move at least: the image read twice (the mipmap pass
+    and the output pass) and the output written once, plus the pyramid written and read."""
+    import torch
+    st = bh.current_stream()
+    out = torch.empty_like(img)
+    b = bh.bh_bloom_create(ctx, W, H, levels)
+    wt = scenes.bloom_weights(levels)
+    for _ in range(3):
+        bh.bh_bloom_apply(b, wt, img.data_ptr(), out.data_ptr(), st)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        bh.bh_bloom_apply(b, wt, img.data_ptr(), out.data_ptr(), st)
+    e1.record()
+    torch.cuda.synchronize()
+    bh.bh_bloom_release(b)
+    us = 1e3 * e0.elapsed_time(e1) / reps
+    pyr, w, h = 0, W, H
+    for _ in range(levels):
+        w, h = (w + 1) // 2, (h + 1) // 2
+        pyr += w * h
+    alg = 16 * (3 * W * H + 2 * pyr)
+    return {"levels": levels, "us_per_frame": us, "mpx_per_s": W * H / us,
+            "algorithmic_bytes": alg, "hbm_gbs": alg / us / 1e3,
+            "hbm_frac": alg / us / 1e3 / HBM_PEAK_GBS}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--legs", default="plain,anim,march,batch,serve,cpu",
-                    help="comma list of plain, anim, march, batch, serve, cpu")
+    ap.add_argument("--legs", default="plain,anim,march,bloom,batch,serve,cpu",
+                    help="comma list of plain, anim, march, bloom, batch, serve, cpu")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--serve-tiles", type=int, default=262144,
                     help="most 16x16 tiles in one serving launch")
@@ -391,6 +422,9 @@ def main():
                              "mpx_per_s": W * H * n_a / awall / 1e6}
         bh.bh_release_particles(ph)
         log("animated:", json.dumps(extra["animated"]))
+    if "bloom" in legs:
+        extra["bloom"] = bloom_leg(bh, scenes, ctx, out, W, H)
+        log("bloom:", json.dumps(extra["bloom"]))
     if "march" in legs:
         extra["ablation_march"] = march_leg(bh, view, ctx, tables, W, H)
         log("march ablation:", json.dumps(extra["ablation_march"]))

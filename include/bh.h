@@ -104,6 +104,31 @@ bh_status bh_create_particles(bh_ctx* ctx, const double* host_triples, int32_t n
                               bh_particles** out);
 bh_status bh_release_particles(bh_particles* p);
 
+/* ---- bloom (Section 3.4.3 "Lens glare effects") ---------------------------------------
+ * A point spread function approximated by small-support filters on the mipmaps of the
+ * final (linear, not yet tone-mapped) image:
+ *   P_0 = I;  P_k = 2x2 box average of P_{k-1} (ceil(n/2) pixels per axis, source indices
+ *   clamped to the last row / column), k = 1 .. levels;
+ *   U_levels = w_levels P_levels;  U_k = w_k P_k + up(U_{k+1});  O = w_0 I + up(U_1),
+ * where up() doubles the resolution bilinearly (fine pixel x samples the coarse grid at
+ * x/2 - 1/4, indices clamped to the edge).  Level k's kernel spans about 2^k pixels; the
+ * weights w_0 .. w_levels shape the point spread function, and with sum 1 the flux of an
+ * interior source is kept.  The paper does not print its filter bank; this is one reading.
+ *
+ * bh_bloom_create allocates the pyramid for one image size (counted in the HBM budget):
+ * width, height in [1, 65536], levels in [0, 16].  bh_bloom_apply reads in_rgba_dev and
+ * writes out_rgba_dev (both device, width*height float4, row-major; they may be the same
+ * buffer), with weights[0 .. levels] in host memory (finite; copied at the call).  Calls on
+ * one handle must not overlap in time (they share the pyramid): issue them on one stream,
+ * or use one handle per stream.  bh_bloom_release frees the pyramid after the device has
+ * finished with it. */
+typedef struct bh_bloom bh_bloom;
+bh_status bh_bloom_create(bh_ctx* ctx, int32_t width, int32_t height, int32_t levels,
+                          bh_bloom** out);
+bh_status bh_bloom_apply(bh_bloom* b, const float* weights, const float* in_rgba_dev,
+                         float* out_rgba_dev, void* hip_stream);
+bh_status bh_bloom_release(bh_bloom* b);
+
 /* ---- star map (Section 3.3.2 "Emitted light") -------------------------------------- */
 
 #define BH_TEXEL_FP16 0     /* RGBA16F texels: I (per-level power-of-two scale), T, p_u, p_v */

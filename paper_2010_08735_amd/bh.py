@@ -25,6 +25,7 @@ EXPORTS = [
     "bh_create", "bh_destroy", "bh_last_error", "bh_bytes_in_use",
     "bh_precompute_tables", "bh_tables_download", "bh_tables_download_time", "bh_release_tables",
     "bh_create_particles", "bh_release_particles",
+    "bh_bloom_create", "bh_bloom_apply", "bh_bloom_release",
     "bh_build_stars", "bh_stars_download", "bh_release_stars",
     "bh_render", "bh_render_march", "bh_render_batch", "bh_tile_config_count", "bh_tile_config_get",
     "bh_set_tile_config", "bh_autotune",
@@ -115,6 +116,9 @@ def lib():
             "bh_trace_rays": ([vp, vp, vp, i64, vp, vp], i32),
             "bh_trace_rays_timed": ([vp, vp, vp, i64, vp, vp, vp], i32),
             "bh_march_rays": ([vp, vp, i64, i32, vp, vp], i32),
+            "bh_bloom_create": ([vp, i32, i32, i32, C.POINTER(vp)], i32),
+            "bh_bloom_apply": ([vp, C.POINTER(C.c_float), vp, vp, vp], i32),
+            "bh_bloom_release": ([vp], i32),
             "bh_render_march": ([vp, C.POINTER(View), i32, vp, vp, vp], i32),
             "bh_footprint_texels": ([vp, vp, C.POINTER(View), vp, C.POINTER(u64)], i32),
             "bh_band_table_info": ([vp, C.POINTER(i32), C.POINTER(C.c_float),
@@ -279,6 +283,24 @@ def bh_trace_rays(ctx, tables, rays_ptr, n, out_ptr, stream=None) -> None:
 
 def bh_trace_rays_timed(ctx, tables, rays_ptr, n, out_ptr, out_time_ptr, stream=None) -> None:
     _check(lib().bh_trace_rays_timed(ctx, tables, rays_ptr, n, out_ptr, out_time_ptr, stream))
+
+
+def bh_bloom_create(ctx, width: int, height: int, levels: int) -> int:
+    out = C.c_void_p()
+    _check(lib().bh_bloom_create(ctx, width, height, levels, C.byref(out)))
+    return out.value
+
+
+def bh_bloom_apply(b, weights, in_ptr, out_ptr, stream=None) -> None:
+    """weights: w_0 .. w_levels (the library reads levels + 1 of them)."""
+    if len(weights) > 17:
+        raise ValueError("at most 17 bloom weights")
+    w = (C.c_float * 17)(*[float(x) for x in weights])  # zero-padded to the largest count
+    _check(lib().bh_bloom_apply(b, w, in_ptr, out_ptr, stream))
+
+
+def bh_bloom_release(b) -> None:
+    _check(lib().bh_bloom_release(b))
 
 
 def bh_march_rays(ctx, rays_ptr, n, max_steps, out_ptr, stream=None) -> None:

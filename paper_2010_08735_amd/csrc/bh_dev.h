@@ -71,6 +71,16 @@ struct ViewDev {
   const float4* parts;    // 2 float4 per particle (see disc_density)
 };
 
+// Bloom launch record: the image's box pyramid, levels 0 (the image) .. levels <= 16, and
+// the weights w_0 .. w_levels of the mipmap filters (Section 3.4.3)
+constexpr int kBloomMaxLevels = 16;
+struct BloomDev {
+  int w[kBloomMaxLevels + 1], h[kBloomMaxLevels + 1];  // level sizes
+  int64_t off[kBloomMaxLevels + 1];  // float4 offset of level k in the pyramid arrays (k >= 1)
+  float wt[kBloomMaxLevels + 1];
+  int levels, tiles_x, tiles_y, pad;  // tiles: 64 x 64 image pixels each
+};
+
 // Work of the batched kernels, as runs of consecutive tiles of one view: the view's tiles
 // tile0 .. tile0 + n - 1 (row-major tile order, tiles_x tiles per row) take the launch's
 // flat tile indices start .. start + n - 1.  A launch lists its runs in increasing start,

@@ -47,6 +47,8 @@ hipError_t launch_render_batch(int cfg, int persistent, int anim, const ViewDev*
 hipError_t launch_trace_rays(const TablesDev& T, const float* rays, int64_t n, float4* out,
                              float4* out_time, hipStream_t s);
 hipError_t launch_render_march(const ViewDev& v, const LutDev& L, hipStream_t s);
+hipError_t launch_bloom(const float4* in, float4* out, float4* P, float4* U, const BloomDev& B,
+                        hipStream_t s);
 hipError_t launch_march_rays(const float* rays, int64_t n, int nsteps, float h, float4* out,
                              hipStream_t s);
 hipError_t launch_render_count(const ViewDev& v, const TablesDev& T, const LutDev& L,
@@ -94,6 +96,15 @@ struct bh_particles {
   bh_ctx* ctx;
   float4* dev = nullptr;  // 2 records per particle
   int n = 0;
+};
+
+struct bh_bloom {
+  bh_ctx* ctx;
+  int width = 0, height = 0, levels = 0;
+  float4* P = nullptr;  // levels 1..K of the image's box pyramid
+  float4* U = nullptr;  // the U chain of the coarse levels (same offsets as P)
+  size_t elems = 0;     // float4 elements of P and of U
+  BloomDev B{};          // launch record (sizes, offsets; weights filled per call)
 };
 
 struct bh_stars {
@@ -147,6 +158,7 @@ struct bh_ctx {
   std::map<std::string, bh_tables*> tables;
   std::map<std::tuple<uint64_t, int, int>, bh_stars*> stars;
   std::set<bh_particles*> particles;
+  std::set<bh_bloom*> blooms;
   float4* lut = nullptr;
   int lut_n = 4096;
   float lut_x0 = 6.0f, lut_dx = 15.0f / 4095.0f;
@@ -266,6 +278,11 @@ extern "C" void bh_destroy(bh_ctx* c) {
     dev_free(c, kv.second->occ, 0);
     dev_free(c, kv.second->occ_off_dev, 0);
     delete kv.second;
+  }
+  for (bh_bloom* b : c->blooms) {
+    dev_free(c, b->P, 0);
+    dev_free(c, b->U, 0);
+    delete b;
   }
   for (bh_particles* p : c->particles) {
     dev_free(c, p->dev, 0);
@@ -455,6 +472,74 @@ extern "C" bh_status bh_release_particles(bh_particles* p) {
   (void)hipDeviceSynchronize();  // launches may still read the records
   dev_free(c, p->dev, sizeof(float4) * 2 * (size_t)std::max(p->n, 1));
   delete p;
+  return BH_OK;
+}
+
+// ---- bloom (Section 3.4.3) -------------------------------------------------------------------
+
+extern "C" bh_status bh_bloom_create(bh_ctx* c, int32_t width, int32_t height, int32_t levels,
+                                     bh_bloom** out) {
+  if (!c || !out) return fail(BH_EINVAL, "NULL argument");
+  if (width < 1 || height < 1 || width > 65536 || height > 65536)
+    return fail(BH_EINVAL, "bad image size");
+  if (levels < 0 || levels > kBloomMaxLevels) return fail(BH_EINVAL, "levels must be in [0, 16]");
+  auto* b = new bh_bloom;
+  b->ctx = c;
+  b->width = width;
+  b->height = height;
+  b->levels = levels;
+  BloomDev& B = b->B;
+  B.w[0] = width;
+  B.h[0] = height;
+  size_t e = 0;
+  for (int k = 1; k <= levels; ++k) {
+    B.w[k] = (B.w[k - 1] + 1) / 2;
+    B.h[k] = (B.h[k - 1] + 1) / 2;
+    B.off[k] = (int64_t)e;
+    e += (size_t)B.w[k] * B.h[k];
+  }
+  B.levels = levels;
+  B.tiles_x = (width + 63) / 64;
+  B.tiles_y = (height + 63) / 64;
+  b->elems = std::max(e, (size_t)1);
+  HIPCHK(hipSetDevice(c->device));
+  bh_status st = dev_alloc(c, sizeof(float4) * b->elems, (void**)&b->P);
+  if (!st) st = dev_alloc(c, sizeof(float4) * b->elems, (void**)&b->U);
+  if (st) {
+    dev_free(c, b->P, b->P ? sizeof(float4) * b->elems : 0);
+    dev_free(c, b->U, b->U ? sizeof(float4) * b->elems : 0);
+    delete b;
+    return st;
+  }
+  std::lock_guard<std::mutex> g(c->mu);
+  c->blooms.insert(b);
+  *out = b;
+  return BH_OK;
+}
+
+extern "C" bh_status bh_bloom_apply(bh_bloom* b, const float* weights, const float* in,
+                                    float* out, void* stream) {
+  if (!b || !weights || !in || !out) return fail(BH_EINVAL, "NULL argument");
+  BloomDev B = b->B;
+  for (int k = 0; k <= b->levels; ++k) {
+    if (!std::isfinite(weights[k])) return fail(BH_EINVAL, "non-finite bloom weight");
+    B.wt[k] = weights[k];
+  }
+  HIPCHK(hipSetDevice(b->ctx->device));
+  HIPCHK(launch_bloom((const float4*)in, (float4*)out, b->P, b->U, B, (hipStream_t)stream));
+  return BH_OK;
+}
+
+extern "C" bh_status bh_bloom_release(bh_bloom* b) {
+  if (!b) return fail(BH_EINVAL, "NULL bloom");
+  bh_ctx* c = b->ctx;
+  std::lock_guard<std::mutex> g(c->mu);
+  if (!c->blooms.erase(b)) return fail(BH_ENOTFOUND, "unknown bloom");
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();  // launches may still use the pyramid
+  dev_free(c, b->P, sizeof(float4) * b->elems);
+  dev_free(c, b->U, sizeof(float4) * b->elems);
+  delete b;
   return BH_OK;
 }
 

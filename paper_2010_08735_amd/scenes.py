@@ -276,6 +276,17 @@ def serve_requests(rate: float = 200.0, duration: float = 60.0, seed: int = 4,
     return out
 
 
+def bloom_weights(levels: int) -> List[float]:
+    """Weights w_0 .. w_levels of the bloom's mipmap filters: most light stays in the pixel
+    and the halo falls off by half per level (each level's kernel is twice as wide); sum 1."""
+    w = [0.0] + [0.5 ** k for k in range(1, levels + 1)]
+    halo = sum(w)
+    scale = 0.1 / halo if halo > 0 else 0.0
+    w = [x * scale for x in w]
+    w[0] = 1.0 - sum(w)
+    return w
+
+
 def sample_quads(width: int, height: int, frac: float, seed: int) -> np.ndarray:
     """Sorted unique 2x2-quad origins (even x, even y) covering about ``frac`` of pixels.
 
