@@ -219,7 +219,8 @@ bh_status bh_render(bh_ctx* ctx, const bh_tables* t, const bh_view* v, float* ou
  * inside a step u(phi) is the cubic Hermite interpolant of the end states, which places the
  * escape angle (its first root) and the disc crossings (its value at alpha + m pi).  A beam
  * still travelling after max_steps steps is drawn as captured and flagged
- * BH_AOV_UNFINISHED.  Needs no tables.  max_steps in [3, 1048576]; the view's disc must be
+ * BH_AOV_UNFINISHED.  A beam within 1e-6 of the radius moves along r only (escapes at
+ * delta' = delta outward, falls in inward).  Needs no tables.  max_steps in [3, 1048576]; the view's disc must be
  * BH_DENSITY_UNIFORM (marching carries no time channels).  Same output layout as
  * bh_render. */
 bh_status bh_render_march(bh_ctx* ctx, const bh_view* v, int32_t max_steps, float* out_rgba_dev,

@@ -20,7 +20,9 @@
  *                 when the beam started inward and the cubic's slope there is negative;
  *  - a ray that has neither escaped nor been captured after N steps is unfinished and is
  *    drawn as captured (it wound more than once around the hole).
- * There is no shortcut for rays that cannot escape: every ray is integrated.
+ * There is no shortcut for rays that cannot escape: every ray is integrated, except beams
+ * within 1e-6 of the radius (|cot delta| >= 1e6), which move along r only: outward they
+ * escape at delta' = delta, inward they fall in.
  */
 #include <math.h>
 #include <string.h>
@@ -123,8 +125,9 @@ int orc_march_ray(double u_c, double delta, double alpha, double u_ic, double u_
   if (nsteps < 1) return 1;
   double sd = sin(delta), cd = cos(delta);
   double u = u_c, w;
-  if (sd < 1e-300) {
-    /* a radial beam has no plane; its slope is unbounded and it moves along r only */
+  if (sd <= 1e-6 * fabs(cd)) {
+    /* within 1e-6 of the radius (|cot delta| >= 1e6) the beam moves along r only: a fixed
+     * step in phi cannot follow its slope, and radial beams are not deflected */
     if (cd > 0.0) {
       o->delta_prime = delta;
     } else {

@@ -229,6 +229,15 @@ __device__ __forceinline__ TraceOut march_ray(float u, float alpha, float cotd, 
   o.dprime = 0.0f;
   float w = -u * cotd;
   o.e = fsqrt(w * w + u * u * (1.0f - u));
+  if (fabsf(cotd) >= 1e6f) {
+    // within 1e-6 of the radius: the beam moves along r only (a step in phi cannot follow
+    // it); outward it escapes undeflected at delta' = delta ~ 1 / cot(delta), inward it falls
+    if (cotd > 0.0f)
+      o.dprime = fdiv(1.0f, cotd);
+    else
+      o.bits = BH_CAPTURED_BIT;
+    return o;
+  }
   const bool inward = w > 0.0f;  // an apsis (largest u) can lie ahead
   const float hh = 0.5f * h, h6 = h * (1.0f / 6.0f), ih = fdiv(1.0f, h);
   float phid = alpha > 0.0f ? alpha : alpha + kPi;  // next disc-plane angle ahead
@@ -762,7 +771,8 @@ __global__ void __launch_bounds__(256)
   const float* r = rays + 5 * i;
   float sd, cd;
   sincosf(r[1], &sd, &cd);
-  TraceOut t = march_ray(r[0], r[2], cd / sd, r[3], r[4], nsteps, h);
+  // a radial beam (delta = 0 or pi) keeps a finite slope, as in the render path
+  TraceOut t = march_ray(r[0], r[2], cd / fmaxf(sd, 1e-7f), r[3], r[4], nsteps, h);
   bool cap = (t.bits & BH_CAPTURED_BIT) != 0;
   out[i] = make_float4(cap ? __builtin_inff() : t.dprime, t.ucr[0], t.ucr[1],
                        __uint_as_float(t.bits));

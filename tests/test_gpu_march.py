@@ -81,6 +81,22 @@ def test_march_rays_match_the_oracle_march(gpu_ctx, orc, nsteps):
     assert s["u_max"] < 1e-5
 
 
+def test_radial_rays(gpu_ctx, orc):
+    """delta = 0 leaves along the radius (delta' = 0), delta = pi falls in: the GPU keeps a
+    finite slope for them, as the render path does, and agrees with the oracle's fates."""
+    rays = np.array([[1 / 6, 0.0, 1.0, 1 / 3, 1 / 20], [1 / 6, math.pi, 1.0, 1 / 3, 1 / 20],
+                     [1 / 40, 0.0, 0.3, 1 / 3, 1 / 20], [0.9, math.pi, 2.0, 1 / 3, 1 / 20]],
+                    np.float32)
+    g = _march_gpu(gpu_ctx, rays, 64)
+    bits = g[:, 3].copy().view(np.uint32)
+    for k in range(len(rays)):
+        o = orc.march(*[float(x) for x in rays[k]], 64)
+        assert bool(bits[k] & bh.BH_AOV_CAPTURED) == o["captured"]
+        assert not bits[k] & bh.BH_AOV_UNFINISHED
+        if not o["captured"]:
+            assert abs(g[k, 0] - o["delta_prime"]) < 1e-5
+
+
 @pytest.fixture(scope="module")
 def small_scene(gpu_ctx, orc):
     field = scenes.star_field(20000, 0)

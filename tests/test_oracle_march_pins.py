@@ -148,6 +148,15 @@ def test_capture_and_the_step_budget(orc):
     assert r["captured"] and r["unfinished"] and r["steps"] == 128
 
 
+def test_radial_beams_are_not_deflected(orc):
+    """A radial beam stays on its radius (u'' and the angle decouple): outward it escapes in
+    its own direction, inward it reaches the horizon."""
+    for uc in (1 / 40, 1 / 6, 0.9):
+        r = orc.march(uc, 1e-8, 1.0, 1 / 3, 1 / 20, 64)
+        assert not r["captured"] and r["delta_prime"] == 1e-8 and r["n_cross"] == 0
+        assert orc.march(uc, math.pi - 1e-8, 1.0, 1 / 3, 1 / 20, 64)["captured"]
+
+
 def test_never_a_third_disc_crossing(orc):
     """A beam meets the disc plane at most twice with u <= 1/3 (Section 3.3.3), and the
     march finds no more: the annulus here reaches from r = 3 out to infinity."""
