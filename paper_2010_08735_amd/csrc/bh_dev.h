@@ -69,6 +69,9 @@ struct ViewDev {
   float time;             // camera coordinate time
   int density_mode, nparts, march_steps;   // march_steps: step budget (marching only)
   const float4* parts;    // 2 float4 per particle (see disc_density)
+  const int* pstart;      // first particle reaching radius bin floor(r * pscale), pbins + 1
+  float pscale;
+  int pbins;
 };
 
 // Bloom launch record: the image's box pyramid, levels 0 (the image) .. levels <= 16, and

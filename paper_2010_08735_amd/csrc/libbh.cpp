@@ -94,9 +94,16 @@ struct bh_tables {
 
 struct bh_particles {
   bh_ctx* ctx;
-  float4* dev = nullptr;  // 2 records per particle
+  float4* dev = nullptr;  // 2 records per particle, then the start table
   int n = 0;
+  size_t bytes = 0;
+  float scale = 0.0f;     // start-table bins per unit radius
 };
+
+// Radius bins of the start table: a crossing at radius r starts its particle loop at
+// start[min(floor(r * scale), kPartBins)], the first particle whose radial reach
+// (r_apo + 1) extends to the bin; no earlier particle can touch r.
+constexpr int kPartBins = 256;
 
 struct bh_bloom {
   bh_ctx* ctx;
@@ -441,18 +448,35 @@ extern "C" bh_status bh_create_particles(bh_ctx* c, const double* tr, int32_t n,
     sorted[2 * j + 1] = rec[2 * order[j] + 1];
   }
   rec.swap(sorted);
+  // start table: prefix maxima of the outer reach are non-decreasing, so the first particle
+  // reaching a bin's lower edge (less a hundredth of a bin) is found by binary search
+  std::vector<float> reach(n);
+  float rmax = 0.0f;
+  for (int32_t j = 0; j < n; ++j) reach[j] = rmax = std::max(rmax, rec[2 * j + 1].z);
+  const float scale = n > 0 ? (float)kPartBins / rmax : 0.0f;
+  std::vector<int32_t> start(kPartBins + 1 + 3, n);  // padded to whole float4s
+  for (int b = 0; b <= kPartBins && n > 0; ++b) {
+    const float edge = ((float)b - 0.01f) / scale;
+    start[b] = (int32_t)(std::lower_bound(reach.begin(), reach.end(), edge) - reach.begin());
+  }
+  const size_t rec_bytes = sizeof(float4) * rec.size();
+  std::vector<char> blob(rec_bytes + sizeof(int32_t) * start.size());
+  memcpy(blob.data(), rec.data(), rec_bytes);
+  memcpy(blob.data() + rec_bytes, start.data(), sizeof(int32_t) * start.size());
   HIPCHK(hipSetDevice(c->device));
   std::lock_guard<std::mutex> g(c->mu);
   auto* p = new bh_particles;
   p->ctx = c;
   p->n = n;
-  size_t bytes = sizeof(float4) * rec.size();
+  p->scale = scale;
+  size_t bytes = blob.size();
+  p->bytes = bytes;
   bh_status st = dev_alloc(c, bytes, (void**)&p->dev);
   if (st) {
     delete p;
     return st;
   }
-  hipError_t e = hipMemcpy(p->dev, rec.data(), bytes, hipMemcpyHostToDevice);
+  hipError_t e = hipMemcpy(p->dev, blob.data(), bytes, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     dev_free(c, p->dev, bytes);
     delete p;
@@ -470,7 +494,7 @@ extern "C" bh_status bh_release_particles(bh_particles* p) {
   if (!c->particles.erase(p)) return fail(BH_ENOTFOUND, "unknown particles");
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();  // launches may still read the records
-  dev_free(c, p->dev, sizeof(float4) * 2 * (size_t)std::max(p->n, 1));
+  dev_free(c, p->dev, p->bytes);
   delete p;
   return BH_OK;
 }
@@ -763,6 +787,9 @@ static bh_status make_view(const bh_view* v, float* out, float* aov, ViewDev* o)
     o->time = (float)v->time;
     o->nparts = v->particles->n;
     o->parts = v->particles->dev;
+    o->pstart = (const int*)(v->particles->dev + 2 * (size_t)std::max(v->particles->n, 1));
+    o->pscale = v->particles->scale;
+    o->pbins = kPartBins;
   }
   if (v->stars) {
     const bh_stars* s = v->stars;

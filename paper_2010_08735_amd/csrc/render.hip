@@ -334,16 +334,28 @@ __device__ __forceinline__ float fatan2_any(float y, float x) {
 __device__ __forceinline__ float disc_density(const ViewDev& v, float ht, float hr, float hphi) {
   const float k2Pi = 2.0f * kPi;
   float rho = 0.0f;
-  for (int j = 0; j < v.nparts; ++j) {
+  // particles are sorted by the inner end of their radial reach; no particle before
+  // pstart[bin of hr] reaches out to hr.  The wave starts at the smallest such index over
+  // its active lanes (an LDS minimum in the wave's own slot: one wave's LDS operations
+  // complete in order), so the loop index stays wave-uniform and the records are scalar loads.
+  __shared__ int wave_start[16];
+  int j0 = 0;
+  if (v.nparts > 0) {
+    int* slot = &wave_start[threadIdx.x >> 6];
+    *slot = v.nparts;
+    atomicMin(slot, v.pstart[(int)fminf(hr * v.pscale, (float)v.pbins)]);
+    j0 = __builtin_amdgcn_readfirstlane(*(volatile int*)slot);
+  }
+  for (int j = j0; j < v.nparts; ++j) {
     float4 p0 = v.parts[2 * j], p1 = v.parts[2 * j + 1];
     if (hr < p1.y) break;  // this and every later particle starts beyond hr
     if (hr > p1.z) continue;
     float ph = fmaf(p0.w, ht, p1.x);
     float a = hphi - ph;
     a -= k2Pi * floorf(a * (1.0f / k2Pi));
-    float sn, cs;
-    fsincos(p0.z * (a + ph), &sn, &cs);
-    float ua = fmaf(p0.y, sn * sn, p0.x);
+    // sin^2 x = (1 - cos 2x) / 2, with the hardware cosine (argument in turns: 2x / 2 pi)
+    const float c2 = __builtin_amdgcn_cosf(p0.z * (a + ph) * (1.0f / kPi));
+    float ua = fmaf(p0.y, fmaf(-0.5f, c2, 0.5f), p0.x);
     float dr = hr - fdiv(1.0f, ua);
     float da = a * (1.0f / kPi) - 1.0f;
     float d2 = da * da + dr * dr;
@@ -601,6 +613,7 @@ struct TileCfg {
   static constexpr int kWaves = kBX * kBY / PPT;
   static constexpr int kThreads = 64 * kWaves;
   static_assert(kBX * kBY % PPT == 0, "blocks must divide by pixels per thread");
+  static_assert(kWaves <= 16, "the particle loop keeps one LDS slot per wave, 16 at most");
 };
 
 template <int TW, int TH, int PPT, bool COUNT = false, bool ANIM = false, bool MARCH = false>
