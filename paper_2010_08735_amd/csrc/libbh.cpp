@@ -208,13 +208,21 @@ static double now_s() {
       .count();
 }
 
+// Reserves the bytes in the budget first (one atomic add, so concurrent callers cannot both
+// pass the check), then allocates; both steps are undone on failure.
 static bh_status dev_alloc(bh_ctx* c, size_t bytes, void** p) {
-  if (c->budget && c->used.load() + bytes > c->budget)
-    return fail(BH_ENOMEM, "HBM budget exceeded: " + std::to_string(c->used.load() + bytes) +
-                               " > " + std::to_string(c->budget));
+  const uint64_t before = c->used.fetch_add(bytes);
+  if (c->budget && before + bytes > c->budget) {
+    c->used -= bytes;
+    return fail(BH_ENOMEM, "HBM budget exceeded: " + std::to_string(before + bytes) + " > " +
+                               std::to_string(c->budget));
+  }
   hipError_t e = hipMalloc(p, bytes);
-  if (e != hipSuccess) return fail(BH_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
-  c->used += bytes;
+  if (e != hipSuccess) {
+    c->used -= bytes;
+    *p = nullptr;
+    return fail(BH_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
   return BH_OK;
 }
 
@@ -252,10 +260,17 @@ extern "C" bh_status bh_create(int device, uint64_t budget, bh_ctx** out) {
   c->cus = prop.multiProcessorCount;
   bh_status st = dev_alloc(c.get(), sizeof(float4) * c->lut_n, (void**)&c->lut);
   if (st) return st;
-  HIPCHK(launch_band_lut(c->lut, c->lut_n, c->lut_x0, c->lut_dx, nullptr));
-  HIPCHK(hipDeviceSynchronize());
-  st = dev_alloc(c.get(), sizeof(int) * 64, (void**)&c->b_counter);
-  if (st) return st;
+  hipError_t e = launch_band_lut(c->lut, c->lut_n, c->lut_x0, c->lut_dx, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e == hipSuccess) {
+    st = dev_alloc(c.get(), sizeof(int) * 64, (void**)&c->b_counter);
+  } else {
+    st = fail(BH_EDEVICE, std::string("band table: ") + hipGetErrorString(e));
+  }
+  if (st) {
+    dev_free(c.get(), c->lut, sizeof(float4) * c->lut_n);
+    return st;
+  }
   *out = c.release();
   return BH_OK;
 }
@@ -1171,13 +1186,14 @@ static void* pool_get(bh_ctx* c, size_t bytes) {
     return p;
   }
   for (;;) {
-    if (!c->budget || c->used.load() + bytes <= c->budget) {
+    // reserve in the budget first, as dev_alloc does, then allocate
+    const uint64_t before = c->used.fetch_add(bytes);
+    if (!c->budget || before + bytes <= c->budget) {
       void* p = nullptr;
-      if (hipMallocFromPoolAsync(&p, bytes, c->img_pool, c->serve_stream) == hipSuccess) {
-        c->used += bytes;
+      if (hipMallocFromPoolAsync(&p, bytes, c->img_pool, c->serve_stream) == hipSuccess)
         return p;
-      }
     }
+    c->used -= bytes;
     if (c->pool.empty()) return nullptr;
     auto big = std::prev(c->pool.end());
     (void)hipFreeAsync(big->second, c->serve_stream);
