@@ -262,7 +262,9 @@ typedef struct {
 bh_status bh_serve_start(bh_ctx* ctx, const bh_serve_params* p);
 /* Queue a frame; returns at once with a ticket.  out_rgba_dev may be NULL, in which case
  * the library allocates the image inside the HBM budget (admission waits for room) and
- * bh_poll returns it; it is freed by bh_ticket_free. */
+ * bh_ticket_image returns it; it is freed by bh_ticket_free.  The view record is copied,
+ * but the handles it names (tables, star map, particles) and a caller-owned output image
+ * must stay alive until bh_poll reports the frame done. */
 bh_status bh_submit(bh_ctx* ctx, const bh_tables* t, const bh_view* v, float* out_rgba_dev,
                     uint64_t* ticket);
 /* done = 1 when the frame is complete on the device (or has failed); latency_s =
