@@ -117,25 +117,6 @@ __device__ __forceinline__ float fsin_small(float x) {
               s * (1.0f / 362880.0f + s * (-1.0f / 39916800.0f))))));
 }
 
-// sin and cos for |x| up to a few hundred: x = k pi/2 + r with k = rint(2x/pi) and pi/2 split
-// as 1.5703125 (exact in FP32) + 4.8382679e-4, then Taylor polynomials on |r| <= pi/4
-// (truncation below 2e-9) and the quadrant of k.
-__device__ __forceinline__ void fsincos(float x, float* sn, float* cs) {
-  float k = rintf(x * 0.636619772367581343f);
-  float r = fmaf(-k, 1.5703125f, x);
-  r = fmaf(-k, 4.83826794896619e-4f, r);
-  float r2 = r * r;
-  float s = r * (1.0f + r2 * (-1.0f / 6.0f + r2 * (1.0f / 120.0f + r2 * (-1.0f / 5040.0f +
-                 r2 * (1.0f / 362880.0f)))));
-  float c = 1.0f + r2 * (-0.5f + r2 * (1.0f / 24.0f + r2 * (-1.0f / 720.0f +
-                 r2 * (1.0f / 40320.0f + r2 * (-1.0f / 3628800.0f)))));
-  int q = (int)k & 3;  // sin(q pi/2 + r), cos(q pi/2 + r)
-  float ss = (q & 1) ? c : s;
-  float cc = (q & 1) ? s : c;
-  *sn = (q & 2) ? -ss : ss;
-  *cs = ((q + 1) & 2) ? -cc : cc;
-}
-
 // atan2(y, x) for y >= 0 (the render path's angles lie in [0, pi]): t = min/max of |x|, |y|
 // in [0, 1], atan(t) = t P(t^2) with a degree-8 P fitted by weighted least squares at
 // Chebyshev nodes (max error 1.2e-7 rad in FP32), then the octant.
