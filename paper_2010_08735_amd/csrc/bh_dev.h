@@ -142,13 +142,17 @@ __device__ __forceinline__ float fatan2_pos(float y, float x) {
 
 // bilinear fetch of a row-major table with texel k of n at unit coordinate k/(n-1),
 // columns clamped to [lo, hi] (so the two halves of D are never mixed)
+// Coordinates are clamped to just below the last texel (k (1 - 2^-23) < k for every k >= 1),
+// so the lower texel is trunc(t), the next one exists, and the weight is fract(t); at the
+// edge itself the result differs from the edge texel by 2^-23 of the last texel step.
+constexpr float kBelowOne = 0.99999988f;  // 1 - 2^-23
+
 __device__ __forceinline__ float bilinear(const float* __restrict__ t, int nx, int ny, int lo,
                                           int hi, float x, float y) {
-  float tx = clampf(x * (float)(nx - 1), (float)lo, (float)hi);
-  float ty = clampf(y * (float)(ny - 1), 0.0f, (float)(ny - 1));
-  int i0 = min((int)tx, hi - 1);
-  int j0 = min((int)ty, ny - 2);
-  float fx = tx - (float)i0, fy = ty - (float)j0;
+  float tx = clampf(x * (float)(nx - 1), (float)lo, (float)hi * kBelowOne);
+  float ty = clampf(y * (float)(ny - 1), 0.0f, (float)(ny - 1) * kBelowOne);
+  int i0 = (int)tx, j0 = (int)ty;
+  float fx = __builtin_amdgcn_fractf(tx), fy = __builtin_amdgcn_fractf(ty);
   const float* r0 = t + (__umul24((unsigned)j0, (unsigned)nx) + (unsigned)i0);  // nx, ny < 2^24
   const float* r1 = r0 + nx;
   float a = r0[0] + fx * (r0[1] - r0[0]);
@@ -189,9 +193,9 @@ __device__ __forceinline__ float lookup_D(const TablesDev& T, const float* tab, 
 __device__ __forceinline__ float lookup_D_apsis(const TablesDev& T, const float* tab, float e2) {
   const int n = T.d_n, hi = n / 2 - 1;
   float x = 0.5f - fsqrt(-flog1p(-e2 * (1.0f / kMu)) * (1.0f / 50.0f));
-  float tx = clampf(x * (float)(n - 1), 0.0f, (float)hi);
-  int i0 = min((int)tx, hi - 1);
-  float fx = tx - (float)i0;
+  float tx = clampf(x * (float)(n - 1), 0.0f, (float)hi * kBelowOne);
+  int i0 = (int)tx;
+  float fx = __builtin_amdgcn_fractf(tx);
   const float* r = tab + (__umul24((unsigned)(n - 1), (unsigned)n) + (unsigned)i0);
   return r[0] + fx * (r[1] - r[0]);
 }
