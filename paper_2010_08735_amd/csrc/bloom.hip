@@ -22,7 +22,6 @@
 namespace bh {
 
 constexpr int kBloomTileLevels = 6;  // levels built inside a 64 x 64 tile
-constexpr int kBloomTile = 64;
 
 __device__ __forceinline__ float4 f4_fma(float a, float4 x, float4 y) {
   return make_float4(fmaf(a, x.x, y.x), fmaf(a, x.y, y.y), fmaf(a, x.z, y.z), fmaf(a, x.w, y.w));
@@ -164,8 +163,10 @@ __global__ void __launch_bounds__(256)
 template <int T, int K>
 struct UpLevel {
   static constexpr int S = (K & 1) ? T / 2 + 2 : T / 4 + 2;  // LDS row stride
-  static constexpr int ROWS = T / (1 << K) + 2;              // rows of the region, at most
+  // rows of the region, at most: T / 2^K + 2 while that is at least 3, then 3
+  static constexpr int ROWS = T / (1 << K) + 2 < 3 ? 3 : T / (1 << K) + 2;
   static constexpr int N = (S * ROWS + 255) / 256;           // slots per thread
+  static_assert(ROWS <= S, "a region's rows and columns fit the LDS row stride");
 };
 
 struct Region {
@@ -187,13 +188,40 @@ __device__ __forceinline__ void load_p(const BloomDev& B, const float4* __restri
   }
 }
 
-// U_K = w_K P_K + up(U_{K+1}) over the region, into `dst`; U_{K+1} from LDS (`src`, region
-// Rs, stride of level K + 1), from the global U array (`from_global`), or none (K = levels)
+// U_7 at the four coarse neighbours of every level-6 element of the region, from the global
+// U array the tail kernel wrote (only when the pyramid has more than 6 levels)
+template <int T>
+__device__ __forceinline__ void load_u_coarse(const BloomDev& B, const float4* __restrict__ U,
+                                              const Region& R,
+                                              float4 (&q)[UpLevel<T, kBloomTileLevels>::N][4]) {
+  using L = UpLevel<T, kBloomTileLevels>;
+  constexpr int K = kBloomTileLevels;
+  const int cnx = B.w[K + 1], cny = B.h[K + 1];
+  const float4* cu = U + B.off[K + 1];
+#pragma unroll
+  for (int j = 0; j < L::N; ++j) {
+    // slots outside the region load a neighbour of its last element, unused: loads that
+    // every lane issues keep the chain's waits on earlier loads exact
+    const int l = threadIdx.x + 256 * j;
+    const int r = l / L::S, c = l - r * L::S;
+    const int x = R.lox + min(c, R.hix - R.lox), y = R.loy + min(r, R.hiy - R.loy);
+    const int xa = max((x - 1) >> 1, 0), xb = min((x + 1) >> 1, cnx - 1);
+    const int ya = max((y - 1) >> 1, 0), yb = min((y + 1) >> 1, cny - 1);
+    q[j][0] = cu[(size_t)ya * cnx + xa];
+    q[j][1] = cu[(size_t)ya * cnx + xb];
+    q[j][2] = cu[(size_t)yb * cnx + xa];
+    q[j][3] = cu[(size_t)yb * cnx + xb];
+  }
+}
+
+// U_K = w_K P_K + up(U_{K+1}) over the region, into `dst`.  U_{K+1} comes from LDS (`src`,
+// region Rs, stride of level K + 1) for K < 6, from the preloaded values `q` for K = 6, and
+// is absent for K = levels.  The chain itself reads no global memory, so its waits cover
+// only the loads it uses.
 template <int T, int K>
-__device__ __forceinline__ void u_level(const BloomDev& B, const float4* __restrict__ U,
-                                        const float4 (&p)[UpLevel<T, K>::N], const Region& R,
-                                        bool from_global, const float4* src, const Region& Rs,
-                                        float4* dst) {
+__device__ __forceinline__ void u_level(const BloomDev& B, const float4 (&p)[UpLevel<T, K>::N],
+                                        const float4 (*q)[4], const Region& R, const float4* src,
+                                        const Region& Rs, float4* dst) {
   using L = UpLevel<T, K>;
   constexpr int SS = UpLevel<T, K + 1>::S;
   const float wk = B.wt[K];
@@ -205,17 +233,16 @@ __device__ __forceinline__ void u_level(const BloomDev& B, const float4* __restr
     const int x = R.lox + c, y = R.loy + r;
     float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
     if (K < B.levels) {
-      const int cnx = B.w[K + 1], cny = B.h[K + 1];
-      const int xa = max((x - 1) >> 1, 0), xb = min((x + 1) >> 1, cnx - 1);
-      const int ya = max((y - 1) >> 1, 0), yb = min((y + 1) >> 1, cny - 1);
       float4 v00, v10, v01, v11;
-      if (from_global) {
-        const float4* cu = U + B.off[K + 1];
-        v00 = cu[(size_t)ya * cnx + xa];
-        v10 = cu[(size_t)ya * cnx + xb];
-        v01 = cu[(size_t)yb * cnx + xa];
-        v11 = cu[(size_t)yb * cnx + xb];
+      if constexpr (K == kBloomTileLevels) {
+        v00 = q[j][0];
+        v10 = q[j][1];
+        v01 = q[j][2];
+        v11 = q[j][3];
       } else {
+        const int cnx = B.w[K + 1], cny = B.h[K + 1];
+        const int xa = max((x - 1) >> 1, 0), xb = min((x + 1) >> 1, cnx - 1);
+        const int ya = max((y - 1) >> 1, 0), yb = min((y + 1) >> 1, cny - 1);
         v00 = src[(ya - Rs.loy) * SS + xa - Rs.lox];
         v10 = src[(ya - Rs.loy) * SS + xb - Rs.lox];
         v01 = src[(yb - Rs.loy) * SS + xa - Rs.lox];
@@ -235,6 +262,7 @@ __global__ void __launch_bounds__(256)
                const float4* __restrict__ P, const float4* __restrict__ U, BloomDev B) {
   constexpr int SA = UpLevel<T, 1>::S, SB = UpLevel<T, 2>::S;
   static_assert(UpLevel<T, 3>::S == SA && UpLevel<T, 4>::S == SB, "odd / even strides");
+  static_assert(256 % T == 0 && T % (256 / T) == 0, "whole rows per pass, whole passes per tile");
   __shared__ float4 sa[SA * SA];
   __shared__ float4 sb[SB * SB];
   const int ntx = (B.w[0] + T - 1) / T;
@@ -263,18 +291,32 @@ __global__ void __launch_bounds__(256)
   if (m >= 3) load_p<T, 3>(B, P, R[3], p3);
   if (m >= 2) load_p<T, 2>(B, P, R[2], p2);
   if (m >= 1) load_p<T, 1>(B, P, R[1], p1);
+  float4 q6[UpLevel<T, 6>::N][4];
+  if (B.levels > kBloomTileLevels) load_u_coarse<T>(B, U, R[6], q6);
+  // this thread's image pixels (column x, rows y0 + kRows j), in flight during the chain;
+  // positions past the image's edge load the edge pixel, unused
+  constexpr int kRows = 256 / T, kIt = T / kRows;
+  const int x = R[0].lox + (int)(threadIdx.x % T);
+  const int y0 = R[0].loy + (int)(threadIdx.x / T);
+  const bool xin = x <= R[0].hix;
+  float4 im[kIt];
+#pragma unroll
+  for (int j = 0; j < kIt; ++j)
+    im[j] = img[(size_t)min(y0 + kRows * j, R[0].hiy) * B.w[0] + min(x, R[0].hix)];
   // U_k, k = m .. 1 (m is the same for the whole launch, so the barriers are uniform)
-  if (m >= 6) { u_level<T, 6>(B, U, p6, R[6], m == 6, sa, R[6], sb); __syncthreads(); }
-  if (m >= 5) { u_level<T, 5>(B, U, p5, R[5], m == 5, sb, R[6], sa); __syncthreads(); }
-  if (m >= 4) { u_level<T, 4>(B, U, p4, R[4], m == 4, sa, R[5], sb); __syncthreads(); }
-  if (m >= 3) { u_level<T, 3>(B, U, p3, R[3], m == 3, sb, R[4], sa); __syncthreads(); }
-  if (m >= 2) { u_level<T, 2>(B, U, p2, R[2], m == 2, sa, R[3], sb); __syncthreads(); }
-  if (m >= 1) { u_level<T, 1>(B, U, p1, R[1], m == 1, sb, R[2], sa); __syncthreads(); }
+  if (m >= 6) { u_level<T, 6>(B, p6, q6, R[6], sa, R[6], sb); __syncthreads(); }
+  if (m >= 5) { u_level<T, 5>(B, p5, nullptr, R[5], sb, R[6], sa); __syncthreads(); }
+  if (m >= 4) { u_level<T, 4>(B, p4, nullptr, R[4], sa, R[5], sb); __syncthreads(); }
+  if (m >= 3) { u_level<T, 3>(B, p3, nullptr, R[3], sb, R[4], sa); __syncthreads(); }
+  if (m >= 2) { u_level<T, 2>(B, p2, nullptr, R[2], sa, R[3], sb); __syncthreads(); }
+  if (m >= 1) { u_level<T, 1>(B, p1, nullptr, R[1], sb, R[2], sa); __syncthreads(); }
   // O = w_0 I + up(U_1)
   const float w0 = B.wt[0];
-  const int x = R[0].lox + (threadIdx.x % T);
-  if (x > R[0].hix) return;
-  for (int y = R[0].loy + (int)(threadIdx.x / T); y <= R[0].hiy; y += 256 / T) {
+  if (!xin) return;
+#pragma unroll
+  for (int j = 0; j < kIt; ++j) {
+    const int y = y0 + kRows * j;
+    if (y > R[0].hiy) break;
     const size_t i = (size_t)y * B.w[0] + x;
     float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
     if (B.levels >= 1) {
@@ -284,7 +326,7 @@ __global__ void __launch_bounds__(256)
       v = blend(sa[ya * SA + xa], sa[ya * SA + xb], sa[yb * SA + xa], sa[yb * SA + xb],
                 (x & 1) ? 0.25f : 0.75f, (y & 1) ? 0.25f : 0.75f);
     }
-    out[i] = f4_fma(w0, img[i], v);
+    out[i] = f4_fma(w0, im[j], v);
   }
 }
 
