@@ -110,6 +110,7 @@ def lib():
         L.orc_render_quads_m.argtypes = [C.POINTER(OrcView), dp, C.c_int32, C.c_int32,
                                          C.POINTER(C.c_int32), C.c_int64, C.c_void_p, C.c_int]
         L.orc_bloom.argtypes = [dp, C.c_int32, C.c_int32, C.c_int32, dp, dp]
+        L.orc_tonemap.argtypes = [dp, C.c_int64, C.c_double, C.c_void_p, dp]
         for f in ("orc_sizeof_pixel", "orc_sizeof_ray", "orc_sizeof_view"):
             getattr(L, f).restype = C.c_int64
         _check_layout(L)
@@ -187,6 +188,18 @@ def bloom(image, levels, weights):
     if lib().orc_bloom(_dp(img), w, h, levels, _dp(wt), _dp(out)):
         raise ValueError("orc_bloom rejected its arguments")
     return out
+
+
+def tonemap(image, exposure):
+    """Display encoding of an (H, W, 4) linear image: (codes, scaled), codes (H, W, 4) uint8
+    (R, G, B, 255) and scaled (H, W, 3) = 255 v + 1/2, the value each code is the floor of."""
+    img = np.ascontiguousarray(image, np.float64)
+    n = img.size // 4
+    out = np.zeros(img.shape[:-1] + (4,), np.uint8)
+    sc = np.zeros(img.shape[:-1] + (3,), np.float64)
+    if lib().orc_tonemap(_dp(img), n, float(exposure), out.ctypes.data, _dp(sc)):
+        raise ValueError("orc_tonemap rejected its arguments")
+    return out, sc
 
 
 class Tables:

@@ -159,6 +159,11 @@ int orc_render_quads_m(const orc_view* v, const double* cubemap, int32_t n0,
 int orc_bloom(const double* in, int32_t width, int32_t height, int32_t levels,
               const double* weights, double* out);
 
+/* ---- display encoding after the glare pass (Section 3.4.3): tone curve, sRGB, 8 bits ---- */
+/* in: n x 4 doubles (linear RGBA); out: n x 4 bytes R, G, B, 255; scaled (may be NULL):
+   n x 3 values 255 v + 1/2 whose floor is each code; exposure finite and > 0 */
+int orc_tonemap(const double* in, int64_t n, double exposure, uint8_t* out, double* scaled);
+
 /* ---- animated disc (Appendix B) ------------------------------------------------------- */
 double orc_ellipk(double kappa);                     /* complete elliptic integral K */
 double orc_particle_u(const double* particle, double a, double t);
