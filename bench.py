@@ -9,7 +9,7 @@ device-resident inputs; tables and star map are built once, before timing.
 
 Also reported: the ablation of Section 5 (TraceRay replaced by RK4 ray marching at several
 step budgets: frame time and escape-angle accuracy), the bloom pass of Section 3.4.3 on the
-rendered frame, the batched form (64 uneven views in
+rendered frame and the display encoding after it (fused and alone), the batched form (64 uneven views in
 one persistent launch) and the served form (Poisson arrivals, continuous batching) against
 one launch per frame, the roofline of the render kernel (algorithmic HBM bytes from a
 footprint-counting pass, kernel duration from HIP events on the launch stream) and the FP64
@@ -286,34 +286,55 @@ def march_leg(bh, view, ctx, tables, W, H, reps=30):
     return res
 
 
-def bloom_leg(bh, scenes, ctx, img, W, H, levels=7, reps=50):
-    """Bloom (Section 3.4.3) of the rendered frame: HIP-event time per pass on the launch
-    stream, and the HBM bytes it must move at least: the image read twice (the mipmap pass
-    and the output pass) and the output written once, plus the pyramid written and read."""
+def _event_time_us(fn, reps):
+    """HIP-event time per call of fn() on the launch stream, after 3 untimed calls."""
     import torch
-    st = bh.current_stream()
-    out = torch.empty_like(img)
-    b = bh.bh_bloom_create(ctx, W, H, levels)
-    wt = scenes.bloom_weights(levels)
     for _ in range(3):
-        bh.bh_bloom_apply(b, wt, img.data_ptr(), out.data_ptr(), st)
+        fn()
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(reps):
-        bh.bh_bloom_apply(b, wt, img.data_ptr(), out.data_ptr(), st)
+        fn()
     e1.record()
     torch.cuda.synchronize()
+    return 1e3 * e0.elapsed_time(e1) / reps
+
+
+def bloom_leg(bh, scenes, ctx, img, W, H, levels=7, reps=50, exposure=4.0):
+    """Bloom (Section 3.4.3) of the rendered frame: HIP-event time per pass on the launch
+    stream, and the HBM bytes it must move at least: the image read twice (the mipmap pass
+    and the output pass) and the output written once, plus the pyramid written and read.
+    Then the display encoding that follows it: fused into the glare pass's output (4-byte
+    pixels written in place of 16-byte ones) and on its own (16 bytes in, 4 out per pixel)."""
+    import torch
+    st = bh.current_stream()
+    out = torch.empty_like(img)
+    disp = torch.empty((H, W), dtype=torch.int32, device=img.device)
+    b = bh.bh_bloom_create(ctx, W, H, levels)
+    wt = scenes.bloom_weights(levels)
+    us = _event_time_us(lambda: bh.bh_bloom_apply(b, wt, img.data_ptr(), out.data_ptr(), st),
+                        reps)
+    us_fused = _event_time_us(lambda: bh.bh_bloom_apply_display(
+        b, wt, exposure, img.data_ptr(), disp.data_ptr(), st), reps)
     bh.bh_bloom_release(b)
-    us = 1e3 * e0.elapsed_time(e1) / reps
+    us_tm = _event_time_us(lambda: bh.bh_tonemap(ctx, out.data_ptr(), disp.data_ptr(), W, H,
+                                                 exposure, st), reps)
     pyr, w, h = 0, W, H
     for _ in range(levels):
         w, h = (w + 1) // 2, (h + 1) // 2
         pyr += w * h
     alg = 16 * (3 * W * H + 2 * pyr)
+    alg_fused = 16 * (2 * W * H + 2 * pyr) + 4 * W * H
+    alg_tm = 20 * W * H
     return {"levels": levels, "us_per_frame": us, "mpx_per_s": W * H / us,
             "algorithmic_bytes": alg, "hbm_gbs": alg / us / 1e3,
-            "hbm_frac": alg / us / 1e3 / HBM_PEAK_GBS}
+            "hbm_frac": alg / us / 1e3 / HBM_PEAK_GBS,
+            "display": {"exposure": exposure,
+                        "fused": {"us_per_frame": us_fused, "algorithmic_bytes": alg_fused,
+                                  "hbm_gbs": alg_fused / us_fused / 1e3},
+                        "tonemap_alone": {"us_per_frame": us_tm, "algorithmic_bytes": alg_tm,
+                                          "hbm_gbs": alg_tm / us_tm / 1e3}}}
 
 
 def main():

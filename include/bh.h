@@ -129,6 +129,29 @@ bh_status bh_bloom_apply(bh_bloom* b, const float* weights, const float* in_rgba
                          float* out_rgba_dev, void* hip_stream);
 bh_status bh_bloom_release(bh_bloom* b);
 
+/* ---- display encoding: the tone mapping after the glare pass (Section 3.4.3) -----------
+ *
+ * The paper applies its glare pass before tone mapping and prints no operator; this is one
+ * reading.  Per colour channel c of a linear pixel: x = exposure * c; y = 1 - exp(-x) (0 for
+ * x <= 0 and for NaN); v = the sRGB transfer function of y (IEC 61966-2-1: 12.92 y for
+ * y <= 0.0031308, else 1.055 y^(1/2.4) - 0.055); code = floor(255 v + 1/2).  Alpha is
+ * encoded as 255.  An encoded pixel is 4 bytes R, G, B, A in memory order (one uint32).
+ * The codes are computed in FP32 with hardware exp2 / log2: a code can differ from the
+ * exactly rounded one only where 255 v + 1/2 lies within 5e-4 of an integer (the computed
+ * value stays within 2e-4 of the exact one).
+ *
+ * bh_tonemap encodes in_rgba_dev (device, width*height float4, row-major) into
+ * out_rgba8_dev (device, width*height uint32); width, height in [1, 65536]; exposure finite
+ * and > 0.  bh_bloom_apply_display runs bh_bloom_apply's glare pass on in_rgba_dev and writes
+ * only the encoding of its result to out_rgba8_dev (the linear result is not stored), with
+ * the same weights, handle and stream rules.  For both, the output must not overlap the
+ * input (BH_EINVAL). */
+bh_status bh_tonemap(bh_ctx* ctx, const float* in_rgba_dev, uint32_t* out_rgba8_dev,
+                     int32_t width, int32_t height, float exposure, void* hip_stream);
+bh_status bh_bloom_apply_display(bh_bloom* b, const float* weights, float exposure,
+                                 const float* in_rgba_dev, uint32_t* out_rgba8_dev,
+                                 void* hip_stream);
+
 /* ---- star map (Section 3.3.2 "Emitted light") -------------------------------------- */
 
 #define BH_TEXEL_FP16 0     /* RGBA16F texels: I (per-level power-of-two scale), T, p_u, p_v */

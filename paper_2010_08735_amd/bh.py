@@ -25,7 +25,8 @@ EXPORTS = [
     "bh_create", "bh_destroy", "bh_last_error", "bh_bytes_in_use",
     "bh_precompute_tables", "bh_tables_download", "bh_tables_download_time", "bh_release_tables",
     "bh_create_particles", "bh_release_particles",
-    "bh_bloom_create", "bh_bloom_apply", "bh_bloom_release",
+    "bh_bloom_create", "bh_bloom_apply", "bh_bloom_release", "bh_bloom_apply_display",
+    "bh_tonemap",
     "bh_build_stars", "bh_stars_download", "bh_release_stars",
     "bh_render", "bh_render_march", "bh_render_batch", "bh_tile_config_count", "bh_tile_config_get",
     "bh_set_tile_config", "bh_autotune",
@@ -119,6 +120,8 @@ def lib():
             "bh_bloom_create": ([vp, i32, i32, i32, C.POINTER(vp)], i32),
             "bh_bloom_apply": ([vp, C.POINTER(C.c_float), vp, vp, vp], i32),
             "bh_bloom_release": ([vp], i32),
+            "bh_bloom_apply_display": ([vp, C.POINTER(C.c_float), C.c_float, vp, vp, vp], i32),
+            "bh_tonemap": ([vp, vp, vp, i32, i32, C.c_float, vp], i32),
             "bh_render_march": ([vp, C.POINTER(View), i32, vp, vp, vp], i32),
             "bh_footprint_texels": ([vp, vp, C.POINTER(View), vp, C.POINTER(u64)], i32),
             "bh_band_table_info": ([vp, C.POINTER(i32), C.POINTER(C.c_float),
@@ -293,14 +296,28 @@ def bh_bloom_create(ctx, width: int, height: int, levels: int) -> int:
 
 def bh_bloom_apply(b, weights, in_ptr, out_ptr, stream=None) -> None:
     """weights: w_0 .. w_levels (the library reads levels + 1 of them)."""
-    if len(weights) > 17:
-        raise ValueError("at most 17 bloom weights")
-    w = (C.c_float * 17)(*[float(x) for x in weights])  # zero-padded to the largest count
-    _check(lib().bh_bloom_apply(b, w, in_ptr, out_ptr, stream))
+    _check(lib().bh_bloom_apply(b, _bloom_weights(weights), in_ptr, out_ptr, stream))
 
 
 def bh_bloom_release(b) -> None:
     _check(lib().bh_bloom_release(b))
+
+
+def _bloom_weights(weights):
+    if len(weights) > 17:
+        raise ValueError("at most 17 bloom weights")
+    return (C.c_float * 17)(*[float(x) for x in weights])  # zero-padded to the largest count
+
+
+def bh_bloom_apply_display(b, weights, exposure, in_ptr, out_ptr, stream=None) -> None:
+    """Glare pass, then the display encoding of its result into out_ptr (uint32 per pixel)."""
+    _check(lib().bh_bloom_apply_display(b, _bloom_weights(weights), float(exposure), in_ptr,
+                                        out_ptr, stream))
+
+
+def bh_tonemap(ctx, in_ptr, out_ptr, width: int, height: int, exposure, stream=None) -> None:
+    """Display encoding of a linear RGBA32F image into uint32 pixels (bytes R, G, B, 255)."""
+    _check(lib().bh_tonemap(ctx, in_ptr, out_ptr, width, height, float(exposure), stream))
 
 
 def bh_march_rays(ctx, rays_ptr, n, max_steps, out_ptr, stream=None) -> None:

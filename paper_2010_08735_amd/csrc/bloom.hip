@@ -14,9 +14,15 @@
 //                 tile) and writes them (HBM-bound: reads the image once);
 //   k_bloom_tail  one workgroup builds the coarse levels 7..K and their U chain, which are
 //                 small (at most 120 x 68 pixels at 7680 x 4320), only when K > 6;
-//   k_bloom_up    one workgroup per 64x64 output tile runs the U chain for levels 6..1 over
-//                 the tile plus the one-pixel halo each bilinear doubling needs, in LDS, then
-//                 writes O (HBM-bound: reads the image once more, writes O).
+//   k_bloom_up    one workgroup per 64x64 output tile (32x32 when encoding for display)
+//                 runs the U chain for levels 6..1 over the tile plus the one-pixel halo each
+//                 bilinear doubling needs, in LDS, then writes O (HBM-bound: reads the image
+//                 once more, writes O), or O's display encoding (below) in place of O.
+//
+// Display encoding (the tone mapping that follows the glare pass; the paper prints no
+// operator, so this is one reading): per colour channel c, x = exposure * c, y = 1 - exp(-x)
+// (0 for x <= 0 or NaN), v = the sRGB transfer function of y (IEC 61966-2-1), 8-bit code
+// floor(255 v + 1/2); alpha 255; bytes R, G, B, A.  k_tonemap applies it to a whole image.
 #include "bh_dev.h"
 
 namespace bh {
@@ -43,6 +49,41 @@ __device__ __forceinline__ float4 blend(float4 v00, float4 v10, float4 v01, floa
                          gx * v01.w + fx * v11.w);
   return make_float4(gy * a.x + fy * b.x, gy * a.y + fy * b.y, gy * a.z + fy * b.z,
                      gy * a.w + fy * b.w);
+}
+
+// ---- display encoding ------------------------------------------------------------------------
+
+// 8-bit code of one colour channel.  1 - exp(-x) loses ~1e-7 absolute to cancellation, which
+// the linear sRGB segment (3295 codes per unit) would turn into 4e-4 codes, so below x = 1/16
+// it comes from its Taylor series to x^5 (truncation below 1e-9 relative).  With hardware
+// exp2 and log2 (about 1 ulp each) the value whose floor is the code stays within 2e-4 of its
+// exact value.
+__device__ __forceinline__ uint32_t display_code(float c, float exposure) {
+  const float x = exposure * c;
+  if (!(x > 0.0f)) return 0u;
+  const float series =
+      x * fmaf(-x, fmaf(-x, fmaf(-x, fmaf(-x, 1.0f / 120.0f, 1.0f / 24.0f), 1.0f / 6.0f), 0.5f),
+               1.0f);
+  const float y = x < 0.0625f ? series
+                              : 1.0f - __builtin_amdgcn_exp2f(x * -1.44269504088896341f);
+  const float v = y <= 0.0031308f
+                      ? 12.92f * y
+                      : fmaf(1.055f,
+                             __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(y) * (1.0f / 2.4f)),
+                             -0.055f);
+  return min((uint32_t)fmaf(255.0f, v, 0.5f), 255u);  // v >= 0: truncation is the floor
+}
+
+__device__ __forceinline__ uint32_t display_pixel(float4 c, float exposure) {
+  return display_code(c.x, exposure) | (display_code(c.y, exposure) << 8) |
+         (display_code(c.z, exposure) << 16) | 0xff000000u;
+}
+
+__global__ void __launch_bounds__(256)
+    k_tonemap(const float4* __restrict__ in, uint32_t* __restrict__ out, int64_t n,
+              float exposure) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) out[i] = display_pixel(in[i], exposure);
 }
 
 // ---- level building inside one 64 x 64 tile --------------------------------------------------
@@ -254,12 +295,17 @@ __device__ __forceinline__ void u_level(const BloomDev& B, const float4 (&p)[UpL
   }
 }
 
-constexpr int kBloomUpTile = 64;
+// Output tile edge: 64 for the linear output; 32 when the pass also encodes for display, whose
+// per-pixel arithmetic (three transcendentals per channel at the end of each workgroup)
+// overlaps other workgroups' memory traffic better with four times as many of them.
+constexpr int kBloomUpTile = 64, kBloomUpTileDisplay = 32;
 
-template <int T>
+// DISPLAY: `out` receives the display encoding of O (uint32 per pixel), else O (float4)
+template <int T, bool DISPLAY>
 __global__ void __launch_bounds__(256)
-    k_bloom_up(const float4* __restrict__ img, float4* __restrict__ out,
-               const float4* __restrict__ P, const float4* __restrict__ U, BloomDev B) {
+    k_bloom_up(const float4* __restrict__ img, void* __restrict__ out,
+               const float4* __restrict__ P, const float4* __restrict__ U, BloomDev B,
+               float exposure) {
   constexpr int SA = UpLevel<T, 1>::S, SB = UpLevel<T, 2>::S;
   static_assert(UpLevel<T, 3>::S == SA && UpLevel<T, 4>::S == SB, "odd / even strides");
   static_assert(256 % T == 0 && T % (256 / T) == 0, "whole rows per pass, whole passes per tile");
@@ -326,12 +372,24 @@ __global__ void __launch_bounds__(256)
       v = blend(sa[ya * SA + xa], sa[ya * SA + xb], sa[yb * SA + xa], sa[yb * SA + xb],
                 (x & 1) ? 0.25f : 0.75f, (y & 1) ? 0.25f : 0.75f);
     }
-    out[i] = f4_fma(w0, im[j], v);
+    const float4 o = f4_fma(w0, im[j], v);
+    if constexpr (DISPLAY)
+      static_cast<uint32_t*>(out)[i] = display_pixel(o, exposure);
+    else
+      static_cast<float4*>(out)[i] = o;
   }
 }
 
-hipError_t launch_bloom(const float4* in, float4* out, float4* P, float4* U, const BloomDev& B,
-                        hipStream_t s) {
+hipError_t launch_tonemap(const float4* in, uint32_t* out, int64_t n, float exposure,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_tonemap, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, out, n,
+                     exposure);
+  return hipGetLastError();
+}
+
+// display: write the display encoding of O (exposure) to `out` (uint32 per pixel), else O
+hipError_t launch_bloom(const float4* in, void* out, float4* P, float4* U, const BloomDev& B,
+                        bool display, float exposure, hipStream_t s) {
   const int tiles = B.tiles_x * B.tiles_y;
   if (B.levels >= 1) {
     hipLaunchKernelGGL(k_bloom_down, dim3(tiles), dim3(256), 0, s, in, P, B);
@@ -348,9 +406,14 @@ hipError_t launch_bloom(const float4* in, float4* out, float4* P, float4* U, con
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  const int ut = ((B.w[0] + kBloomUpTile - 1) / kBloomUpTile) *
-                 ((B.h[0] + kBloomUpTile - 1) / kBloomUpTile);
-  hipLaunchKernelGGL(k_bloom_up<kBloomUpTile>, dim3(ut), dim3(256), 0, s, in, out, P, U, B);
+  const int T = display ? kBloomUpTileDisplay : kBloomUpTile;
+  const int ut = ((B.w[0] + T - 1) / T) * ((B.h[0] + T - 1) / T);
+  if (display)
+    hipLaunchKernelGGL((k_bloom_up<kBloomUpTileDisplay, true>), dim3(ut), dim3(256), 0, s, in,
+                       out, P, U, B, exposure);
+  else
+    hipLaunchKernelGGL((k_bloom_up<kBloomUpTile, false>), dim3(ut), dim3(256), 0, s, in, out, P,
+                       U, B, exposure);
   return hipGetLastError();
 }
 

@@ -47,8 +47,10 @@ hipError_t launch_render_batch(int cfg, int persistent, int anim, const ViewDev*
 hipError_t launch_trace_rays(const TablesDev& T, const float* rays, int64_t n, float4* out,
                              float4* out_time, hipStream_t s);
 hipError_t launch_render_march(const ViewDev& v, const LutDev& L, hipStream_t s);
-hipError_t launch_bloom(const float4* in, float4* out, float4* P, float4* U, const BloomDev& B,
-                        hipStream_t s);
+hipError_t launch_bloom(const float4* in, void* out, float4* P, float4* U, const BloomDev& B,
+                        bool display, float exposure, hipStream_t s);
+hipError_t launch_tonemap(const float4* in, uint32_t* out, int64_t n, float exposure,
+                          hipStream_t s);
 hipError_t launch_march_rays(const float* rays, int64_t n, int nsteps, float h, float4* out,
                              hipStream_t s);
 hipError_t launch_render_count(const ViewDev& v, const TablesDev& T, const LutDev& L,
@@ -556,16 +558,56 @@ extern "C" bh_status bh_bloom_create(bh_ctx* c, int32_t width, int32_t height, i
   return BH_OK;
 }
 
-extern "C" bh_status bh_bloom_apply(bh_bloom* b, const float* weights, const float* in,
-                                    float* out, void* stream) {
-  if (!b || !weights || !in || !out) return fail(BH_EINVAL, "NULL argument");
-  BloomDev B = b->B;
+static bh_status bloom_weights(const bh_bloom* b, const float* weights, BloomDev& B) {
+  B = b->B;
   for (int k = 0; k <= b->levels; ++k) {
     if (!std::isfinite(weights[k])) return fail(BH_EINVAL, "non-finite bloom weight");
     B.wt[k] = weights[k];
   }
+  return BH_OK;
+}
+
+static bool bad_exposure(float e) { return !(e > 0.0f) || !std::isfinite(e); }
+
+// [a, a + na) and [b, b + nb) share a byte
+static bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+  return x < y + nb && y < x + na;
+}
+
+extern "C" bh_status bh_bloom_apply(bh_bloom* b, const float* weights, const float* in,
+                                    float* out, void* stream) {
+  if (!b || !weights || !in || !out) return fail(BH_EINVAL, "NULL argument");
+  BloomDev B;
+  if (bh_status st = bloom_weights(b, weights, B)) return st;
   HIPCHK(hipSetDevice(b->ctx->device));
-  HIPCHK(launch_bloom((const float4*)in, (float4*)out, b->P, b->U, B, (hipStream_t)stream));
+  HIPCHK(launch_bloom((const float4*)in, out, b->P, b->U, B, false, 1.0f, (hipStream_t)stream));
+  return BH_OK;
+}
+
+extern "C" bh_status bh_bloom_apply_display(bh_bloom* b, const float* weights, float exposure,
+                                            const float* in, uint32_t* out, void* stream) {
+  if (!b || !weights || !in || !out) return fail(BH_EINVAL, "NULL argument");
+  if (bad_exposure(exposure)) return fail(BH_EINVAL, "exposure must be finite and > 0");
+  const size_t n = (size_t)b->width * b->height;
+  if (overlaps(in, 16 * n, out, 4 * n)) return fail(BH_EINVAL, "output overlaps the input");
+  BloomDev B;
+  if (bh_status st = bloom_weights(b, weights, B)) return st;
+  HIPCHK(hipSetDevice(b->ctx->device));
+  HIPCHK(launch_bloom((const float4*)in, out, b->P, b->U, B, true, exposure, (hipStream_t)stream));
+  return BH_OK;
+}
+
+extern "C" bh_status bh_tonemap(bh_ctx* c, const float* in, uint32_t* out, int32_t width,
+                                int32_t height, float exposure, void* stream) {
+  if (!c || !in || !out) return fail(BH_EINVAL, "NULL argument");
+  if (width < 1 || height < 1 || width > 65536 || height > 65536)
+    return fail(BH_EINVAL, "bad image size");
+  if (bad_exposure(exposure)) return fail(BH_EINVAL, "exposure must be finite and > 0");
+  const size_t n = (size_t)width * height;
+  if (overlaps(in, 16 * n, out, 4 * n)) return fail(BH_EINVAL, "output overlaps the input");
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(launch_tonemap((const float4*)in, out, (int64_t)n, exposure, (hipStream_t)stream));
   return BH_OK;
 }
 
