@@ -395,3 +395,41 @@ def test_tent_filter_conserves_flux(orc, W, fov, n0):
     assert (n0 == 64) == (px["mip_level"].max() == 0)
     lum = px["star_rgb"].sum()
     assert abs(lum / 0.5 - 1) < 5e-3
+
+
+def test_lensing_factor_in_flat_space(orc):
+    """Section 3.4.1: Omega/Omega' is the ratio of the cross products of the screen-space
+    derivatives of q (camera side) and d' (emitter side).  Far from the hole d' is q rotated
+    into the world frame, so the ratio is (exact |d_w q x d_h q|) / (quad differences of q):
+    the numerator is taken here from central differences of normalize(x, y, -f) and the
+    denominator from the pixel grid, both in numpy.  A 90-degree field on 16 pixels makes the
+    ratio depart from 1 by up to ~10%, so a wrong power of |Q| or a wrong difference shows."""
+    pos = scenes.spherical_position(1e12, math.pi / 2 - 0.3, 0.4)
+    W = 16
+    fov = math.pi / 2
+    v = scenes.aimed_view(pos, np.zeros(3), W, W, fov_y=fov)
+    field = scenes.star_field(2000, 5)
+    px = orc.render_quads(v, scenes.all_quads(W, W), cube=orc.cubemap(field, 64), n0=64)
+    f = 0.5 * W / math.tan(0.5 * fov)
+
+    def q(x, y):
+        Q = np.array([x + 0.5 - 0.5 * W, 0.5 * W - y - 0.5, -f])
+        return Q / np.linalg.norm(Q)
+
+    eps = 1e-4
+    checked = 0
+    ratios = []
+    for p in px:
+        x, y = int(p["x"]), int(p["y"])
+        dqx = (q(x + eps, y) - q(x - eps, y)) / (2 * eps)
+        dqy = (q(x, y + eps) - q(x, y - eps)) / (2 * eps)
+        om = np.linalg.norm(np.cross(dqx, dqy))
+        x0, y0 = x & ~1, y & ~1
+        dw = q(x0 + 1, y) - q(x0, y)
+        dh = q(x, y0 + 1) - q(x, y0)
+        omp = np.linalg.norm(np.cross(dw, dh))
+        assert abs(p["omega_ratio"] / (om / omp) - 1) < 1e-6, (x, y)
+        ratios.append(om / omp)
+        checked += 1
+    assert checked == W * W
+    assert max(abs(r - 1) for r in ratios) > 0.05
