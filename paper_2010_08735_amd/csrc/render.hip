@@ -16,9 +16,10 @@
 //   disc        T' from the temperature law, Doppler factor g(k,l)/g(k',l') with the
 //               Keplerian k' (eq. k_prime), band radiances of a blackbody at D T'
 //               (Section 3.4.2), front-to-back composite
-//   stars       fine quad differences of d' and q, face Jacobian, mip level such that the
-//               extended footprint spans at most 9x9 texels, tent-weighted gather
-//               f(w) f(h), lensing factor Omega/Omega', one Doppler shift per pixel.
+//   stars       fine quad differences of d' (q's derivatives are exact), face Jacobian, mip
+//               level such that the extended footprint spans at most 9x9 texels,
+//               tent-weighted gather f(w) f(h), lensing factor Omega/Omega', one Doppler
+//               shift per pixel.
 #include "bh_dev.h"
 
 namespace bh {
@@ -336,30 +337,38 @@ __device__ __forceinline__ float disc_density(const ViewDev& v, float ht, float 
   float rho = 0.0f;
   // particles are sorted by the inner end of their radial reach; no particle before
   // pstart[bin of hr] reaches out to hr.  The wave starts at the smallest such index over
-  // its active lanes (an LDS minimum in the wave's own slot: one wave's LDS operations
-  // complete in order), so the loop index stays wave-uniform and the records are scalar loads.
-  __shared__ int wave_start[16];
+  // its active lanes and stops at the first particle whose reach starts beyond the largest
+  // hr of its active lanes (an LDS minimum and maximum in the wave's own slots: one wave's
+  // LDS operations complete in order), so the loop and its exit are wave-uniform and the
+  // records are scalar loads; each lane tests its own hr against the particle's reach.
+  __shared__ int wave_start[16], wave_hmax[16];
   int j0 = 0;
+  float hmax = 0.0f;
   if (v.nparts > 0) {
     int* slot = &wave_start[threadIdx.x >> 6];
+    int* hslot = &wave_hmax[threadIdx.x >> 6];
     *slot = v.nparts;
+    *hslot = 0;
     atomicMin(slot, v.pstart[(int)fminf(hr * v.pscale, (float)v.pbins)]);
+    atomicMax(hslot, __float_as_int(hr));  // hr > 0: its bit patterns order as its values
     j0 = __builtin_amdgcn_readfirstlane(*(volatile int*)slot);
+    hmax = __int_as_float(__builtin_amdgcn_readfirstlane(*(volatile int*)hslot));
   }
   for (int j = j0; j < v.nparts; ++j) {
-    float4 p0 = v.parts[2 * j], p1 = v.parts[2 * j + 1];
-    if (hr < p1.y) break;  // this and every later particle starts beyond hr
-    if (hr > p1.z) continue;
-    float ph = fmaf(p0.w, ht, p1.x);
-    float a = hphi - ph;
-    a -= k2Pi * floorf(a * (1.0f / k2Pi));
-    // sin^2 x = (1 - cos 2x) / 2, with the hardware cosine (argument in turns: 2x / 2 pi)
-    const float c2 = __builtin_amdgcn_cosf(p0.z * (a + ph) * (1.0f / kPi));
-    float ua = fmaf(p0.y, fmaf(-0.5f, c2, 0.5f), p0.x);
-    float dr = hr - fdiv(1.0f, ua);
-    float da = a * (1.0f / kPi) - 1.0f;
-    float d2 = da * da + dr * dr;
-    if (d2 < 1.0f) rho += (1.0f - d2) * (1.0f - d2);
+    const float4 p0 = v.parts[2 * j], p1 = v.parts[2 * j + 1];
+    if (hmax < p1.y) break;  // this and every later particle starts beyond every lane's hr
+    if (hr >= p1.y && hr <= p1.z) {
+      float ph = fmaf(p0.w, ht, p1.x);
+      float a = hphi - ph;
+      a -= k2Pi * floorf(a * (1.0f / k2Pi));
+      // sin^2 x = (1 - cos 2x) / 2, with the hardware cosine (argument in turns: 2x / 2 pi)
+      const float c2 = __builtin_amdgcn_cosf(p0.z * (a + ph) * (1.0f / kPi));
+      float ua = fmaf(p0.y, fmaf(-0.5f, c2, 0.5f), p0.x);
+      float dr = hr - fdiv(1.0f, ua);
+      float da = a * (1.0f / kPi) - 1.0f;
+      float d2 = da * da + dr * dr;
+      if (d2 < 1.0f) rho += (1.0f - d2) * (1.0f - d2);
+    }
   }
   return rho;
 }
@@ -496,8 +505,6 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
   cap |= __builtin_amdgcn_mov_dpp(cap, 0x4E, 0xF, 0xF, true);
   float dw0 = quad_diff<1>(dp0), dw1 = quad_diff<1>(dp1), dw2 = quad_diff<1>(dp2);
   float dh0 = quad_diff<2>(dp0), dh1 = quad_diff<2>(dp1), dh2 = quad_diff<2>(dp2);
-  float qw0 = quad_diff<1>(q0), qw1 = quad_diff<1>(q1), qw2 = quad_diff<1>(q2);
-  float qh0 = quad_diff<2>(q0), qh1 = quad_diff<2>(q1), qh2 = quad_diff<2>(q2);
   int mip = 255;
   if (cap) bits |= BH_STAR_ZEROED_BIT;
   if (v.has_stars && !cap) {
@@ -582,16 +589,16 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
       A *= iscale;
       B *= S.fp16 ? iscale * 1024.0f : iscale;
     }
-    float cqx = qw1 * qh2 - qw2 * qh1, cqy = qw2 * qh0 - qw0 * qh2, cqz = qw0 * qh1 - qw1 * qh0;
     float cdx = dw1 * dh2 - dw2 * dh1, cdy = dw2 * dh0 - dw0 * dh2, cdz = dw0 * dh1 - dw1 * dh0;
-    // Omega / Omega' = |q_w x q_h| / |d'_w x d'_h|
-    const float om2 = cqx * cqx + cqy * cqy + cqz * cqz;
+    // Omega / Omega' = |q_w x q_h| / |d'_w x d'_h|; q = (q^w, q^h, -f) / |.| has exact
+    // partial derivatives, |q_w x q_h| = f / |(q^w, q^h, -f)|^3 = f inq^3
+    const float om = v.f * (inq * inq) * inq;
     const float omp2 = cdx * cdx + cdy * cdy + cdz * cdz;
     if (A > 0.0f && omp2 > 0.0f) {
       float Tpix = fdiv(B, A);
       float4 Lr = band_lookup(L, dcam * Tpix);
       float4 Ln = band_lookup(L, Tpix);
-      float sc = trans * v.k_star * fsqrt(om2) * __builtin_amdgcn_rsqf(omp2) * fdiv(A, Ln.w);
+      float sc = trans * v.k_star * om * __builtin_amdgcn_rsqf(omp2) * fdiv(A, Ln.w);
       cr += sc * Lr.x;
       cg += sc * Lr.y;
       cb += sc * Lr.z;
