@@ -52,12 +52,16 @@ struct StarsDev {
 };
 
 // ---- per-view constant block (host computes it in FP64 from bh_view) -----------------
+// The camera axes and the velocity direction are passed split into their parts transverse
+// to the radial direction e_x' and their radial components: a beam's transverse part is then
+// a sum of small, accurately computed terms, and its angle to e_x' keeps its relative
+// precision even for a distant camera, whose beams are all nearly radial.
 struct ViewDev {
   float rhat[3], sq1mu;   // e_x' = radial unit vector at the camera, sqrt(1 - u_c)
-  float ew[3], f;         // camera axes in world coordinates, focal length in pixels
+  float ew[3], f;         // camera axes' parts transverse to e_x' (world), focal length in pixels
   float eh[3], u_c;
   float ed[3], gamma;
-  float vhat[3], vmag;    // camera velocity direction and speed (static frame)
+  float vhat[3], vmag;    // velocity direction's part transverse to e_x', speed (static frame)
   float half_w, half_h, u_ic, u_oc;
   float inv_sq1mu, T0, T_exp, rho;
   float k_disc, k_star, T_norm, march_h;   // march_h: ray-marching step (marching only)
@@ -72,6 +76,10 @@ struct ViewDev {
   const int* pstart;      // first particle reaching radius bin floor(r * pscale), pbins + 1
   float pscale;
   int pbins;
+  // radial components of e_w, e_h, e_d and of the velocity direction.  Last in the record:
+  // inserted before the star-map fields it shifted their offsets and the render measured
+  // 2.6% slower at 1920x1080.
+  float er[4];
 };
 
 // Bloom launch record: the image's box pyramid, levels 0 (the image) .. levels <= 16, and

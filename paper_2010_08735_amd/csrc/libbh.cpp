@@ -812,13 +812,22 @@ static bh_status make_view(const bh_view* v, float* out, float* aov, ViewDev* o)
   if (!out) return fail(BH_EINVAL, "NULL output");
   memset(o, 0, sizeof(*o));
   double u = 1.0 / r;
+  double rh[3], vh[3];
   for (int i = 0; i < 3; ++i) {
-    o->rhat[i] = (float)(v->cam_pos[i] / (r * v->r_s));
-    o->ew[i] = (float)R[i];
-    o->eh[i] = (float)R[3 + i];
-    o->ed[i] = (float)R[6 + i];
-    o->vhat[i] = vm > 0 ? (float)(v->cam_vel[i] / vm) : 0.0f;
+    rh[i] = v->cam_pos[i] / (r * v->r_s);
+    vh[i] = vm > 0 ? v->cam_vel[i] / vm : 0.0;
   }
+  // a vector's radial component and its part transverse to rh, in FP64
+  auto split = [&](const double* w, float* perp, float* radial) {
+    const double c = w[0] * rh[0] + w[1] * rh[1] + w[2] * rh[2];
+    for (int i = 0; i < 3; ++i) perp[i] = (float)(w[i] - c * rh[i]);
+    *radial = (float)c;
+  };
+  split(R, o->ew, &o->er[0]);
+  split(R + 3, o->eh, &o->er[1]);
+  split(R + 6, o->ed, &o->er[2]);
+  split(vh, o->vhat, &o->er[3]);
+  for (int i = 0; i < 3; ++i) o->rhat[i] = (float)rh[i];
   o->sq1mu = (float)std::sqrt(1.0 - u);
   o->inv_sq1mu = (float)(1.0 / std::sqrt(1.0 - u));
   o->u_c = (float)u;

@@ -387,23 +387,27 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
   float qh = v.half_h - (float)py - 0.5f;
   float inq = __builtin_amdgcn_rsqf(qw * qw + qh * qh + v.f * v.f);  // argument >= f^2 > 0
   float q0 = qw * inq, q1 = qh * inq, q2 = -v.f * inq;
+  // camera direction and its aberration into the static frame, as the part transverse to
+  // e_x' (n0, n1, n2) and the radial component nr
   float nc0 = q0 * v.ew[0] + q1 * v.eh[0] + q2 * v.ed[0];
   float nc1 = q0 * v.ew[1] + q1 * v.eh[1] + q2 * v.ed[1];
   float nc2 = q0 * v.ew[2] + q1 * v.eh[2] + q2 * v.ed[2];
-  float nv = nc0 * v.vhat[0] + nc1 * v.vhat[1] + nc2 * v.vhat[2];
+  float ncr = q0 * v.er[0] + q1 * v.er[1] + q2 * v.er[2];
+  float nv = nc0 * v.vhat[0] + nc1 * v.vhat[1] + nc2 * v.vhat[2] + ncr * v.er[3];
   float ka = (v.gamma - 1.0f) * nv - v.gamma * v.vmag;
-  float ns0 = nc0 + ka * v.vhat[0], ns1 = nc1 + ka * v.vhat[1], ns2 = nc2 + ka * v.vhat[2];
+  // coordinate direction d: the transverse part as is, the radial component scaled by
+  // sqrt(1 - u) (eq. staticbasis)
+  const float d0 = nc0 + ka * v.vhat[0], d1 = nc1 + ka * v.vhat[1], d2 = nc2 + ka * v.vhat[2];
+  const float dr = v.sq1mu * (ncr + ka * v.er[3]);
   float dcam = fdiv(v.inv_sq1mu, v.gamma * (1.0f - v.vmag * nv));
-  float nr = ns0 * v.rhat[0] + ns1 * v.rhat[1] + ns2 * v.rhat[2];
-  float kr = (v.sq1mu - 1.0f) * nr;
-  float d0 = ns0 + kr * v.rhat[0], d1 = ns1 + kr * v.rhat[1], d2 = ns2 + kr * v.rhat[2];
+  // e_z' = e_x' x d / |e_x' x d|, and |e_x' x d| = |transverse part|
   float cz0 = v.rhat[1] * d2 - v.rhat[2] * d1;
   float cz1 = v.rhat[2] * d0 - v.rhat[0] * d2;
   float cz2 = v.rhat[0] * d1 - v.rhat[1] * d0;
-  const float ncz2 = cz0 * cz0 + cz1 * cz1 + cz2 * cz2;
-  float dr = d0 * v.rhat[0] + d1 * v.rhat[1] + d2 * v.rhat[2];
-  const float dn2 = d0 * d0 + d1 * d1 + d2 * d2;
+  const float ncz2 = d0 * d0 + d1 * d1 + d2 * d2;
+  const float dn2 = ncz2 + dr * dr;
   float ncz, inv_ncz;  // |e_x' x d| and its inverse
+  float ey0, ey1, ey2;  // e_y' = e_z' x e_x'
   unsigned bits = 0;
   float u_ic = v.u_ic, u_oc = v.u_oc;
   if (!(ncz2 > 1e-14f * dn2)) {
@@ -415,6 +419,9 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
     cz2 = v.rhat[0] * ax1 - v.rhat[1] * ax0;
     float n2 = __builtin_amdgcn_rsqf(cz0 * cz0 + cz1 * cz1 + cz2 * cz2);
     cz0 *= n2; cz1 *= n2; cz2 *= n2;
+    ey0 = cz1 * v.rhat[2] - cz2 * v.rhat[1];
+    ey1 = cz2 * v.rhat[0] - cz0 * v.rhat[2];
+    ey2 = cz0 * v.rhat[1] - cz1 * v.rhat[0];
     ncz = fmaxf(fsqrt(ncz2), 1e-7f * fsqrt(dn2));
     inv_ncz = fdiv(1.0f, ncz);
     u_ic = -1.0f;
@@ -422,12 +429,10 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
     inv_ncz = __builtin_amdgcn_rsqf(ncz2);
     ncz = ncz2 * inv_ncz;
     cz0 *= inv_ncz; cz1 *= inv_ncz; cz2 *= inv_ncz;
+    // (e_x' x d) x e_x' is d's transverse part
+    ey0 = d0 * inv_ncz; ey1 = d1 * inv_ncz; ey2 = d2 * inv_ncz;
   }
   float delta = fatan2_pos(ncz, dr);
-  // e_y' = e_z' x e_x'
-  float ey0 = cz1 * v.rhat[2] - cz2 * v.rhat[1];
-  float ey1 = cz2 * v.rhat[0] - cz0 * v.rhat[2];
-  float ey2 = cz0 * v.rhat[1] - cz1 * v.rhat[0];
   // t = +-(e_z x e_z') with t.e_y' >= 0; alpha = angle(e_x', t)
   float t0 = -cz1, t1 = cz0;
   float nt = fsqrt(t0 * t0 + t1 * t1);

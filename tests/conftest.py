@@ -53,6 +53,16 @@ def orc_tables(orc):
 
 
 @pytest.fixture(scope="session")
+def small_scene(gpu_ctx, orc):
+    """20 000 seeded stars in a 6 x 256^2 FP16 map (GPU) and the oracle's map."""
+    from paper_2010_08735_amd import bh, scenes
+    field = scenes.star_field(20000, 0)
+    n0 = 256
+    h = gpu_star_map(gpu_ctx, field, n0, bh.BH_TEXEL_FP16, key=1000)
+    return field, n0, h, orc.cubemap(field, n0)
+
+
+@pytest.fixture(scope="session")
 def big_field_scene(gpu_ctx, orc):
     """One million seeded stars in a 6 x 2048^2 FP16 map (GPU) and the oracle's map."""
     from paper_2010_08735_amd import bh, scenes

@@ -15,7 +15,6 @@ import pytest
 
 from paper_2010_08735_amd import bh, scenes
 
-from conftest import gpu_star_map
 import parity
 
 pytestmark = pytest.mark.gpu
@@ -95,14 +94,6 @@ def test_radial_rays(gpu_ctx, orc):
         assert not bits[k] & bh.BH_AOV_UNFINISHED
         if not o["captured"]:
             assert abs(g[k, 0] - o["delta_prime"]) < 1e-5
-
-
-@pytest.fixture(scope="module")
-def small_scene(gpu_ctx, orc):
-    field = scenes.star_field(20000, 0)
-    n0 = 256
-    h = gpu_star_map(gpu_ctx, field, n0, bh.BH_TEXEL_FP16, key=1000)
-    return field, n0, h, orc.cubemap(field, n0)
 
 
 def render_march_gpu(ctx, view, stars, nsteps):

@@ -141,14 +141,6 @@ def test_traceray_matches_oracle(gpu_ctx, gpu_tables, orc, orc_tables):
     assert stats["exact"]["dprime_max"] < 1e-3 and stats["exact"]["u_max"] < 1e-3
 
 
-@pytest.fixture(scope="module")
-def small_scene(gpu_ctx, orc):
-    field = scenes.star_field(20000, 0)
-    n0 = 256
-    h = gpu_star_map(gpu_ctx, field, n0, bh.BH_TEXEL_FP16, key=1000)
-    return field, n0, h, orc.cubemap(field, n0)
-
-
 def test_small_static_view_full_frame(gpu_ctx, gpu_tables, orc, orc_tables, small_scene):
     """128x128 static camera at r = 15: every pixel against the oracle."""
     field, n0, h, cube = small_scene
