@@ -325,3 +325,46 @@ def test_batched_views_sampled_parity(gpu_ctx, gpu_tables, orc, orc_tables, big_
     n = sum(w["star_n"] for w in worst.values())
     within = sum(w["star_2e-2"] * w["star_n"] for w in worst.values())
     assert within / n > 0.99
+
+
+def test_autotune_sweep_renders_every_form_bitwise_equal():
+    """bh_autotune renders the views with every tile configuration in both batched forms
+    (one workgroup per tile, then persistent workgroups on an atomic counter), the last
+    being the persistent form of the last configuration, into the caller's images: those
+    images, and a batch rendered afterwards with the chosen form, equal bh_render bit for
+    bit.  A context of its own, so the choice does not carry into other tests."""
+    import torch
+    ctx = bh.bh_create(0, 0)
+    try:
+        tables = bh.bh_precompute_tables(ctx, 512, 64, 32, bh.BH_TAB_FP64_BAND, 0.05)
+        hs = gpu_star_map(ctx, scenes.star_field(20000, 0), 256, bh.BH_TEXEL_FP16, key=5)
+        sizes = [(64, 48), (100, 37), (16, 16), (130, 66)]
+        views = []
+        for k, (w, h) in enumerate(sizes):
+            v = scenes.small_static_view()
+            v.width, v.height = w, h
+            v.cam_pos = tuple(float(x) for x in
+                              scenes.spherical_position(12.0 + 3 * k, math.radians(70 + 5 * k), 0.3 * k))
+            v.cam_rot = scenes.look_rotation(-np.array(v.cam_pos))
+            views.append(v)
+        recs = [bh.make_view(v, hs) for v in views]
+        outs = [torch.full((h, w, 4), float("nan"), dtype=torch.float32, device="cuda")
+                for (w, h) in sizes]
+        best, ms = bh.bh_autotune(ctx, tables, recs, [o.data_ptr() for o in outs], reps=1)
+        torch.cuda.synchronize()
+        assert 0 <= best < 2 * bh.bh_tile_config_count() and all(m > 0 for m in ms)
+        swept = [o.cpu().numpy() for o in outs]
+        for o in outs:
+            o.fill_(float("nan"))
+        bh.bh_render_batch(ctx, tables, recs, [o.data_ptr() for o in outs], bh.current_stream())
+        torch.cuda.synchronize()
+        chosen = [o.cpu().numpy() for o in outs]
+        for (w, h), rec, a, b in zip(sizes, recs, swept, chosen):
+            ref = torch.full((h, w, 4), float("nan"), dtype=torch.float32, device="cuda")
+            bh.bh_render(ctx, tables, rec, ref.data_ptr(), None, bh.current_stream())
+            torch.cuda.synchronize()
+            r = ref.cpu().numpy()
+            assert np.isfinite(r).all()
+            assert np.array_equal(a, r) and np.array_equal(b, r)
+    finally:
+        bh.bh_destroy(ctx)
