@@ -13,7 +13,8 @@
 //                 (a level-k pixel depends on a 2^k x 2^k block of the image, inside one
 //                 tile) and writes them (HBM-bound: reads the image once);
 //   k_bloom_tail  one workgroup builds the coarse levels 7..K and their U chain, which are
-//                 small (at most 120 x 68 pixels at 7680 x 4320), only when K > 6;
+//                 small (at most 120 x 68 pixels at 7680 x 4320), only when K > 7 (for
+//                 K = 7 the output pass forms the U_7 values it needs from level 6);
 //   k_bloom_up    one workgroup per 64x64 output tile (32x32 when encoding for display)
 //                 runs the U chain for levels 6..1 over the tile plus the one-pixel halo each
 //                 bilinear doubling needs, in LDS, then writes O (HBM-bound: reads the image
@@ -229,16 +230,51 @@ __device__ __forceinline__ void load_p(const BloomDev& B, const float4* __restri
   }
 }
 
-// U_7 at the four coarse neighbours of every level-6 element of the region, from the global
-// U array the tail kernel wrote (only when the pyramid has more than 6 levels)
+// U_7 = w_7 P_7 at level-7 pixel (x, y) of a pyramid of exactly 7 levels, from level 6: the
+// operations of the tail kernel, in its order, so the values are the same bits
+__device__ __forceinline__ float4 u7_from_p6(const BloomDev& B, const float4* __restrict__ P,
+                                             int x, int y) {
+  constexpr int K = kBloomTileLevels + 1;
+  const int px = B.w[K - 1], py = B.h[K - 1];
+  const int x0 = 2 * x, y0 = 2 * y, x1 = min(x0 + 1, px - 1), y1 = min(y0 + 1, py - 1);
+  const float4* src = P + B.off[K - 1];
+  const float4 p = box4(src[(size_t)y0 * px + x0], src[(size_t)y0 * px + x1],
+                        src[(size_t)y1 * px + x0], src[(size_t)y1 * px + x1]);
+  return f4_fma(B.wt[K], p, make_float4(0.f, 0.f, 0.f, 0.f));
+}
+
+// The level-7 neighbourhood of a tile's level-6 region R: at most 3 x 3 pixels
+__device__ __forceinline__ Region coarse_region(const BloomDev& B, const Region& R) {
+  constexpr int K = kBloomTileLevels + 1;
+  return Region{max((R.lox - 1) >> 1, 0), min((R.hix + 1) >> 1, B.w[K] - 1),
+                max((R.loy - 1) >> 1, 0), min((R.hiy + 1) >> 1, B.h[K] - 1)};
+}
+constexpr int kU7Max = 16;  // >= 3 x 3
+
+// U_7 over the coarse region C of a 7-level pyramid, one value per thread, into LDS `su7`
+// (row stride 4)
+__device__ __forceinline__ void fill_u7(const BloomDev& B, const float4* __restrict__ P,
+                                        const Region& C, float4* su7) {
+  const int t = threadIdx.x, w = C.hix - C.lox + 1, h = C.hiy - C.loy + 1;
+  if (t < w * h) {
+    const int x = t % w, y = t / w;
+    su7[y * 4 + x] = u7_from_p6(B, P, C.lox + x, C.loy + y);
+  }
+}
+
+// U_7 at the four coarse neighbours of every level-6 element of the region (only when the
+// pyramid has more than 6 levels): with exactly 7, from `su7` (fill_u7, region C); with
+// more, from the global U array the tail kernel wrote
 template <int T>
 __device__ __forceinline__ void load_u_coarse(const BloomDev& B, const float4* __restrict__ U,
-                                              const Region& R,
+                                              const Region& R, const float4* su7,
+                                              const Region& C,
                                               float4 (&q)[UpLevel<T, kBloomTileLevels>::N][4]) {
   using L = UpLevel<T, kBloomTileLevels>;
   constexpr int K = kBloomTileLevels;
   const int cnx = B.w[K + 1], cny = B.h[K + 1];
   const float4* cu = U + B.off[K + 1];
+  const bool direct = B.levels == K + 1;
 #pragma unroll
   for (int j = 0; j < L::N; ++j) {
     // slots outside the region load a neighbour of its last element, unused: loads that
@@ -248,10 +284,17 @@ __device__ __forceinline__ void load_u_coarse(const BloomDev& B, const float4* _
     const int x = R.lox + min(c, R.hix - R.lox), y = R.loy + min(r, R.hiy - R.loy);
     const int xa = max((x - 1) >> 1, 0), xb = min((x + 1) >> 1, cnx - 1);
     const int ya = max((y - 1) >> 1, 0), yb = min((y + 1) >> 1, cny - 1);
-    q[j][0] = cu[(size_t)ya * cnx + xa];
-    q[j][1] = cu[(size_t)ya * cnx + xb];
-    q[j][2] = cu[(size_t)yb * cnx + xa];
-    q[j][3] = cu[(size_t)yb * cnx + xb];
+    if (direct) {
+      q[j][0] = su7[(ya - C.loy) * 4 + xa - C.lox];
+      q[j][1] = su7[(ya - C.loy) * 4 + xb - C.lox];
+      q[j][2] = su7[(yb - C.loy) * 4 + xa - C.lox];
+      q[j][3] = su7[(yb - C.loy) * 4 + xb - C.lox];
+    } else {
+      q[j][0] = cu[(size_t)ya * cnx + xa];
+      q[j][1] = cu[(size_t)ya * cnx + xb];
+      q[j][2] = cu[(size_t)yb * cnx + xa];
+      q[j][3] = cu[(size_t)yb * cnx + xb];
+    }
   }
 }
 
@@ -338,7 +381,13 @@ __global__ void __launch_bounds__(256)
   if (m >= 2) load_p<T, 2>(B, P, R[2], p2);
   if (m >= 1) load_p<T, 1>(B, P, R[1], p1);
   float4 q6[UpLevel<T, 6>::N][4];
-  if (B.levels > kBloomTileLevels) load_u_coarse<T>(B, U, R[6], q6);
+  __shared__ float4 su7[kU7Max];
+  const Region C7 = coarse_region(B, R[6]);
+  if (B.levels == kBloomTileLevels + 1) {  // uniform: the barrier is reached by all threads
+    fill_u7(B, P, C7, su7);
+    __syncthreads();
+  }
+  if (B.levels > kBloomTileLevels) load_u_coarse<T>(B, U, R[6], su7, C7, q6);
   // this thread's image pixels (column x, rows y0 + kRows j), in flight during the chain;
   // positions past the image's edge load the edge pixel, unused
   constexpr int kRows = 256 / T, kIt = T / kRows;
@@ -396,7 +445,8 @@ hipError_t launch_bloom(const float4* in, void* out, float4* P, float4* U, const
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  if (B.levels > kBloomTileLevels) {
+  // with exactly 7 levels the output pass computes the few U_7 values it needs itself
+  if (B.levels > kBloomTileLevels + 1) {
     const int64_t tail = B.off[B.levels] + (int64_t)B.w[B.levels] * B.h[B.levels] -
                          B.off[kBloomTileLevels + 1];
     if (tail <= kBloomTailLds)
