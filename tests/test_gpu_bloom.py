@@ -29,9 +29,11 @@ def _bloom_gpu(ctx, img, levels, weights, handle=None, in_place=False, stream=No
     return out.cpu().numpy()
 
 
+# exactly 7 levels takes the output pass's own U_7 (no tail launch): ragged and tiny sizes
+# of that depth are included
 CASES = [(1, 1, 0), (1, 1, 3), (3, 5, 2), (64, 64, 6), (65, 33, 7), (130, 70, 9),
          (200, 129, 16), (64, 1, 8), (1, 300, 10), (257, 130, 7), (1920, 1080, 7),
-         (3840, 2160, 8)]
+         (3840, 2160, 8), (1, 1, 7), (3, 200, 7), (700, 5, 7)]
 
 
 @pytest.mark.parametrize("w,h,levels", CASES)
