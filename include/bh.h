@@ -141,7 +141,8 @@ bh_status bh_bloom_release(bh_bloom* b);
  * value stays within 2e-4 of the exact one).
  *
  * bh_tonemap encodes in_rgba_dev (device, width*height float4, row-major) into
- * out_rgba8_dev (device, width*height uint32); width, height in [1, 65536]; exposure finite
+ * out_rgba8_dev (device, width*height uint32); width, height in [1, 65536] with
+ * width * height <= 2^31; exposure finite
  * and > 0.  bh_bloom_apply_display runs bh_bloom_apply's glare pass on in_rgba_dev and writes
  * only the encoding of its result to out_rgba8_dev (the linear result is not stored), with
  * the same weights, handle and stream rules.  For both, the output must not overlap the
@@ -191,7 +192,7 @@ typedef struct {
   double cam_rot[9];    /* rows e_w, e_h, e_d (orthonormal) of the camera in its own
                            (boosted) frame; the camera looks along -e_d                    */
   double fov_y;         /* vertical field of view, radians, (0, pi)                       */
-  int32_t width, height;
+  int32_t width, height; /* pixels, each in [1, 65536], width * height <= 2^31           */
   double disc_r_in;     /* >= 3 r_s (innermost stable circular orbit, Section 3.3.3)       */
   double disc_r_out;    /* > disc_r_in                                                     */
   int32_t disc_T_law;   /* BH_T_*                                                          */
@@ -251,7 +252,8 @@ bh_status bh_render_march(bh_ctx* ctx, const bh_view* v, int32_t max_steps, floa
 
 /* Render n views of any sizes in one persistent launch (work list of tiles, replayed as
  * a HIP graph when the same shapes repeat).  outs_dev[i] has views[i].width*height float4.
- * Per pixel the result is bitwise identical to bh_render. */
+ * Per pixel the result is bitwise identical to bh_render.  BH_EINVAL when the views' tiles
+ * (each view padded to whole tiles of the selected configuration) hold 2^32 pixels or more. */
 bh_status bh_render_batch(bh_ctx* ctx, const bh_tables* t, const bh_view* views, int32_t n,
                           float* const* outs_dev, void* hip_stream);
 
@@ -307,7 +309,8 @@ bh_status bh_serve_drain(bh_ctx* ctx);
 /* ---- unit-level entry points used by the tests ------------------------------------------ */
 
 /* TraceRay (Algorithm 1) alone for n rays given as 5 floats each
- * [u = 1/p^r, delta, alpha, u_ic, u_oc]; writes 4 floats per ray in the AOV layout. */
+ * [u = 1/p^r, delta, alpha, u_ic, u_oc]; writes 4 floats per ray in the AOV layout.
+ * n in [0, 2^31] here and in bh_trace_rays_timed, bh_march_rays and bh_band_eval. */
 bh_status bh_trace_rays(bh_ctx* ctx, const bh_tables* t, const float* rays_dev, int64_t n,
                         float* out_dev, void* hip_stream);
 /* The same, also writing 4 floats per ray to out_time_dev: the retarded times of the two

@@ -71,6 +71,11 @@ static bh_status fail(bh_status s, const std::string& msg) {
   return s;
 }
 
+// One kernel launch covers at most 2^32 - 1 work-items.  Images (width x height) and arrays
+// of rays or temperatures are held to 2^31 elements, which keeps every launch below that
+// bound with its tile padding.
+constexpr int64_t kMaxElems = (int64_t)1 << 31;
+
 #define HIPCHK(expr)                                                                        \
   do {                                                                                      \
     hipError_t e_ = (expr);                                                                 \
@@ -601,7 +606,8 @@ extern "C" bh_status bh_bloom_apply_display(bh_bloom* b, const float* weights, f
 extern "C" bh_status bh_tonemap(bh_ctx* c, const float* in, uint32_t* out, int32_t width,
                                 int32_t height, float exposure, void* stream) {
   if (!c || !in || !out) return fail(BH_EINVAL, "NULL argument");
-  if (width < 1 || height < 1 || width > 65536 || height > 65536)
+  if (width < 1 || height < 1 || width > 65536 || height > 65536 ||
+      (int64_t)width * height > kMaxElems)
     return fail(BH_EINVAL, "bad image size");
   if (bad_exposure(exposure)) return fail(BH_EINVAL, "exposure must be finite and > 0");
   const size_t n = (size_t)width * height;
@@ -791,7 +797,8 @@ static bh_status make_view(const bh_view* v, float* out, float* aov, ViewDev* o)
                         v->cam_vel[2] * v->cam_vel[2]);
   if (!(vm < 1.0)) return fail(BH_EINVAL, "camera speed must be < c");
   if (!(v->fov_y > 0 && v->fov_y < M_PI)) return fail(BH_EINVAL, "fov_y must be in (0, pi)");
-  if (v->width < 1 || v->height < 1 || v->width > 65536 || v->height > 65536)
+  if (v->width < 1 || v->height < 1 || v->width > 65536 || v->height > 65536 ||
+      (int64_t)v->width * v->height > kMaxElems)
     return fail(BH_EINVAL, "bad image size");
   if (!(v->disc_r_in >= 3.0 * v->r_s * (1.0 - 1e-12)))
     return fail(BH_EINVAL, "disc_r_in must be >= 3 r_s (innermost stable circular orbit)");
@@ -1068,7 +1075,9 @@ extern "C" bh_status bh_render_batch(bh_ctx* c, const bh_tables* t, const bh_vie
     int tx = (views[i].width + tw - 1) / tw, ty = (views[i].height + th - 1) / th;
     runs.push_back(TileRun{i, 0, (int)ntiles, tx});
     ntiles += (int64_t)tx * ty;
-    if (ntiles >= (int64_t)1 << 31) return fail(BH_EINVAL, "too many tiles");
+    // the one-workgroup-per-tile launch runs ntiles x (tile pixels / ppt) work-items
+    if (ntiles * tw * th > kMaxElems * 2 - 1)
+      return fail(BH_EINVAL, "batch too large: more than 2^32 - 1 pixels in its tiles");
   }
   bh_status st = ensure_batch_buffers(c, n);
   if (st) return st;
@@ -1139,7 +1148,8 @@ extern "C" bh_status bh_autotune(bh_ctx* c, const bh_tables* t, const bh_view* v
 
 extern "C" bh_status bh_trace_rays(bh_ctx* c, const bh_tables* t, const float* rays, int64_t n,
                                    float* out, void* stream) {
-  if (!c || !t || (n > 0 && (!rays || !out)) || n < 0) return fail(BH_EINVAL, "bad arguments");
+  if (!c || !t || (n > 0 && (!rays || !out)) || n < 0 || n > kMaxElems)
+    return fail(BH_EINVAL, "bad arguments");
   HIPCHK(hipSetDevice(c->device));
   HIPCHK(launch_trace_rays(tables_dev(t), rays, n, (float4*)out, nullptr, (hipStream_t)stream));
   return BH_OK;
@@ -1147,7 +1157,8 @@ extern "C" bh_status bh_trace_rays(bh_ctx* c, const bh_tables* t, const float* r
 
 extern "C" bh_status bh_march_rays(bh_ctx* c, const float* rays, int64_t n, int32_t max_steps,
                                    float* out, void* stream) {
-  if (!c || (n > 0 && (!rays || !out)) || n < 0) return fail(BH_EINVAL, "bad arguments");
+  if (!c || (n > 0 && (!rays || !out)) || n < 0 || n > kMaxElems)
+    return fail(BH_EINVAL, "bad arguments");
   bh_status st = check_march_steps(max_steps);
   if (st) return st;
   HIPCHK(hipSetDevice(c->device));
@@ -1158,7 +1169,7 @@ extern "C" bh_status bh_march_rays(bh_ctx* c, const float* rays, int64_t n, int3
 
 extern "C" bh_status bh_trace_rays_timed(bh_ctx* c, const bh_tables* t, const float* rays,
                                          int64_t n, float* out, float* out_time, void* stream) {
-  if (!c || !t || (n > 0 && (!rays || !out || !out_time)) || n < 0)
+  if (!c || !t || (n > 0 && (!rays || !out || !out_time)) || n < 0 || n > kMaxElems)
     return fail(BH_EINVAL, "bad arguments");
   HIPCHK(hipSetDevice(c->device));
   HIPCHK(launch_trace_rays(tables_dev(t), rays, n, (float4*)out, (float4*)out_time,
@@ -1211,7 +1222,8 @@ extern "C" bh_status bh_band_table_download(const bh_ctx* c, float* host) {
 
 extern "C" bh_status bh_band_eval(bh_ctx* c, const float* temps, int64_t n, float* out,
                                   void* stream) {
-  if (!c || n < 0 || (n > 0 && (!temps || !out))) return fail(BH_EINVAL, "bad arguments");
+  if (!c || n < 0 || n > kMaxElems || (n > 0 && (!temps || !out)))
+    return fail(BH_EINVAL, "bad arguments");
   HIPCHK(hipSetDevice(c->device));
   HIPCHK(launch_band_eval(lut_dev(c), temps, n, out, (hipStream_t)stream));
   return BH_OK;

@@ -1,6 +1,7 @@
 """The largest frames: 7680x4320 (the biggest frame of the serving mix) and the 65536-pixel
 limit on a side, against the oracle on seeded samples of quads (same tolerances and mask as
-the 1080p parity test)."""
+the 1080p parity test); sizes past the limits (65536 a side, 2^31 pixels or elements, batches
+whose tiles hold 2^32 pixels) are refused."""
 import json
 
 import numpy as np
@@ -70,3 +71,36 @@ def test_views_beyond_the_size_limit_are_rejected(gpu_ctx, gpu_tables):
         with pytest.raises(bh.BhError) as ei:
             bh.bh_render(gpu_ctx, gpu_tables, bh.make_view(v), out.data_ptr())
         assert ei.value.status == bh.BH_EINVAL
+
+
+def test_sizes_beyond_one_launch_are_rejected(gpu_ctx, gpu_tables):
+    """One launch covers fewer than 2^32 work-items: images above 2^31 pixels, arrays above
+    2^31 rays or temperatures and batches whose tiles hold 2^32 pixels are refused before any
+    device work (the buffers passed are small and never touched)."""
+    import torch
+    out = torch.zeros((8, 8, 4), dtype=torch.float32, device="cuda")
+    base = scenes.small_static_view()
+    for w, h in ((65536, 65536), (65536, 32769), (32769, 65536)):
+        v = scenes.View(**{**base.__dict__, "width": w, "height": h})
+        with pytest.raises(bh.BhError) as ei:
+            bh.bh_render(gpu_ctx, gpu_tables, bh.make_view(v), out.data_ptr())
+        assert ei.value.status == bh.BH_EINVAL
+        with pytest.raises(bh.BhError) as ei:
+            bh.bh_tonemap(gpu_ctx, out.data_ptr(), out.data_ptr() + 1024, w, h, 1.0)
+        assert ei.value.status == bh.BH_EINVAL
+    half = scenes.View(**{**base.__dict__, "width": 65536, "height": 32768})
+    with pytest.raises(bh.BhError) as ei:
+        bh.bh_render_batch(gpu_ctx, gpu_tables, [bh.make_view(half)] * 2,
+                           [out.data_ptr()] * 2)
+    assert ei.value.status == bh.BH_EINVAL
+    n = (1 << 31) + 1
+    p = out.data_ptr()
+    for call in (lambda: bh.bh_trace_rays(gpu_ctx, gpu_tables, p, n, p),
+                 lambda: bh.bh_trace_rays_timed(gpu_ctx, gpu_tables, p, n, p, p),
+                 lambda: bh.bh_march_rays(gpu_ctx, p, n, 64, p),
+                 lambda: bh.bh_band_eval(gpu_ctx, p, n, p)):
+        with pytest.raises(bh.BhError) as ei:
+            call()
+        assert ei.value.status == bh.BH_EINVAL
+    torch.cuda.synchronize()
+    assert not out.any()
