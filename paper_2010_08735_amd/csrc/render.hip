@@ -68,15 +68,23 @@ __device__ __forceinline__ void gather(const void* tex, const Footprint& F, uint
     }
   }
   uint64_t lo = (uint64_t)w0 | ((uint64_t)w1 << 32);
+  // texels from the footprint's corner: row r, column c lies r nL + c = idx + r (nL - 9)
+  // texels on (nL - 9 >= -8: a signed 24-bit product)
+  const Half4r* tex16 = (const Half4r*)tex + F.texel0;
+  const float4* tex32 = (const float4*)tex + F.texel0;
+  const int nLm9 = F.nL - 9;
   auto tap = [&](int idx) {
     int r = (idx * 57) >> 9;  // idx / 9 for idx < 81
     int c = idx - 9 * r;
-    uint32_t t = F.texel0 + __umul24((unsigned)r, (unsigned)F.nL) + (uint32_t)c;  // nL < 2^24
-    if (COUNT) atomicOr(&touched[t >> 5], 1u << (t & 31));
+    uint32_t t = (uint32_t)(__mul24(r, nLm9) + idx);  // r nL + c, nL < 2^23
+    if (COUNT) {
+      uint32_t ta = F.texel0 + t;
+      atomicOr(&touched[ta >> 5], 1u << (ta & 31));
+    }
     const float fc = (float)c, fr = (float)r;
     if (FP16) {
       // half operands go straight into mixed-precision multiply-adds
-      Half4r hx = ((const Half4r*)tex)[t];
+      Half4r hx = tex16[t];
       float a = fmaf((float)hx.z, F.one, fc), b = fmaf((float)hx.w, F.one, fr);
       float w = fmaf(F.Wc, a, fmaf(F.Wr, b, F.W0));
       float h = fmaf(F.Hc, a, fmaf(F.Hr, b, F.H0));
@@ -86,7 +94,7 @@ __device__ __forceinline__ void gather(const void* tex, const Footprint& F, uint
       A += wi;
       B = fmaf(wi, (float)hx.y, B);
     } else {
-      float4 x = ((const float4*)tex)[t];
+      float4 x = tex32[t];
       float a = fc + x.z, b = fr + x.w;
       float w = fmaf(F.Wc, a, fmaf(F.Wr, b, F.W0));
       float h = fmaf(F.Hc, a, fmaf(F.Hr, b, F.H0));
