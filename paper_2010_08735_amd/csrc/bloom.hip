@@ -83,8 +83,14 @@ __device__ __forceinline__ uint32_t display_pixel(float4 c, float exposure) {
 __global__ void __launch_bounds__(256)
     k_tonemap(const float4* __restrict__ in, uint32_t* __restrict__ out, int64_t n,
               float exposure) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < n) out[i] = display_pixel(in[i], exposure);
+  // two pixels per thread, one grid apart (both loads in flight before either encoding);
+  // the launch has ceil(n / 512) workgroups, so i0 + step covers the rest of the image
+  const int64_t step = (int64_t)gridDim.x * 256;
+  const int64_t i0 = (int64_t)blockIdx.x * 256 + threadIdx.x, i1 = i0 + step;
+  const float4 a = i0 < n ? in[i0] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  const float4 b = i1 < n ? in[i1] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  if (i0 < n) out[i0] = display_pixel(a, exposure);
+  if (i1 < n) out[i1] = display_pixel(b, exposure);
 }
 
 // ---- level building inside one 64 x 64 tile --------------------------------------------------
@@ -431,7 +437,7 @@ __global__ void __launch_bounds__(256)
 
 hipError_t launch_tonemap(const float4* in, uint32_t* out, int64_t n, float exposure,
                           hipStream_t s) {
-  hipLaunchKernelGGL(k_tonemap, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, out, n,
+  hipLaunchKernelGGL(k_tonemap, dim3((unsigned)((n + 511) / 512)), dim3(256), 0, s, in, out, n,
                      exposure);
   return hipGetLastError();
 }
