@@ -38,9 +38,10 @@
  *   every texel of level L whose cell meets [U-hu, U+hu] x [V-hv, V+hv] on the centre face
  *   is visited rows then columns; a star at face position s gets (w, h) = J^-1 (s - c) and
  *   weight f(w) f(h), f(x) = max(1 - |x|, 0); A = sum w I, B = sum w I T.
- *   Omega/Omega' = |d_w q x d_h q| / |d_w d' x d_h d'|, where q = normalize(q^w, q^h, -f) is
- *   known in closed form, so its partial derivatives are exact: |d_w q x d_h q| =
- *   f / |(q^w, q^h, -f)|^3 at the pixel centre (reading: only d' needs differences);
+ *   Omega/Omega' = |d_w q x d_h q| / |d_w d' x d_h d'| (Section 3.4.1), q = normalize(q^w,
+ *   q^h, -f) the camera-frame direction; both partial derivatives are the same fine 2x2-quad
+ *   differences (the pipeline's screen-space derivatives, Section 3.3.2), so the ratio is
+ *   exactly 1 wherever d' is a rotation of q (flat space, static camera);
  *   star colour_b = k_star (Omega/Omega') A L_b(D_cam T_pix) / sum_b L_b(T_pix), T_pix = B/A
  *   (static stars: k' = [1, 0, 0, 0]).  If any member of the quad is captured the star
  *   term is zero for the whole quad.
@@ -91,7 +92,7 @@ static void setup(const orc_view* v, vsetup* s) {
 typedef struct {
   int captured, degenerate;
   double dprime[3];
-  double omega_cam; /* |d_w q x d_h q| = f / |(q^w, q^h, -f)|^3, exact */
+  double q[3];      /* camera-frame direction normalize(q^w, q^h, -f) */
   double ey[3];
   double e2, zeta, d_cam, delta, alpha;
   orc_ray ray;
@@ -113,7 +114,9 @@ static void trace_pixel(const ctx_t* c, int32_t x, int32_t y, ray_out* o) {
   memset(o, 0, sizeof(*o));
   double qw = x + 0.5 - 0.5 * v->width, qh = 0.5 * v->height - y - 0.5;
   double nq = sqrt(qw * qw + qh * qh + s->f * s->f);
-  o->omega_cam = s->f / (nq * nq * nq);
+  o->q[0] = qw / nq;
+  o->q[1] = qh / nq;
+  o->q[2] = -s->f / nq;
   double nc[3];
   for (int i = 0; i < 3; ++i) nc[i] = (qw * s->ew[i] + qh * s->eh[i] - s->f * s->ed[i]) / nq;
   /* aberration into the static observer's frame */
@@ -307,14 +310,17 @@ static void shade_quad(const ctx_t* c, int32_t x0, int32_t y0, orc_pixel* out) {
     if (c->cube && !any_captured) {
       int mw0 = (m & 2), mw1 = (m & 2) | 1; /* same row */
       int mh0 = (m & 1), mh1 = (m & 1) | 2; /* same column */
-      double dw[3], dh[3];
+      double dw[3], dh[3], qw[3], qh[3];
       for (int i = 0; i < 3; ++i) {
         dw[i] = r[mw1].dprime[i] - r[mw0].dprime[i];
         dh[i] = r[mh1].dprime[i] - r[mh0].dprime[i];
+        qw[i] = r[mw1].q[i] - r[mw0].q[i];
+        qh[i] = r[mh1].q[i] - r[mh0].q[i];
       }
-      double cd[3];
+      double cd[3], cq[3];
       cross3(dw, dh, cd);
-      double om = o->omega_cam, omp = norm3(cd);
+      cross3(qw, qh, cq);
+      double om = norm3(cq), omp = norm3(cd);
       p->omega_ratio = omp > 0.0 ? om / omp : 0.0;
       double A, B;
       p->mip_level = gather(c, o->dprime, dw, dh, &A, &B);
