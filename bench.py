@@ -62,13 +62,13 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def star_map(bh, ctx, field, n0, key):
+def star_map(bh, ctx, field, n0):
     import torch
     d = torch.from_numpy(field.dirs).cuda()
     i = torch.from_numpy(field.intensity).cuda()
     t = torch.from_numpy(field.temperature).cuda()
     h = bh.bh_build_stars(ctx, d.data_ptr(), i.data_ptr(), t.data_ptr(), len(field), n0,
-                          bh.BH_TEXEL_FP16, key, bh.current_stream())
+                          bh.BH_TEXEL_FP16, bh.current_stream())
     torch.cuda.synchronize()
     return h
 
@@ -157,7 +157,7 @@ def serve_leg(bh, scenes, tables_of, fields, duration, rate, seed, budget, max_t
     ctx = bh.bh_create(0, budget)
     try:
         tables = tables_of(ctx)
-        smaps = [star_map(bh, ctx, f, 2048, 40 + k) for k, f in enumerate(fields)]
+        smaps = [star_map(bh, ctx, f, 2048) for f in fields]
         bh.bh_set_tile_config(ctx, tile_config)
         bh.bh_serve_start(ctx, 0, inflight, max_tiles)
         for mode in ("poisson", "saturated_first_pass", "saturated"):
@@ -198,7 +198,7 @@ def serve_leg(bh, scenes, tables_of, fields, duration, rate, seed, budget, max_t
     ctx = bh.bh_create(0, budget)
     try:
         tables = tables_of(ctx)
-        smaps = [star_map(bh, ctx, f, 2048, 40 + k) for k, f in enumerate(fields)]
+        smaps = [star_map(bh, ctx, f, 2048) for f in fields]
         imgs = {}
         for r in reqs:
             key = (r.view.width, r.view.height)
@@ -377,7 +377,7 @@ def main():
     t_tab = time.perf_counter() - t0
     field = scenes.star_field(1_000_000, 1)
     t0 = time.perf_counter()
-    stars = star_map(bh, ctx, field, 2048, 1)
+    stars = star_map(bh, ctx, field, 2048)
     t_star = time.perf_counter() - t0
     sv = scenes.boosted_orbit_view()
     view = bh.make_view(sv, stars)

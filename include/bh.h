@@ -18,6 +18,8 @@
  *   - Handles (bh_ctx, bh_tables, bh_stars) are owned by the library.  Tables and star
  *     maps are reference counted and shared by key: a second request with the same key
  *     returns the resident handle with its count incremented; bh_release_* drops it.
+ *     Tables are keyed by their parameters, star maps by their content (a hash of the
+ *     three star arrays, the star count, the face size and the texel format).
  *   - Thread safety: every call is safe to make concurrently on one context.
  */
 #ifndef BH_H
@@ -165,13 +167,13 @@ typedef struct {
   int64_t n;
   int32_t face_size;            /* level-0 texels per cube face edge, power of two         */
   int32_t texel_format;         /* BH_TEXEL_*                                              */
-  uint64_t key;                 /* non-zero: share the resident map built with this key,
-                                   face size and format                                    */
 } bh_star_field;
 
 /* Splat the stars into a cube map (one texel holds the intensity sum, the
  * intensity-weighted mean temperature and the intensity-weighted mean position of the
  * stars inside it) and build every mip level with the same rule.  Deterministic.
+ * A field whose arrays hash to a resident map of the same star count, face size and
+ * format returns that map (its count incremented) without building anything.
  * Synchronises hip_stream before returning. */
 bh_status bh_build_stars(bh_ctx* ctx, const bh_star_field* f, void* hip_stream, bh_stars** out);
 /* Copy mip level `level` as float (face, y, x, [I, T, p_u, p_v]) to host_texels
@@ -267,6 +269,9 @@ int32_t bh_tile_config_count(void);
 bh_status bh_tile_config_get(int32_t index, bh_tile_config* out);
 /* Select the tile configuration used by bh_render / bh_render_batch (-1: built-in default) */
 bh_status bh_set_tile_config(bh_ctx* ctx, int32_t index);
+/* Select the launch form of the batched calls: 1 = persistent workgroups claiming tiles
+ * from an atomic counter, 0 = one workgroup per tile (the default). */
+bh_status bh_set_batch_form(bh_ctx* ctx, int32_t persistent);
 /* Time every tile configuration with both batched launch forms (persistent workgroups
  * pulling tiles from an atomic counter, or one workgroup per tile) on the given views and
  * keep the fastest.  best_index = 2 * config + persistent; ms_per_config receives
@@ -280,7 +285,9 @@ bh_status bh_autotune(bh_ctx* ctx, const bh_tables* t, const bh_view* views, int
 typedef struct {
   int32_t max_queue;          /* submissions beyond this return BH_EAGAIN                */
   int32_t max_inflight_launches; /* launches kept in flight on the serving stream (6)    */
-  int64_t max_tiles_per_launch;  /* tiles per launch; bigger requests are split (262144) */
+  int64_t max_tiles_per_launch;  /* tiles per launch; bigger requests are split (262144);
+                                    at most 4194303 (BH_EINVAL above: a launch covers fewer
+                                    than 2^32 work-items)                                  */
 } bh_serve_params;
 
 /* Start the serving scheduler thread on its own stream (call once per context). */

@@ -28,8 +28,9 @@ EXPORTS = [
     "bh_bloom_create", "bh_bloom_apply", "bh_bloom_release", "bh_bloom_apply_display",
     "bh_tonemap",
     "bh_build_stars", "bh_stars_download", "bh_release_stars",
-    "bh_render", "bh_render_march", "bh_render_batch", "bh_tile_config_count", "bh_tile_config_get",
-    "bh_set_tile_config", "bh_autotune",
+    "bh_render", "bh_render_march", "bh_render_batch",
+    "bh_tile_config_count", "bh_tile_config_get",
+    "bh_set_tile_config", "bh_set_batch_form", "bh_autotune",
     "bh_serve_start", "bh_submit", "bh_poll", "bh_ticket_image", "bh_ticket_free",
     "bh_serve_drain",
     "bh_trace_rays", "bh_trace_rays_timed", "bh_march_rays", "bh_footprint_texels", "bh_band_table_info", "bh_band_table_download", "bh_band_eval",
@@ -50,7 +51,7 @@ class TableParams(C.Structure):
 class StarField(C.Structure):
     _fields_ = [("dir_xyz_dev", C.c_void_p), ("intensity_dev", C.c_void_p),
                 ("temperature_dev", C.c_void_p), ("n", C.c_int64), ("face_size", C.c_int32),
-                ("texel_format", C.c_int32), ("key", C.c_uint64)]
+                ("texel_format", C.c_int32)]
 
 
 class View(C.Structure):
@@ -103,6 +104,7 @@ def lib():
             "bh_release_stars": ([vp], i32),
             "bh_render": ([vp, vp, C.POINTER(View), vp, vp, vp], i32),
             "bh_render_batch": ([vp, vp, C.POINTER(View), i32, C.POINTER(vp), vp], i32),
+            "bh_set_batch_form": ([vp, i32], i32),
             "bh_tile_config_count": ([], i32),
             "bh_tile_config_get": ([i32, C.POINTER(TileConfig)], i32),
             "bh_set_tile_config": ([vp, i32], i32),
@@ -194,8 +196,8 @@ def bh_release_particles(particles) -> None:
 
 
 def bh_build_stars(ctx, dir_ptr, inten_ptr, temp_ptr, n, face_size, texel_format=BH_TEXEL_FP16,
-                   key=0, stream=None) -> int:
-    f = StarField(dir_ptr, inten_ptr, temp_ptr, n, face_size, texel_format, key)
+                   stream=None) -> int:
+    f = StarField(dir_ptr, inten_ptr, temp_ptr, n, face_size, texel_format)
     out = C.c_void_p()
     _check(lib().bh_build_stars(ctx, C.byref(f), stream, C.byref(out)))
     return out.value
@@ -222,6 +224,10 @@ def bh_render_batch(ctx, tables, views, out_ptrs, stream=None) -> None:
     arr = (View * n)(*views)
     outs = (C.c_void_p * n)(*out_ptrs)
     _check(lib().bh_render_batch(ctx, tables, arr, n, outs, stream))
+
+
+def bh_set_batch_form(ctx, persistent: int) -> None:
+    _check(lib().bh_set_batch_form(ctx, persistent))
 
 
 def bh_tile_config_count() -> int:

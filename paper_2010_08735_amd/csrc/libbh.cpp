@@ -34,6 +34,8 @@ hipError_t launch_star_build(const float* dirs, const float* inten, const float*
                              int* next, float2* pos, float4* master, unsigned* maxbits,
                              float* scale, int fp16, void* out, hipStream_t s);
 hipError_t launch_fill_int(int* p, int64_t n, int v, hipStream_t s);
+hipError_t launch_star_hash(const float* dirs, const float* inten, const float* temp, int64_t n,
+                            unsigned long long* acc, hipStream_t s);
 hipError_t launch_star_occupancy(const void* tex, int n0, int levels, const uint32_t* level_off,
                                  const uint32_t* occ_off, int fp16, uint32_t* occ,
                                  hipStream_t s);
@@ -121,9 +123,13 @@ struct bh_bloom {
   BloomDev B{};          // launch record (sizes, offsets; weights filled per call)
 };
 
+// Star maps are shared by content: (hash of the star arrays, star count, face size,
+// texel format).
+using StarKey = std::tuple<uint64_t, int64_t, int, int>;
+
 struct bh_stars {
   bh_ctx* ctx;
-  uint64_t key;
+  StarKey key;
   int n0, levels, fp16;
   void* tex = nullptr;
   float* scale = nullptr;
@@ -170,7 +176,7 @@ struct bh_ctx {
   int cus = 256;
   std::mutex mu;  // resources, tile config, batch staging
   std::map<std::string, bh_tables*> tables;
-  std::map<std::tuple<uint64_t, int, int>, bh_stars*> stars;
+  std::map<StarKey, bh_stars*> stars;
   std::set<bh_particles*> particles;
   std::set<bh_bloom*> blooms;
   float4* lut = nullptr;
@@ -196,7 +202,11 @@ struct bh_ctx {
     hipGraphExec_t exec;
     hipStream_t stream;
   };
-  std::map<std::tuple<int, int, int, int, const void*, uintptr_t>, GraphEntry> graphs;
+  // a captured batch launch holds its kernel arguments by value: the key is every one of
+  // them that can change between calls (tables by all their pointers and sizes)
+  using GraphKey = std::tuple<int, int, int, int, uintptr_t, const void*, const void*, const void*,
+                              const void*, int, int, int>;
+  std::map<GraphKey, GraphEntry> graphs;
   // serving
   std::thread serve_thread;
   bool serving = false, stop = false;
@@ -418,6 +428,16 @@ extern "C" bh_status bh_release_tables(bh_tables* t) {
   if (--t->refs > 0) return BH_OK;
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
+  // captured batch launches that read these tables must not be replayed on a later table
+  // set that happens to reuse the freed addresses
+  for (auto it = c->graphs.begin(); it != c->graphs.end();) {
+    if (std::get<5>(it->first) == t->D) {
+      (void)hipGraphExecDestroy(it->second.exec);
+      it = c->graphs.erase(it);
+    } else {
+      ++it;
+    }
+  }
   c->tables.erase(t->key);
   dev_free(c, t->D, sizeof(float) * (size_t)t->p.d_n * t->p.d_n);
   dev_free(c, t->U, sizeof(float) * (size_t)t->p.u_ne * t->p.u_nphi);
@@ -643,15 +663,30 @@ extern "C" bh_status bh_build_stars(bh_ctx* c, const bh_star_field* f, void* str
   if (f->texel_format != BH_TEXEL_FP16 && f->texel_format != BH_TEXEL_FP32)
     return fail(BH_EINVAL, "bad texel_format");
   HIPCHK(hipSetDevice(c->device));
+  hipStream_t hs = (hipStream_t)stream;
+  // content hash of the three arrays (ordered after the caller's work on the stream)
+  uint64_t hash = 0;
+  {
+    unsigned long long* acc = nullptr;
+    bh_status hst = dev_alloc(c, sizeof(unsigned long long), (void**)&acc);
+    if (hst) return hst;
+    hipError_t e = hipMemsetAsync(acc, 0, sizeof(unsigned long long), hs);
+    if (e == hipSuccess)
+      e = launch_star_hash(f->dir_xyz_dev, f->intensity_dev, f->temperature_dev, f->n, acc, hs);
+    unsigned long long h = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, acc, sizeof(h), hipMemcpyDeviceToHost, hs);
+    if (e == hipSuccess) e = hipStreamSynchronize(hs);
+    dev_free(c, acc, sizeof(unsigned long long));
+    if (e != hipSuccess) return fail(BH_EDEVICE, std::string("star hash: ") + hipGetErrorString(e));
+    hash = h;
+  }
   std::lock_guard<std::mutex> g(c->mu);
-  auto key = std::make_tuple(f->key, n0, f->texel_format);
-  if (f->key) {
-    auto it = c->stars.find(key);
-    if (it != c->stars.end()) {
-      it->second->refs++;
-      *out = it->second;
-      return BH_OK;
-    }
+  StarKey key{hash, f->n, n0, f->texel_format};
+  auto found = c->stars.find(key);
+  if (found != c->stars.end()) {
+    found->second->refs++;
+    *out = found->second;
+    return BH_OK;
   }
   int levels = 0;
   while ((n0 >> levels) >= 1) ++levels;
@@ -667,7 +702,7 @@ extern "C" bh_status bh_build_stars(bh_ctx* c, const bh_star_field* f, void* str
   size_t tsz = fp16 ? 8 : 16;
   auto* s = new bh_stars;
   s->ctx = c;
-  s->key = f->key;
+  s->key = key;
   s->n0 = n0;
   s->levels = levels;
   s->fp16 = fp16;
@@ -697,7 +732,6 @@ extern "C" bh_status bh_build_stars(bh_ctx* c, const bh_star_field* f, void* str
   if (!st) st = dev_alloc(c, bmaster, (void**)&master);
   if (!st) st = dev_alloc(c, bmax, (void**)&maxbits);
   hipError_t e = hipSuccess;
-  hipStream_t hs = (hipStream_t)stream;
   if (!st) {
     e = hipMemcpyAsync(s->level_off_dev, off.data(), boff, hipMemcpyHostToDevice, hs);
     if (e == hipSuccess)
@@ -728,7 +762,7 @@ extern "C" bh_status bh_build_stars(bh_ctx* c, const bh_star_field* f, void* str
     return fail(BH_EDEVICE, std::string("star build: ") + hipGetErrorString(e));
   }
   s->bytes = btex + bsc + 2 * boff + bocc;
-  if (f->key) c->stars[key] = s;
+  c->stars[key] = s;
   *out = s;
   return BH_OK;
 }
@@ -759,7 +793,7 @@ extern "C" bh_status bh_release_stars(bh_stars* s) {
   if (--s->refs > 0) return BH_OK;
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
-  if (s->key) c->stars.erase(std::make_tuple(s->key, s->n0, s->fp16 ? BH_TEXEL_FP16 : BH_TEXEL_FP32));
+  c->stars.erase(s->key);
   size_t tsz = s->fp16 ? 8 : 16;
   uint64_t total = 0;
   for (int l = 0; l < s->levels; ++l) total += 6ull * (s->n0 >> l) * (s->n0 >> l);
@@ -958,6 +992,21 @@ extern "C" bh_status bh_set_tile_config(bh_ctx* c, int32_t i) {
   return BH_OK;
 }
 
+extern "C" bh_status bh_set_batch_form(bh_ctx* c, int32_t persistent) {
+  if (!c || (persistent != 0 && persistent != 1)) return fail(BH_EINVAL, "persistent must be 0 or 1");
+  std::lock_guard<std::mutex> g(c->mu);
+  c->persistent = persistent;
+  return BH_OK;
+}
+
+// Workgroups (of 4 waves, each claiming tiles on its own) of a persistent batched launch:
+// as many as fit at the kernel's 7 resident waves per SIMD, 4 SIMDs per CU (k_render_batch);
+// fewer when the launch has fewer tiles than waves.
+static int batch_grid(const bh_ctx* c, int cfg, int64_t ntiles) {
+  (void)cfg;
+  return (int)std::max<int64_t>(1, std::min<int64_t>((ntiles + 3) / 4, (int64_t)c->cus * 7));
+}
+
 // Upload view blocks and tile runs through a pinned staging buffer and enqueue one batched
 // launch over `ntiles` tiles on stream s.  With a copy stream `cs`, the uploads run there
 // (after `slot_free`, the end of the last launch that read dviews/druns) and s waits for
@@ -986,10 +1035,7 @@ static bh_status enqueue_batch(bh_ctx* c, const TablesDev& T, const std::vector<
   }
   int cfg = c->tile_cfg;
   int pers = c->persistent;
-  int tw, th, waves, ppt;
-  tile_config(cfg, &tw, &th, &waves, &ppt);
-  int per_cu = std::max(1, 16 / waves);
-  int grid = std::max(1, std::min<int>(ntiles, c->cus * per_cu));
+  int grid = batch_grid(c, cfg, ntiles);
   int nruns = (int)runs.size();
   int anim = 0;
   for (const ViewDev& vd : vds) anim |= vd.density_mode != 0;
@@ -999,8 +1045,9 @@ static bh_status enqueue_batch(bh_ctx* c, const TablesDev& T, const std::vector<
                                grid, s));
     return BH_OK;
   }
-  auto key = std::make_tuple(cfg * 4 + pers * 2 + anim, ntiles, nruns, grid, (const void*)T.D,
-                             (uintptr_t)counter);
+  bh_ctx::GraphKey key{cfg * 4 + pers * 2 + anim, ntiles, nruns, grid, (uintptr_t)counter,
+                       (const void*)T.D, (const void*)T.U, (const void*)T.Dt, (const void*)T.Ut,
+                       T.d_n, T.u_ne, T.u_nphi};
   auto it = c->graphs.find(key);
   if (it == c->graphs.end()) {
     hipStream_t cap;
@@ -1464,7 +1511,15 @@ static void serve_loop(bh_ctx* c) {
   for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
 }
 
+// Most tiles one serving launch may hold: the one-workgroup-per-tile launch runs
+// tiles x (tile pixels / pixels per thread) work-items, at most 1024 per tile (every tile
+// configuration), which must stay below 2^32; tile indices are ints.
+constexpr int64_t kMaxServeTiles = ((int64_t)1 << 32) / 1024 - 1;
+
 extern "C" bh_status bh_serve_start(bh_ctx* c, const bh_serve_params* p) {
+  if (p && p->max_tiles_per_launch > kMaxServeTiles)
+    return fail(BH_EINVAL, "max_tiles_per_launch above " + std::to_string(kMaxServeTiles) +
+                               " (one launch covers fewer than 2^32 work-items)");
   if (!c) return fail(BH_EINVAL, "NULL context");
   std::lock_guard<std::mutex> lk(c->smu);
   if (c->serving) return fail(BH_EINVAL, "serving already started");

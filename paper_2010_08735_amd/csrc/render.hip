@@ -16,7 +16,7 @@
 //   disc        T' from the temperature law, Doppler factor g(k,l)/g(k',l') with the
 //               Keplerian k' (eq. k_prime), band radiances of a blackbody at D T'
 //               (Section 3.4.2), front-to-back composite
-//   stars       fine quad differences of d' (q's derivatives are exact), face Jacobian, mip
+//   stars       fine quad differences of d' and of q, face Jacobian, mip
 //               level such that the extended footprint spans at most 9x9 texels,
 //               tent-weighted gather f(w) f(h), lensing factor Omega/Omega', one Doppler
 //               shift per pixel.
@@ -603,15 +603,22 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
       B *= S.fp16 ? iscale * 1024.0f : iscale;
     }
     float cdx = dw1 * dh2 - dw2 * dh1, cdy = dw2 * dh0 - dw0 * dh2, cdz = dw0 * dh1 - dw1 * dh0;
-    // Omega / Omega' = |q_w x q_h| / |d'_w x d'_h|; q = (q^w, q^h, -f) / |.| has exact
-    // partial derivatives, |q_w x q_h| = f / |(q^w, q^h, -f)|^3 = f inq^3
-    const float om = v.f * (inq * inq) * inq;
+    // Omega / Omega' = |q_w x q_h| / |d'_w x d'_h| with the same quad differences of the
+    // camera-frame direction q = (q^w, q^h, -f) inq.  The row partner shares q^h and the
+    // column partner q^w, so with a = quad difference of inq along the row and b along the
+    // column, q_w = (dq0, q^h a, -f a) and q_h = (q^w b, dq1, -f b), whose cross product is
+    // (f a (dq1 - q^h b), f b (dq0 - q^w a), dq0 dq1 - q^w q^h a b).
+    const float qa = quad_diff<1>(inq), qb = quad_diff<2>(inq);
+    const float dq0 = quad_diff<1>(q0), dq1 = quad_diff<2>(q1);
+    const float cq0 = v.f * qa * (dq1 - qh * qb), cq1 = v.f * qb * (dq0 - qw * qa);
+    const float cq2 = dq0 * dq1 - (qw * qh) * (qa * qb);
+    const float om2 = cq0 * cq0 + cq1 * cq1 + cq2 * cq2;
     const float omp2 = cdx * cdx + cdy * cdy + cdz * cdz;
     if (A > 0.0f && omp2 > 0.0f) {
       float Tpix = fdiv(B, A);
       float4 Lr = band_lookup(L, dcam * Tpix);
       float4 Ln = band_lookup(L, Tpix);
-      float sc = trans * v.k_star * om * __builtin_amdgcn_rsqf(omp2) * fdiv(A, Ln.w);
+      float sc = trans * v.k_star * fsqrt(om2) * __builtin_amdgcn_rsqf(omp2) * fdiv(A, Ln.w);
       cr += sc * Lr.x;
       cg += sc * Lr.y;
       cb += sc * Lr.z;
@@ -725,25 +732,63 @@ __device__ __forceinline__ void render_flat_tile(const ViewDev* __restrict__ vie
                                                  int it, const TablesDev& T, const LutDev& L) {
   TileRun r = find_run(runs, nruns, it);
   int tile = r.tile0 + (it - r.start);
-  ViewDev v = views[r.view];
+  // fields are read through the reference as they are needed (wave-uniform scalar loads):
+  // a copy of the whole record would hold ~65 scalar registers across the tile
+  const ViewDev& v = views[r.view];
   render_tile<TW, TH, PPT, false, ANIM>(v, T, L, (tile % r.tiles_x) * TW,
                                         (tile / r.tiles_x) * TH);
 }
 
-// Persistent launch over the tiles of many views: workgroups take flat tile indices from
-// an atomic counter until all ntiles are done.
+// Persistent launch over the tiles of many views.  Every wave works on its own: it claims
+// indices from an atomic counter and renders every 8x8 block of the tiles a claim covers,
+// so no claim waits on a barrier and the workgroup shape (4 waves) is the same for every
+// tile configuration.  Claim j < nbig covers claim_tiles consecutive flat tiles (about 16
+// blocks); the last `tail` tiles (4 per wave) go one per claim, so the launch does not end
+// waiting on a few long claims.  A wave leaves at its first claim past the last tile; the
+// counter only grows, so every wave reaches that exit.  Held to 7 resident waves per SIMD:
+// the loop over tiles keeps ~14 more vector registers live than one tile does, so at 8
+// waves it would spill; the host sizes the grid to 7 waves per SIMD.
+constexpr int kBatchThreads = 256;
+
 template <int TW, int TH, int PPT, bool ANIM>
-__global__ void __launch_bounds__((TW / 8) * (TH / 8) * 64 / PPT)
+__global__ void __launch_bounds__(kBatchThreads, 7)
     k_render_batch(const ViewDev* __restrict__ views, const TileRun* __restrict__ runs,
                    int nruns, int ntiles, int* __restrict__ counter, TablesDev T, LutDev L) {
-  __shared__ int s_item;
+  using C = TileCfg<TW, TH, 1>;
+  constexpr int kBlocks = C::kBX * C::kBY;                // 8x8 blocks per tile
+  constexpr int claim_tiles = kBlocks >= 16 ? 1 : 16 / kBlocks;
+  const int lane = threadIdx.x & 63;
+  const int q = lane >> 2;
+  const int ox = 2 * (q & 3) + (lane & 1), oy = 2 * (q >> 2) + ((lane >> 1) & 1);
+  const int tail = min(ntiles, 4 * (int)(gridDim.x * (kBatchThreads / 64)));
+  const int nbig = (ntiles - tail) / claim_tiles;          // tiles [0, claim_tiles nbig)
+  const int first_single = claim_tiles * nbig;
   for (;;) {
-    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
-    __syncthreads();
-    int it = __builtin_amdgcn_readfirstlane(s_item);
-    __syncthreads();
-    if (it >= ntiles) break;
-    render_flat_tile<TW, TH, PPT, ANIM>(views, runs, nruns, it, T, L);
+    int j = 0;
+    if (lane == 0) j = atomicAdd(counter, 1);
+    j = __builtin_amdgcn_readfirstlane(j);                 // lane 0's claim, the wave's
+    int it0, it1;
+    if (j < nbig) {
+      it0 = claim_tiles * j;
+      it1 = it0 + claim_tiles;
+    } else {
+      it0 = first_single + (j - nbig);
+      it1 = it0 + 1;
+    }
+    if (it0 >= ntiles) break;
+#pragma unroll 1
+    for (int it = it0; it < it1; ++it) {
+      const TileRun r = find_run(runs, nruns, it);
+      const int tile = r.tile0 + (it - r.start);
+      const ViewDev& v = views[r.view];
+      const int tx0 = (tile % r.tiles_x) * TW, ty0 = (tile / r.tiles_x) * TH;
+#pragma unroll 1
+      for (int blk = 0; blk < kBlocks; ++blk) {
+        const int bx = tx0 + 8 * (blk % C::kBX), by = ty0 + 8 * (blk / C::kBX);
+        if (bx >= v.width || by >= v.height) continue;    // block outside the image
+        render_pixel<false, ANIM>(v, T, L, bx + ox, by + oy, nullptr);
+      }
+    }
   }
 }
 
@@ -841,9 +886,8 @@ template <int TW, int TH, int PPT, bool ANIM>
 static void launch_batch(const ViewDev* views, const TileRun* runs, int nruns, int ntiles,
                          int* counter, const TablesDev& T, const LutDev& L, int grid,
                          hipStream_t s) {
-  using C = TileCfg<TW, TH, PPT>;
   hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, counter);
-  hipLaunchKernelGGL((k_render_batch<TW, TH, PPT, ANIM>), dim3(grid), dim3(C::kThreads), 0, s,
+  hipLaunchKernelGGL((k_render_batch<TW, TH, PPT, ANIM>), dim3(grid), dim3(kBatchThreads), 0, s,
                      views, runs, nruns, ntiles, counter, T, L);
 }
 

@@ -234,6 +234,41 @@ hipError_t launch_star_build(const float* dirs, const float* inten, const float*
   return hipGetLastError();
 }
 
+// Content hash of a star field, the key under which its maps are shared: every star
+// contributes a 64-bit mix of its index and the bit patterns of its five floats, and the
+// contributions are summed with integer atomics (addition commutes, so the result does
+// not depend on the order the atomics run in).  The mix is the splitmix64 finaliser.
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+__global__ void __launch_bounds__(256)
+    k_star_hash(const float* __restrict__ dirs, const float* __restrict__ inten,
+                const float* __restrict__ temp, int64_t n, unsigned long long* __restrict__ acc) {
+  int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  uint64_t h = 0;
+  if (s < n) {
+    h = mix64((uint64_t)s + 0x9e3779b97f4a7c15ull);
+    h = mix64(h ^ __float_as_uint(dirs[3 * s]));
+    h = mix64(h ^ ((uint64_t)__float_as_uint(dirs[3 * s + 1]) << 32));
+    h = mix64(h ^ __float_as_uint(dirs[3 * s + 2]));
+    h = mix64(h ^ ((uint64_t)__float_as_uint(inten[s]) << 32));
+    h = mix64(h ^ __float_as_uint(temp[s]));
+  }
+  for (int o = 32; o > 0; o >>= 1) h += __shfl_xor(h, o);
+  if ((threadIdx.x & 63) == 0 && s - (threadIdx.x & 63) < n) atomicAdd(acc, (unsigned long long)h);
+}
+
+hipError_t launch_star_hash(const float* dirs, const float* inten, const float* temp, int64_t n,
+                            unsigned long long* acc, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_star_hash, dim3(blocks_for(n, 256)), dim3(256), 0, s, dirs, inten, temp,
+                     n, acc);
+  return hipGetLastError();
+}
+
 __global__ void k_fill_int(int* p, int64_t n, int v) {
   int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t < n) p[t] = v;

@@ -58,7 +58,7 @@ def small_scene(gpu_ctx, orc):
     from paper_2010_08735_amd import bh, scenes
     field = scenes.star_field(20000, 0)
     n0 = 256
-    h = gpu_star_map(gpu_ctx, field, n0, bh.BH_TEXEL_FP16, key=1000)
+    h = gpu_star_map(gpu_ctx, field, n0, bh.BH_TEXEL_FP16)
     return field, n0, h, orc.cubemap(field, n0)
 
 
@@ -68,17 +68,17 @@ def big_field_scene(gpu_ctx, orc):
     from paper_2010_08735_amd import bh, scenes
     field = scenes.star_field(1_000_000, 1)
     n0 = 2048
-    h = gpu_star_map(gpu_ctx, field, n0, bh.BH_TEXEL_FP16, key=1001)
+    h = gpu_star_map(gpu_ctx, field, n0, bh.BH_TEXEL_FP16)
     return field, n0, h, orc.cubemap(field, n0)
 
 
-def gpu_star_map(ctx, field, n0, fmt=0, key=0):
+def gpu_star_map(ctx, field, n0, fmt=0):
     import torch
     from paper_2010_08735_amd import bh
     d = torch.from_numpy(field.dirs).cuda()
     i = torch.from_numpy(field.intensity).cuda()
     t = torch.from_numpy(field.temperature).cuda()
     h = bh.bh_build_stars(ctx, d.data_ptr(), i.data_ptr(), t.data_ptr(), len(field), n0, fmt,
-                          key, bh.current_stream())
+                          bh.current_stream())
     torch.cuda.synchronize()
     return h

@@ -72,3 +72,16 @@ def test_structs_match_header_layout(tmp_path, name):
     assert C.sizeof(cls) == size
     for f in fields:
         assert getattr(cls, f).offset == offs[f], f
+
+
+def test_serve_start_rejects_launches_past_the_work_item_range(lib):
+    """A serving launch holds at most 4194303 tiles (1024 pixels each at most, fewer than
+    2^32 work-items); a larger max_tiles_per_launch is refused before any device work."""
+    import ctypes as C
+    p = bh.ServeParams(0, 0, 1 << 22)
+    rc = lib.bh_serve_start(None, C.byref(p))
+    assert rc == bh.BH_EINVAL
+    assert b"max_tiles_per_launch" in lib.bh_last_error()
+    p = bh.ServeParams(0, 0, (1 << 22) - 1)
+    assert lib.bh_serve_start(None, C.byref(p)) == bh.BH_EINVAL
+    assert b"NULL context" in lib.bh_last_error()

@@ -48,7 +48,7 @@ def test_empty_star_field_adds_nothing(gpu_ctx, gpu_tables):
     field = scenes.StarField(np.zeros((0, 3), np.float32), np.zeros(0, np.float32),
                              np.zeros(0, np.float32), 0)
     from conftest import gpu_star_map
-    h = gpu_star_map(gpu_ctx, field, 64, bh.BH_TEXEL_FP16, key=4242)
+    h = gpu_star_map(gpu_ctx, field, 64, bh.BH_TEXEL_FP16)
     v = scenes.small_static_view()
     with_map, _ = parity.render_gpu(gpu_ctx, gpu_tables, v, h)
     without, _ = parity.render_gpu(gpu_ctx, gpu_tables, v, None)

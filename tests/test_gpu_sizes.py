@@ -46,7 +46,7 @@ def test_frames_at_the_size_limit(gpu_ctx, gpu_tables, orc, orc_tables, W, H):
     written, and sampled quads agree with the oracle's table mode."""
     from conftest import gpu_star_map
     field = scenes.star_field(20000, 0)
-    hs = gpu_star_map(gpu_ctx, field, 256, bh.BH_TEXEL_FP16, key=1000)
+    hs = gpu_star_map(gpu_ctx, field, 256, bh.BH_TEXEL_FP16)
     v = scenes.small_static_view()
     v.width, v.height = W, H
     rgb, aov = parity.render_gpu(gpu_ctx, gpu_tables, v, hs)

@@ -56,7 +56,7 @@ def test_precision_study_4k_star_map_formats(gpu_ctx, orc, big_field_scene):
     quads = scenes.sample_quads(v.width, v.height, 0.01, 22)
     pe = orc.render_quads(v, quads, cube=cube, n0=n0)
     pt = orc.render_quads(v, quads, cube=cube, n0=n0, tables=ref_tables)
-    h32 = gpu_star_map(gpu_ctx, field, n0, bh.BH_TEXEL_FP32, key=1001)
+    h32 = gpu_star_map(gpu_ctx, field, n0, bh.BH_TEXEL_FP32)
     out = {}
     try:
         for name, h in (("fp16", h16), ("fp32", h32)):
@@ -105,7 +105,7 @@ def test_paper_temperature_law_and_black_sky(gpu_ctx, gpu_tables, orc, orc_table
 
 def test_every_tile_configuration_gives_the_same_image(gpu_ctx, gpu_tables):
     field = scenes.star_field(20000, 0)
-    h = gpu_star_map(gpu_ctx, field, 256, bh.BH_TEXEL_FP16, key=1000)
+    h = gpu_star_map(gpu_ctx, field, 256, bh.BH_TEXEL_FP16)
     v = scenes.boosted_orbit_view(200, 136)   # not a multiple of any tile
     ref = None
     try:
@@ -124,7 +124,7 @@ def test_small_and_ragged_images(gpu_ctx, gpu_tables, orc, orc_tables, W, H):
     """Images smaller than a tile and with odd sizes: every pixel is written, capture agrees
     with the oracle and escaping beams carry the same deflection."""
     field = scenes.star_field(20000, 0)
-    h = gpu_star_map(gpu_ctx, field, 256, bh.BH_TEXEL_FP16, key=1000)
+    h = gpu_star_map(gpu_ctx, field, 256, bh.BH_TEXEL_FP16)
     v = scenes.small_static_view()
     v.width, v.height = W, H
     rgb, aov = parity.render_gpu(gpu_ctx, gpu_tables, v, h)
@@ -173,18 +173,29 @@ def test_camera_between_photon_sphere_and_isco(gpu_ctx, gpu_tables, orc, orc_tab
 
 
 def test_tables_and_star_maps_are_shared_by_key(gpu_ctx):
+    """Tables are shared by parameters; star maps by content (a hash of the star arrays,
+    the star count, the face size and the texel format): the same stars uploaded again
+    into new device arrays share the map, a different field of the same size does not,
+    and neither does one changed in a single star's temperature."""
     t1 = bh.bh_precompute_tables(gpu_ctx, 512, 64, 32, bh.BH_TAB_FP64_BAND, 0.05)
     used = bh.bh_bytes_in_use(gpu_ctx)
     t2 = bh.bh_precompute_tables(gpu_ctx, 512, 64, 32, bh.BH_TAB_FP64_BAND, 0.05)
     assert t1 == t2 and bh.bh_bytes_in_use(gpu_ctx) == used
     field = scenes.star_field(5000, 9)
-    s1 = gpu_star_map(gpu_ctx, field, 128, bh.BH_TEXEL_FP16, key=77)
+    s1 = gpu_star_map(gpu_ctx, field, 128, bh.BH_TEXEL_FP16)
     used = bh.bh_bytes_in_use(gpu_ctx)
-    s2 = gpu_star_map(gpu_ctx, field, 128, bh.BH_TEXEL_FP16, key=77)
+    s2 = gpu_star_map(gpu_ctx, field, 128, bh.BH_TEXEL_FP16)
     assert s1 == s2 and bh.bh_bytes_in_use(gpu_ctx) == used
-    s3 = gpu_star_map(gpu_ctx, field, 128, bh.BH_TEXEL_FP32, key=77)
+    s3 = gpu_star_map(gpu_ctx, field, 128, bh.BH_TEXEL_FP32)
     assert s3 != s1 and bh.bh_bytes_in_use(gpu_ctx) > used
-    for s in (s3, s2, s1):
+    other = scenes.star_field(5000, 10)
+    s4 = gpu_star_map(gpu_ctx, other, 128, bh.BH_TEXEL_FP16)
+    assert s4 not in (s1, s3)
+    tweaked = scenes.StarField(field.dirs, field.intensity, field.temperature.copy(), 0)
+    tweaked.temperature[1234] += 1.0
+    s5 = gpu_star_map(gpu_ctx, tweaked, 128, bh.BH_TEXEL_FP16)
+    assert s5 not in (s1, s3, s4)
+    for s in (s5, s4, s3, s2, s1):
         bh.bh_release_stars(s)
     bh.bh_release_tables(t2)
     bh.bh_release_tables(t1)
@@ -337,7 +348,7 @@ def test_autotune_sweep_renders_every_form_bitwise_equal():
     ctx = bh.bh_create(0, 0)
     try:
         tables = bh.bh_precompute_tables(ctx, 512, 64, 32, bh.BH_TAB_FP64_BAND, 0.05)
-        hs = gpu_star_map(ctx, scenes.star_field(20000, 0), 256, bh.BH_TEXEL_FP16, key=5)
+        hs = gpu_star_map(ctx, scenes.star_field(20000, 0), 256, bh.BH_TEXEL_FP16)
         sizes = [(64, 48), (100, 37), (16, 16), (130, 66)]
         views = []
         for k, (w, h) in enumerate(sizes):
@@ -366,5 +377,39 @@ def test_autotune_sweep_renders_every_form_bitwise_equal():
             r = ref.cpu().numpy()
             assert np.isfinite(r).all()
             assert np.array_equal(a, r) and np.array_equal(b, r)
+    finally:
+        bh.bh_destroy(ctx)
+
+
+def test_batch_after_tables_are_replaced_matches_plain():
+    """A captured batch launch holds the table pointers and sizes by value.  Releasing a
+    table set and precomputing one of another size (whose arrays may reuse the freed
+    addresses) must not replay the old launch: the second batch equals bh_render with the
+    new tables bit for bit."""
+    import torch
+    ctx = bh.bh_create(0, 0)
+    try:
+        hs = gpu_star_map(ctx, scenes.star_field(20000, 0), 256, bh.BH_TEXEL_FP16)
+        views = []
+        for k, (w, h) in enumerate([(64, 48), (40, 72)]):
+            v = scenes.small_static_view()
+            v.width, v.height = w, h
+            views.append(bh.make_view(v, hs))
+        outs = [torch.empty((v.height, v.width, 4), dtype=torch.float32, device="cuda")
+                for v in views]
+        ptrs = [o.data_ptr() for o in outs]
+        st = bh.current_stream()
+        for d_n, u_ne, u_nphi in ((512, 64, 32), (512, 128, 64), (256, 64, 32)):
+            t = bh.bh_precompute_tables(ctx, d_n, u_ne, u_nphi, bh.BH_TAB_FP64_BAND, 0.05)
+            bh.bh_render_batch(ctx, t, views, ptrs, st)
+            torch.cuda.synchronize()
+            got = [o.cpu().numpy().copy() for o in outs]
+            for v, o, g in zip(views, outs, got):
+                o.zero_()
+                bh.bh_render(ctx, t, v, o.data_ptr(), None, st)
+                torch.cuda.synchronize()
+                assert np.array_equal(o.cpu().numpy(), g), (d_n, u_ne, u_nphi)
+            bh.bh_release_tables(t)
+        bh.bh_release_stars(hs)
     finally:
         bh.bh_destroy(ctx)
