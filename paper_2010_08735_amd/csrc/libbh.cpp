@@ -22,6 +22,7 @@
 
 #include "bh.h"
 #include "bh_dev.h"
+#include "bh_sched.h"
 
 namespace bh {
 hipError_t launch_precompute(float* D, float* Dt, int d_n, float* U, float* Ut, int u_ne,
@@ -149,25 +150,7 @@ struct Staging {
   bool used = false;
 };
 
-struct ServeReq {
-  uint64_t ticket;
-  bh_view view;
-  const bh_tables* tables;
-  float* out;
-  bool owned = false;         // out allocated by the library
-  size_t out_bytes = 0;
-  int tiles_total = 0, tiles_next = 0;
-  int tiles_x = 0;
-  double t_submit = 0, t_done = 0;
-  bool admitted = false, done = false;
-  bh_status status = BH_OK;
-};
-
-struct Launch {
-  hipEvent_t ev = nullptr;
-  std::vector<uint64_t> finishing;  // tickets whose last tile is in this launch
-  int slot = 0;
-};
+struct ServeBackend;
 
 struct bh_ctx {
   int device = 0;
@@ -184,12 +167,6 @@ struct bh_ctx {
   float lut_x0 = 6.0f, lut_dx = 15.0f / 4095.0f;
   int tile_cfg = 0;
   int persistent = 0;  // batched launches: 1 = persistent workgroups, 0 = one per tile
-  // recycled library-allocated images (serving), counted in `used`
-  std::multimap<size_t, void*> pool;
-  int64_t owned_live = 0;  // library-allocated images held by requests (not yet freed)
-  // stream-ordered memory pool of the library-allocated images: allocation and release on
-  // the serving stream never wait for the device
-  hipMemPool_t img_pool = nullptr;
   // batched launches
   ViewDev* b_views = nullptr;
   TileRun* b_runs = nullptr;
@@ -207,17 +184,11 @@ struct bh_ctx {
   using GraphKey = std::tuple<int, int, int, int, uintptr_t, const void*, const void*, const void*,
                               const void*, int, int, int>;
   std::map<GraphKey, GraphEntry> graphs;
-  // serving
-  std::thread serve_thread;
-  bool serving = false, stop = false;
-  bh_serve_params sp{};
-  hipStream_t serve_stream = nullptr;
+  // serving: the scheduler (bh_sched.h), its HIP backend and thread; smu guards their lifetime
   std::mutex smu;
-  std::condition_variable scv, done_cv;
-  std::deque<ServeReq*> queue;
-  std::unordered_map<uint64_t, ServeReq*> reqs;
-  uint64_t next_ticket = 1;
-  size_t pending = 0;
+  std::unique_ptr<ServeBackend> serve_backend;
+  std::unique_ptr<sched::Scheduler<ServeBackend>> sched;
+  std::thread serve_thread;
 };
 
 static double now_s() {
@@ -1012,7 +983,8 @@ static int batch_grid(const bh_ctx* c, int cfg, int64_t ntiles) {
 // (after `slot_free`, the end of the last launch that read dviews/druns) and s waits for
 // them through `copied`, so they overlap the kernels already queued on s.  Caller holds
 // c->mu.
-static bh_status enqueue_batch(bh_ctx* c, const TablesDev& T, const std::vector<ViewDev>& vds,
+static bh_status enqueue_batch(bh_ctx* c, int cfg, int pers, const TablesDev& T,
+                               const std::vector<ViewDev>& vds,
                                const std::vector<TileRun>& runs, int ntiles, ViewDev* dviews,
                                TileRun* druns, int* counter, Staging& stg, hipStream_t s,
                                bool use_graph, hipStream_t cs = nullptr,
@@ -1033,8 +1005,6 @@ static bh_status enqueue_batch(bh_ctx* c, const TablesDev& T, const std::vector<
     HIPCHK(hipEventRecord(copied, cs));
     HIPCHK(hipStreamWaitEvent(s, copied, 0));
   }
-  int cfg = c->tile_cfg;
-  int pers = c->persistent;
   int grid = batch_grid(c, cfg, ntiles);
   int nruns = (int)runs.size();
   int anim = 0;
@@ -1135,8 +1105,8 @@ extern "C" bh_status bh_render_batch(bh_ctx* c, const bh_tables* t, const bh_vie
   // call after the previous one even when it was issued on another stream
   if (!c->b_last) HIPCHK(hipEventCreateWithFlags(&c->b_last, hipEventDisableTiming));
   else HIPCHK(hipStreamWaitEvent(s, c->b_last, 0));
-  st = enqueue_batch(c, tables_dev(t), vds, runs, (int)ntiles, c->b_views, c->b_runs, c->b_counter,
-                     stg, s, true);
+  st = enqueue_batch(c, c->tile_cfg, c->persistent, tables_dev(t), vds, runs, (int)ntiles,
+                     c->b_views, c->b_runs, c->b_counter, stg, s, true);
   if (st) return st;
   HIPCHK(hipEventRecord(c->b_last, s));
   return BH_OK;
@@ -1277,239 +1247,191 @@ extern "C" bh_status bh_band_eval(bh_ctx* c, const float* temps, int64_t n, floa
 }
 
 // ---- serving ---------------------------------------------------------------------------------
-// One scheduler thread per context.  Each iteration admits queued requests in arrival
-// order while their library-allocated images fit the HBM budget, then fills one
-// persistent launch with up to max_tiles_per_launch tiles taken from the admitted requests
-// in order (a big frame spills into later launches, so frames that arrive meanwhile join
-// the next launch instead of waiting behind it).  Up to max_inflight_launches launches are
-// kept queued on the serving stream; a request completes with the launch holding its last
-// tile.
+// The policy (admission by budget, continuous batching, failure and cancellation) is the
+// scheduler of bh_sched.h, run on its own thread; this is its HIP backend.  Launches go to
+// the serving stream through maxin + 1 slots of device records (view blocks, tile runs,
+// a claim counter), uploaded on a copy stream after the slot's previous launch; a launch is
+// in flight until an event recorded after it completes.  Library images come from a
+// stream-ordered memory pool on the serving stream, inside the context's HBM budget.
+struct ServePayload {
+  bh_view view;
+  const bh_tables* tables;
+};
 
-// Library-allocated images: reuse a freed image of the same size, else allocate inside
-// the budget from the context's stream-ordered pool, releasing pooled images (in stream
-// order) if that is what it takes.  Caller holds c->smu.
-static void* pool_get(bh_ctx* c, size_t bytes) {
-  auto it = c->pool.find(bytes);
-  if (it != c->pool.end()) {
-    void* p = it->second;
-    c->pool.erase(it);
-    return p;
+struct ServeBackend {
+  using Payload = ServePayload;
+  struct Handle {
+    hipEvent_t ev = nullptr;
+  };
+  using Pieces = std::vector<sched::Piece<Payload>>;
+
+  bh_ctx* c;
+  int cfg = 0, pers = 0;         // tile configuration and launch form, fixed at start
+  int tw = 16, th = 16;
+  int slots = 0, slot = 0;
+  hipStream_t stream = nullptr, copy_stream = nullptr;
+  hipMemPool_t img_pool = nullptr;
+  std::vector<Staging> stg;
+  std::vector<ViewDev*> dviews;
+  std::vector<TileRun*> druns;
+  std::vector<int*> dcounter;
+  std::vector<size_t> rcap;
+  std::vector<hipEvent_t> slot_free, copied, evpool;
+  bool dev_ok = true;
+
+  ServeBackend(bh_ctx* ctx, int maxin) : c(ctx), slots(maxin + 1) {
+    cfg = c->tile_cfg;
+    pers = c->persistent;
+    int waves, ppt;
+    tile_config(cfg, &tw, &th, &waves, &ppt);
+    stg.resize(slots);
+    dviews.assign(slots, nullptr);
+    druns.assign(slots, nullptr);
+    dcounter.assign(slots, nullptr);
+    rcap.assign(slots, 0);
+    slot_free.assign(slots, nullptr);
+    copied.assign(slots, nullptr);
   }
-  for (;;) {
-    // reserve in the budget first, as dev_alloc does, then allocate
+
+  // streams, image pool, per-slot counters and events
+  hipError_t init() {
+    hipError_t e = hipStreamCreateWithFlags(&stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&copy_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) {
+      hipMemPoolProps props = {};
+      props.allocType = hipMemAllocationTypePinned;
+      props.location.type = hipMemLocationTypeDevice;
+      props.location.id = c->device;
+      e = hipMemPoolCreate(&img_pool, &props);
+    }
+    if (e == hipSuccess) {
+      uint64_t keep = UINT64_MAX;  // released images stay reserved for the next allocations
+      e = hipMemPoolSetAttribute(img_pool, hipMemPoolAttrReleaseThreshold, &keep);
+    }
+    for (int k = 0; k < slots && e == hipSuccess; ++k) {
+      e = hipMalloc(&dcounter[k], sizeof(int) * 16);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&slot_free[k], hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&copied[k], hipEventDisableTiming);
+    }
+    return e;
+  }
+
+  // after the scheduler is gone (its destructor returned every image through dealloc)
+  ~ServeBackend() {
+    if (stream) (void)hipStreamSynchronize(stream);
+    if (copy_stream) {
+      (void)hipStreamSynchronize(copy_stream);
+      (void)hipStreamDestroy(copy_stream);
+    }
+    for (int k = 0; k < slots; ++k) {
+      if (slot_free[k]) (void)hipEventDestroy(slot_free[k]);
+      if (copied[k]) (void)hipEventDestroy(copied[k]);
+      if (dviews[k]) (void)hipFree(dviews[k]);
+      if (druns[k]) (void)hipFree(druns[k]);
+      if (dcounter[k]) (void)hipFree(dcounter[k]);
+      if (stg[k].host) (void)hipHostFree(stg[k].host);
+      if (stg[k].done) (void)hipEventDestroy(stg[k].done);
+    }
+    for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
+    if (img_pool) (void)hipMemPoolDestroy(img_pool);
+    if (stream) (void)hipStreamDestroy(stream);
+  }
+
+  double now() { return now_s(); }
+
+  int64_t tiles(const Payload& p) {
+    return (int64_t)((p.view.width + tw - 1) / tw) * ((p.view.height + th - 1) / th);
+  }
+
+  // reserve in the budget first, as dev_alloc does, then allocate on the serving stream
+  void* try_alloc(size_t bytes) {
     const uint64_t before = c->used.fetch_add(bytes);
     if (!c->budget || before + bytes <= c->budget) {
       void* p = nullptr;
-      if (hipMallocFromPoolAsync(&p, bytes, c->img_pool, c->serve_stream) == hipSuccess)
-        return p;
+      if (hipMallocFromPoolAsync(&p, bytes, img_pool, stream) == hipSuccess) return p;
     }
     c->used -= bytes;
-    if (c->pool.empty()) return nullptr;
-    auto big = std::prev(c->pool.end());
-    (void)hipFreeAsync(big->second, c->serve_stream);
-    c->used -= big->first;
-    c->pool.erase(big);
+    return nullptr;
   }
-}
 
-static void pool_put(bh_ctx* c, void* p, size_t bytes) { c->pool.emplace(bytes, p); }
-
-static void finish_launch(bh_ctx* c, Launch& L) {
-  double t = now_s();
-  std::lock_guard<std::mutex> g(c->smu);
-  for (uint64_t tk : L.finishing) {
-    auto it = c->reqs.find(tk);
-    if (it == c->reqs.end()) continue;
-    it->second->done = true;
-    it->second->t_done = t;
-    c->pending--;
+  void dealloc(void* p, size_t bytes) {
+    (void)hipFreeAsync(p, stream);
+    c->used -= bytes;
   }
-  c->done_cv.notify_all();
-}
 
-static void serve_loop(bh_ctx* c) {
-  (void)hipSetDevice(c->device);
-  const int maxin = std::max(1, c->sp.max_inflight_launches);
-  const int64_t maxtiles = std::max<int64_t>(1, c->sp.max_tiles_per_launch);
-  std::vector<Staging> stg(maxin + 1);
-  // per launch slot: view blocks, tile runs (one per request in the launch), tile counter
-  std::vector<ViewDev*> dviews(maxin + 1, nullptr);
-  std::vector<TileRun*> druns(maxin + 1, nullptr);
-  std::vector<int*> dcounter(maxin + 1, nullptr);
-  std::vector<size_t> rcap(maxin + 1, 0);
-  // uploads on their own stream; per slot: end of its last launch, end of its upload
-  hipStream_t copy_stream = nullptr;
-  std::vector<hipEvent_t> slot_free(maxin + 1, nullptr), copied(maxin + 1, nullptr);
-  bool dev_ok = hipStreamCreateWithFlags(&copy_stream, hipStreamNonBlocking) == hipSuccess;
-  for (int k = 0; k <= maxin; ++k) {
-    dev_ok = dev_ok && hipMalloc(&dcounter[k], sizeof(int) * 16) == hipSuccess;
-    dev_ok = dev_ok && hipEventCreateWithFlags(&slot_free[k], hipEventDisableTiming) == hipSuccess;
-    dev_ok = dev_ok && hipEventCreateWithFlags(&copied[k], hipEventDisableTiming) == hipSuccess;
-  }
-  std::deque<Launch> inflight;
-  std::vector<hipEvent_t> evpool;
-  int slot = 0;
-  std::vector<ServeReq*> active;
-  for (;;) {
-    // retire finished launches
-    while (!inflight.empty() && hipEventQuery(inflight.front().ev) == hipSuccess) {
-      finish_launch(c, inflight.front());
-      evpool.push_back(inflight.front().ev);
-      inflight.pop_front();
-    }
-    std::vector<ServeReq*> admit_now;
-    {
-      std::unique_lock<std::mutex> lk(c->smu);
-      if (c->stop && c->queue.empty() && active.empty() && inflight.empty()) break;
-      // admission: FIFO, stop at the first request that does not fit the budget
-      while (!c->queue.empty()) {
-        ServeReq* r = c->queue.front();
-        if (!r->out) {
-          void* p = pool_get(c, r->out_bytes);
-          if (!p) {
-            if (c->owned_live > 0) break;  // wait for the client to free an image
-            // nothing held and nothing pooled: the image can never be allocated
-            r->status = BH_ENOMEM;
-            r->done = true;
-            r->t_done = now_s();
-            c->pending--;
-            c->queue.pop_front();
-            c->done_cv.notify_all();
-            continue;
-          }
-          r->out = (float*)p;
-          r->owned = true;
-          c->owned_live++;
-        }
-        r->admitted = true;
-        c->queue.pop_front();
-        active.push_back(r);
+  int launch(const Pieces& pieces, int64_t ntiles, Handle* h) {
+    int st = sched::kEDEVICE;
+    if (ntiles > 0 && dev_ok) st = enqueue(pieces, ntiles);
+    if (evpool.empty()) {
+      hipEvent_t ev = nullptr;
+      if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+        dev_ok = false;
+        (void)hipStreamSynchronize(stream);  // no event: make the launch complete now
       }
-      if (active.empty() && inflight.empty()) {
-        if (c->stop) continue;
-        c->scv.wait_for(lk, std::chrono::milliseconds(2));
-        continue;
-      }
+      evpool.push_back(ev);
     }
-    if (active.empty()) {
-      // launches in flight, nothing to add: poll so new arrivals are admitted at once
-      std::unique_lock<std::mutex> lk(c->smu);
-      c->scv.wait_for(lk, std::chrono::microseconds(50));
-      continue;
+    h->ev = evpool.back();
+    evpool.pop_back();
+    if (h->ev && hipEventRecord(h->ev, stream) != hipSuccess) {
+      (void)hipStreamSynchronize(stream);
+      (void)hipEventDestroy(h->ev);
+      h->ev = nullptr;
     }
-    if ((int)inflight.size() >= maxin) {
-      (void)hipEventSynchronize(inflight.front().ev);  // the device is busy: wait for a slot
-      continue;
-    }
-    // fill one launch: one run of tiles per request, at most maxtiles tiles in all
+    slot = (slot + 1) % slots;
+    return st;
+  }
+
+  int enqueue(const Pieces& pieces, int64_t ntiles) {
     std::vector<ViewDev> vds;
     std::vector<TileRun> runs;
-    std::vector<uint64_t> in_launch;  // tickets with tiles in this launch
-    int64_t ntiles = 0;
-    Launch L;
-    std::vector<ServeReq*> keep;
-    int tw, th, waves, ppt;
-    tile_config(c->tile_cfg, &tw, &th, &waves, &ppt);
-    const bh_tables* tb = active.front()->tables;  // one table set per launch
-    for (ServeReq* r : active) {
-      if (ntiles >= maxtiles || r->tables != tb) {
-        keep.push_back(r);
-        continue;
-      }
-      if (r->tiles_total == 0) {
-        r->tiles_x = (r->view.width + tw - 1) / tw;
-        r->tiles_total = r->tiles_x * ((r->view.height + th - 1) / th);
-      }
+    int64_t start = 0;
+    for (const auto& pc : pieces) {
       ViewDev vd;
-      if (make_view(&r->view, r->out, nullptr, &vd) != BH_OK) {  // validated at submit
-        r->status = BH_EINVAL;
-        L.finishing.push_back(r->ticket);
-        continue;
-      }
-      int vi = (int)vds.size();
+      if (make_view(&pc.r->payload.view, pc.r->out, nullptr, &vd) != BH_OK) return sched::kEINVAL;
+      const int tx = (pc.r->payload.view.width + tw - 1) / tw;
+      runs.push_back(TileRun{(int)vds.size(), (int)pc.first, (int)start, tx});
       vds.push_back(vd);
-      int64_t take = std::min<int64_t>(r->tiles_total - r->tiles_next, maxtiles - ntiles);
-      runs.push_back(TileRun{vi, r->tiles_next, (int)ntiles, r->tiles_x});
-      in_launch.push_back(r->ticket);
-      ntiles += take;
-      r->tiles_next += (int)take;
-      if (r->tiles_next >= r->tiles_total)
-        L.finishing.push_back(r->ticket);
-      else
-        keep.push_back(r);
+      start += pc.count;
     }
-    active.swap(keep);
-    if (ntiles == 0) {
-      if (!L.finishing.empty()) finish_launch(c, L);
-      continue;
-    }
-    // device buffers of this slot (the slot's previous launch has finished: at most maxin
-    // launches are in flight and there are maxin + 1 slots)
-    if (dev_ok && rcap[slot] < vds.size()) {
+    // this slot's device records (its previous launch has finished: fewer than `slots`
+    // launches are in flight, and the upload also waits for its slot_free event)
+    if (rcap[slot] < vds.size()) {
       if (dviews[slot]) (void)hipFree(dviews[slot]);
       if (druns[slot]) (void)hipFree(druns[slot]);
       dviews[slot] = nullptr;
       druns[slot] = nullptr;
       rcap[slot] = 0;
-      size_t cap = std::max<size_t>(vds.size(), 256);
-      if (hipMalloc(&dviews[slot], sizeof(ViewDev) * cap) == hipSuccess &&
-          hipMalloc(&druns[slot], sizeof(TileRun) * cap) == hipSuccess)
-        rcap[slot] = cap;
-      else
+      const size_t cap = std::max<size_t>(vds.size(), 256);
+      if (hipMalloc(&dviews[slot], sizeof(ViewDev) * cap) != hipSuccess ||
+          hipMalloc(&druns[slot], sizeof(TileRun) * cap) != hipSuccess) {
         dev_ok = false;
-    }
-    bh_status st = BH_EDEVICE;
-    if (dev_ok) {
-      std::lock_guard<std::mutex> g(c->mu);
-      st = enqueue_batch(c, tables_dev(tb), vds, runs, (int)ntiles, dviews[slot], druns[slot],
-                         dcounter[slot], stg[slot], c->serve_stream, false, copy_stream,
-                         slot_free[slot], copied[slot]);
-      if (st == BH_OK && hipEventRecord(slot_free[slot], c->serve_stream) != hipSuccess)
-        st = BH_EDEVICE;
-    }
-    if (evpool.empty()) {
-      hipEvent_t ev;
-      (void)hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-      evpool.push_back(ev);
-    }
-    L.ev = evpool.back();
-    evpool.pop_back();
-    (void)hipEventRecord(L.ev, c->serve_stream);
-    if (st != BH_OK) {
-      // every request with tiles in this launch fails; the unfinished ones stop here
-      std::lock_guard<std::mutex> lk(c->smu);
-      for (uint64_t tk : in_launch) {
-        ServeReq* r = c->reqs[tk];
-        r->status = st;
-        if (r->tiles_next < r->tiles_total) {
-          r->tiles_next = r->tiles_total;
-          L.finishing.push_back(tk);
-        }
+        return sched::kEDEVICE;
       }
-      active.erase(std::remove_if(active.begin(), active.end(),
-                                  [](ServeReq* r) { return r->status != BH_OK; }),
-                   active.end());
+      rcap[slot] = cap;
     }
-    L.slot = slot;
-    slot = (slot + 1) % (maxin + 1);
-    inflight.push_back(L);
+    bh_status st = enqueue_batch(c, cfg, pers, tables_dev(pieces.front().r->payload.tables), vds,
+                                 runs, (int)ntiles, dviews[slot], druns[slot], dcounter[slot],
+                                 stg[slot], stream, false, copy_stream, slot_free[slot],
+                                 copied[slot]);
+    if (st == BH_OK && hipEventRecord(slot_free[slot], stream) != hipSuccess) st = BH_EDEVICE;
+    return st;
   }
-  (void)hipStreamSynchronize(c->serve_stream);
-  if (copy_stream) {
-    (void)hipStreamSynchronize(copy_stream);
-    (void)hipStreamDestroy(copy_stream);
+
+  bool done(Handle& h) { return !h.ev || hipEventQuery(h.ev) == hipSuccess; }
+  void wait(Handle& h) {
+    if (h.ev) (void)hipEventSynchronize(h.ev);
   }
-  for (int k = 0; k <= maxin; ++k) {
-    if (slot_free[k]) (void)hipEventDestroy(slot_free[k]);
-    if (copied[k]) (void)hipEventDestroy(copied[k]);
-    if (dviews[k]) (void)hipFree(dviews[k]);
-    if (druns[k]) (void)hipFree(druns[k]);
-    if (dcounter[k]) (void)hipFree(dcounter[k]);
-    if (stg[k].host) (void)hipHostFree(stg[k].host);
-    if (stg[k].done) (void)hipEventDestroy(stg[k].done);
+  void release(Handle& h) {
+    if (h.ev) evpool.push_back(h.ev);
+    h.ev = nullptr;
   }
-  for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
-}
+};
+
+static_assert((int)sched::kEAGAIN == (int)BH_EAGAIN && (int)sched::kENOMEM == (int)BH_ENOMEM &&
+                  (int)sched::kECANCELED == (int)BH_ECANCELED &&
+                  (int)sched::kENOTFOUND == (int)BH_ENOTFOUND &&
+                  (int)sched::kEDEVICE == (int)BH_EDEVICE,
+              "scheduler status codes are those of bh_status");
 
 // Most tiles one serving launch may hold: the one-workgroup-per-tile launch runs
 // tiles x (tile pixels / pixels per thread) work-items, at most 1024 per tile (every tile
@@ -1522,67 +1444,41 @@ extern "C" bh_status bh_serve_start(bh_ctx* c, const bh_serve_params* p) {
                                " (one launch covers fewer than 2^32 work-items)");
   if (!c) return fail(BH_EINVAL, "NULL context");
   std::lock_guard<std::mutex> lk(c->smu);
-  if (c->serving) return fail(BH_EINVAL, "serving already started");
-  c->sp.max_queue = p && p->max_queue > 0 ? p->max_queue : 1 << 20;
-  c->sp.max_inflight_launches = p && p->max_inflight_launches > 0 ? p->max_inflight_launches : 6;
-  c->sp.max_tiles_per_launch = p && p->max_tiles_per_launch > 0 ? p->max_tiles_per_launch : 262144;
+  if (c->sched) return fail(BH_EINVAL, "serving already started");
+  sched::Params sp;
+  sp.max_queue = p && p->max_queue > 0 ? p->max_queue : 1 << 20;
+  sp.max_inflight = p && p->max_inflight_launches > 0 ? p->max_inflight_launches : 6;
+  sp.max_tiles = p && p->max_tiles_per_launch > 0 ? p->max_tiles_per_launch : 262144;
   HIPCHK(hipSetDevice(c->device));
-  HIPCHK(hipStreamCreateWithFlags(&c->serve_stream, hipStreamNonBlocking));
-  hipMemPoolProps props = {};
-  props.allocType = hipMemAllocationTypePinned;
-  props.location.type = hipMemLocationTypeDevice;
-  props.location.id = c->device;
-  hipError_t e = hipMemPoolCreate(&c->img_pool, &props);
-  if (e == hipSuccess) {
-    uint64_t keep = UINT64_MAX;  // released images stay reserved for the next allocations
-    e = hipMemPoolSetAttribute(c->img_pool, hipMemPoolAttrReleaseThreshold, &keep);
+  std::unique_ptr<ServeBackend> be;
+  {
+    std::lock_guard<std::mutex> g(c->mu);  // tile configuration and launch form
+    be.reset(new ServeBackend(c, sp.max_inflight));
   }
-  if (e != hipSuccess) {
-    if (c->img_pool) (void)hipMemPoolDestroy(c->img_pool);
-    c->img_pool = nullptr;
-    (void)hipStreamDestroy(c->serve_stream);
-    return fail(BH_EDEVICE, std::string("image pool: ") + hipGetErrorString(e));
-  }
-  c->stop = false;
-  c->serving = true;
-  c->serve_thread = std::thread(serve_loop, c);
+  hipError_t e = be->init();
+  if (e != hipSuccess) return fail(BH_EDEVICE, std::string("serving set-up: ") + hipGetErrorString(e));
+  c->serve_backend = std::move(be);
+  c->sched.reset(new sched::Scheduler<ServeBackend>(*c->serve_backend, sp));
+  c->serve_thread = std::thread([c] {
+    (void)hipSetDevice(c->device);
+    c->sched->run();
+  });
   return BH_OK;
 }
 
+// Queued requests are cancelled, admitted ones finish; then every serving resource goes.
 static void serve_stop(bh_ctx* c) {
-  {
-    std::lock_guard<std::mutex> lk(c->smu);
-    if (!c->serving) return;
-    // queued requests that were never admitted are cancelled
-    for (ServeReq* r : c->queue) {
-      r->status = BH_ECANCELED;
-      r->done = true;
-      c->pending--;
-    }
-    c->queue.clear();
-    c->stop = true;
-  }
-  c->scv.notify_all();
+  std::lock_guard<std::mutex> lk(c->smu);
+  if (!c->sched) return;
+  c->sched->stop();
   c->serve_thread.join();
-  c->serving = false;
-  for (auto& kv : c->reqs) {
-    if (kv.second->owned) {
-      (void)hipFreeAsync(kv.second->out, c->serve_stream);
-      c->used -= kv.second->out_bytes;
-      c->owned_live--;
-    }
-    delete kv.second;
-  }
-  c->reqs.clear();
-  for (auto& kv : c->pool) {
-    (void)hipFreeAsync(kv.second, c->serve_stream);
-    c->used -= kv.first;
-  }
-  c->pool.clear();
-  (void)hipStreamSynchronize(c->serve_stream);
-  (void)hipMemPoolDestroy(c->img_pool);
-  c->img_pool = nullptr;
-  (void)hipStreamDestroy(c->serve_stream);
+  c->sched.reset();          // returns the requests' and the pool's images
+  c->serve_backend.reset();  // then the streams, slots and pool
+}
+
+static sched::Scheduler<ServeBackend>* serving(bh_ctx* c) {
+  std::lock_guard<std::mutex> lk(c->smu);
+  return c->sched.get();
 }
 
 extern "C" bh_status bh_submit(bh_ctx* c, const bh_tables* t, const bh_view* v, float* out,
@@ -1592,68 +1488,50 @@ extern "C" bh_status bh_submit(bh_ctx* c, const bh_tables* t, const bh_view* v, 
   float dummy = 0;
   bh_status st = make_view(v, out ? out : &dummy, nullptr, &tmp);
   if (st) return st;
-  std::lock_guard<std::mutex> lk(c->smu);
-  if (!c->serving) return fail(BH_EINVAL, "serving not started");
-  if ((int)c->queue.size() >= c->sp.max_queue) return fail(BH_EAGAIN, "serving queue full");
-  auto* r = new ServeReq;
-  r->ticket = c->next_ticket++;
-  r->view = *v;
-  r->tables = t;
-  r->out = out;
-  r->out_bytes = sizeof(float4) * (size_t)v->width * v->height;
-  if (!out && c->budget && r->out_bytes > c->budget) {
-    delete r;
-    return fail(BH_ENOMEM, "image larger than the HBM budget");
-  }
-  r->t_submit = now_s();
-  c->reqs[r->ticket] = r;
-  c->queue.push_back(r);
-  c->pending++;
-  *ticket = r->ticket;
-  c->scv.notify_all();
+  auto* s = serving(c);
+  if (!s) return fail(BH_EINVAL, "serving not started");
+  const size_t bytes = sizeof(float4) * (size_t)v->width * v->height;
+  if (!out && c->budget && bytes > c->budget) return fail(BH_ENOMEM, "image larger than the HBM budget");
+  const int rc = s->submit(ServePayload{*v, t}, t, out, bytes, ticket);
+  if (rc == sched::kEAGAIN) return fail(BH_EAGAIN, "serving queue full");
+  if (rc != sched::kOK) return fail((bh_status)rc, "serving stopped");
   return BH_OK;
 }
 
 extern "C" bh_status bh_poll(bh_ctx* c, uint64_t ticket, int32_t* done, double* latency) {
   if (!c || !done) return fail(BH_EINVAL, "NULL argument");
-  std::lock_guard<std::mutex> lk(c->smu);
-  auto it = c->reqs.find(ticket);
-  if (it == c->reqs.end()) return fail(BH_ENOTFOUND, "unknown ticket");
-  ServeReq* r = it->second;
-  *done = r->done ? 1 : 0;
-  if (latency) *latency = r->done ? r->t_done - r->t_submit : now_s() - r->t_submit;
-  return r->status;
+  auto* s = serving(c);
+  if (!s) return fail(BH_ENOTFOUND, "serving not started");
+  int d = 0;
+  const int rc = s->poll(ticket, &d, latency);
+  if (rc == sched::kENOTFOUND) return fail(BH_ENOTFOUND, "unknown ticket");
+  *done = d;
+  return (bh_status)rc;
 }
 
 extern "C" bh_status bh_ticket_image(bh_ctx* c, uint64_t ticket, float** img) {
   if (!c || !img) return fail(BH_EINVAL, "NULL argument");
-  std::lock_guard<std::mutex> lk(c->smu);
-  auto it = c->reqs.find(ticket);
-  if (it == c->reqs.end()) return fail(BH_ENOTFOUND, "unknown ticket");
-  if (!it->second->done) return fail(BH_EAGAIN, "not finished");
-  *img = it->second->out;
+  auto* s = serving(c);
+  if (!s) return fail(BH_ENOTFOUND, "serving not started");
+  const int rc = s->image(ticket, img);
+  if (rc == sched::kENOTFOUND) return fail(BH_ENOTFOUND, "unknown ticket");
+  if (rc == sched::kEAGAIN) return fail(BH_EAGAIN, "not finished");
   return BH_OK;
 }
 
 extern "C" bh_status bh_ticket_free(bh_ctx* c, uint64_t ticket) {
   if (!c) return fail(BH_EINVAL, "NULL context");
-  std::lock_guard<std::mutex> lk(c->smu);
-  auto it = c->reqs.find(ticket);
-  if (it == c->reqs.end()) return fail(BH_ENOTFOUND, "unknown ticket");
-  if (!it->second->done) return fail(BH_EAGAIN, "not finished");
-  if (it->second->owned) {
-    pool_put(c, it->second->out, it->second->out_bytes);
-    c->owned_live--;
-  }
-  delete it->second;
-  c->reqs.erase(it);
-  c->scv.notify_all();  // freed budget may admit queued requests
+  auto* s = serving(c);
+  if (!s) return fail(BH_ENOTFOUND, "serving not started");
+  const int rc = s->release(ticket);
+  if (rc == sched::kENOTFOUND) return fail(BH_ENOTFOUND, "unknown ticket");
+  if (rc == sched::kEAGAIN) return fail(BH_EAGAIN, "not finished");
   return BH_OK;
 }
 
 extern "C" bh_status bh_serve_drain(bh_ctx* c) {
   if (!c) return fail(BH_EINVAL, "NULL context");
-  std::unique_lock<std::mutex> lk(c->smu);
-  c->done_cv.wait(lk, [&] { return c->pending == 0; });
+  auto* s = serving(c);
+  if (s) s->drain();
   return BH_OK;
 }

@@ -1,0 +1,116 @@
+/*
+ * Sanitizer run of the FP64 oracle's C code (test infrastructure).  Calls every entry point
+ * of oracle/bh_oracle.h on small inputs, the multithreaded ones with several threads, so
+ * that tests/test_sanitizers.py can build it under ASan + UBSan and under TSan and check
+ * that the runs are clean.  Exits non-zero if a result is not finite.
+ */
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "bh_oracle.h"
+
+static int bad = 0;
+#define FINITE(x)                                                \
+  do {                                                           \
+    if (!isfinite(x)) {                                          \
+      fprintf(stderr, "%s:%d: not finite: %s\n", __FILE__, __LINE__, #x); \
+      bad = 1;                                                   \
+    }                                                            \
+  } while (0)
+
+int main(void) {
+  /* geometry of single rays */
+  orc_ray r;
+  orc_trace_exact(1.0 / 15.0, 1.2, 0.4, 1.0 / 3.0, 1.0 / 12.0, 1.0, &r);
+  FINITE(r.delta_prime);
+  orc_march_ray(1.0 / 15.0, 1.2, 0.4, 1.0 / 3.0, 1.0 / 12.0, 100, 1.0, &r);
+  FINITE(r.delta_prime);
+  FINITE(orc_apsis(0.1));
+  FINITE(orc_deflection(0.2));
+  FINITE(orc_u_at_phi(0.05, 0.01, 1.0, 1.0));
+
+  /* tables by quadrature, four threads */
+  const int dn = 32, ne = 8, nphi = 8;
+  double* D = calloc((size_t)dn * dn, sizeof(double));
+  double* U = calloc((size_t)ne * nphi, sizeof(double));
+  double* Dt = calloc((size_t)dn * dn, sizeof(double));
+  double* Ut = calloc((size_t)ne * nphi, sizeof(double));
+  if (orc_tables(dn, ne, nphi, D, U, 4) || orc_tables_time(dn, ne, nphi, Dt, Ut, 4)) bad = 1;
+  orc_trace_table_t(D, Dt, dn, U, Ut, ne, nphi, 1.0 / 15.0, 1.2, 0.4, 1.0 / 3.0, 1.0 / 12.0, &r);
+  FINITE(r.delta_prime);
+
+  /* emission and a star cube map */
+  double L[3];
+  orc_band_radiance(6000.0, L);
+  FINITE(L[0] + L[1] + L[2]);
+  enum { NS = 500, N0 = 16 };
+  float dirs[3 * NS], inten[NS], temp[NS];
+  unsigned s = 12345u;
+  for (int i = 0; i < NS; ++i) {
+    for (int k = 0; k < 3; ++k) {
+      s = s * 1664525u + 1013904223u;
+      dirs[3 * i + k] = (float)((s >> 8) / 16777216.0 * 2.0 - 1.0);
+    }
+    inten[i] = 0.5f;
+    temp[i] = 5000.0f + (float)i;
+  }
+  double* cube = calloc((size_t)orc_cubemap_texels(N0) * 4, sizeof(double));
+  if (orc_cubemap_build(dirs, inten, temp, NS, N0, cube)) bad = 1;
+
+  /* whole pixels: exact mode, table mode and marching, four threads */
+  orc_view v;
+  memset(&v, 0, sizeof(v));
+  v.r_s = 1.0;
+  v.cam_pos[0] = 15.0;
+  v.cam_pos[2] = 2.0;
+  double rot[9] = {0, 1, 0, 0, 0, 1, 1, 0, 0}; /* e_w, e_h, e_d: looking along -x */
+  memcpy(v.cam_rot, rot, sizeof(rot));
+  v.fov_y = 1.0;
+  v.width = v.height = 8;
+  v.disc_r_in = 3.0;
+  v.disc_r_out = 12.0;
+  v.disc_T0 = 1e4;
+  v.disc_T_exp = -0.75;
+  v.disc_opacity = 1.0;
+  v.k_disc = 1e-7;
+  v.k_star = 1.0;
+  int32_t quads[32];
+  int nq = 0;
+  for (int y = 0; y < 8; y += 2)
+    for (int x = 0; x < 8; x += 2) {
+      quads[2 * nq] = x;
+      quads[2 * nq + 1] = y;
+      ++nq;
+    }
+  orc_pixel* px = calloc((size_t)4 * nq, sizeof(orc_pixel));
+  if (orc_render_quads(&v, cube, N0, NULL, 0, NULL, 0, 0, quads, nq, px, 4)) bad = 1;
+  if (orc_render_quads(&v, cube, N0, D, dn, U, ne, nphi, quads, nq, px, 4)) bad = 1;
+  if (orc_render_quads_m(&v, cube, N0, 50, quads, nq, px, 4)) bad = 1;
+  for (int i = 0; i < 4 * nq; ++i) FINITE(px[i].rgb[0] + px[i].rgb[1] + px[i].rgb[2]);
+  double parts[6] = {5.0, 6.0, 0.3, 8.0, 9.0, 2.0};
+  v.disc_density = 1;
+  v.n_particles = 2;
+  v.particles = parts;
+  v.time = 100.0;
+  if (orc_render_quads_t(&v, cube, N0, D, Dt, dn, U, Ut, ne, nphi, quads, nq, px, 4)) bad = 1;
+  FINITE(orc_ellipk(0.5));
+
+  /* post-process */
+  double img[8 * 8 * 4], out[8 * 8 * 4], w[4] = {0.7, 0.2, 0.07, 0.03};
+  for (int i = 0; i < 8 * 8 * 4; ++i) img[i] = (i % 7) * 0.1;
+  if (orc_bloom(img, 8, 8, 3, w, out)) bad = 1;
+  uint8_t codes[8 * 8 * 4];
+  double scaled[8 * 8 * 3];
+  if (orc_tonemap(out, 64, 2.0, codes, scaled)) bad = 1;
+
+  free(px);
+  free(cube);
+  free(D);
+  free(U);
+  free(Dt);
+  free(Ut);
+  if (!bad) printf("oracle sanitizer run ok\n");
+  return bad;
+}
