@@ -259,6 +259,20 @@ bh_status bh_render_march(bh_ctx* ctx, const bh_view* v, int32_t max_steps, floa
 bh_status bh_render_batch(bh_ctx* ctx, const bh_tables* t, const bh_view* views, int32_t n,
                           float* const* outs_dev, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): bh_render_batch without any allocation.
+ * The launch's view records, tile runs and work counter live in a fixed device array of
+ * the library (256 B + 512 x 304 B = 152 KiB, one per GPU, held until the process ends), so n is at
+ * most BH_NOALLOC_MAX_VIEWS (BH_EINVAL above); the records are uploaded through pinned host
+ * memory that bh_create sets up, and the kernels are launched directly (no graph is
+ * built).  Same kernels as bh_render_batch with the same tile configuration and launch
+ * form, so the same bits.  Every call on one GPU (any context) uses the same array: calls
+ * in order on one stream are safe, calls that overlap on one GPU (other streams or threads)
+ * race. */
+#define BH_NOALLOC_MAX_VIEWS 512
+bh_status bh_render_batch_noalloc(bh_ctx* ctx, const bh_tables* t, const bh_view* views,
+                                  int32_t n, float* const* outs_dev, void* hip_stream);
+
 /* Tile configuration of the render kernels (the autotuner chooses among these). */
 typedef struct {
   int32_t tile_w, tile_h;  /* pixels per workgroup tile (multiples of 8)                  */

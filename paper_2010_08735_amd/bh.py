@@ -28,7 +28,7 @@ EXPORTS = [
     "bh_bloom_create", "bh_bloom_apply", "bh_bloom_release", "bh_bloom_apply_display",
     "bh_tonemap",
     "bh_build_stars", "bh_stars_download", "bh_release_stars",
-    "bh_render", "bh_render_march", "bh_render_batch",
+    "bh_render", "bh_render_march", "bh_render_batch", "bh_render_batch_noalloc",
     "bh_tile_config_count", "bh_tile_config_get",
     "bh_set_tile_config", "bh_set_batch_form", "bh_autotune",
     "bh_serve_start", "bh_submit", "bh_poll", "bh_ticket_image", "bh_ticket_free",
@@ -104,6 +104,7 @@ def lib():
             "bh_release_stars": ([vp], i32),
             "bh_render": ([vp, vp, C.POINTER(View), vp, vp, vp], i32),
             "bh_render_batch": ([vp, vp, C.POINTER(View), i32, C.POINTER(vp), vp], i32),
+            "bh_render_batch_noalloc": ([vp, vp, C.POINTER(View), i32, C.POINTER(vp), vp], i32),
             "bh_set_batch_form": ([vp, i32], i32),
             "bh_tile_config_count": ([], i32),
             "bh_tile_config_get": ([i32, C.POINTER(TileConfig)], i32),
@@ -224,6 +225,13 @@ def bh_render_batch(ctx, tables, views, out_ptrs, stream=None) -> None:
     arr = (View * n)(*views)
     outs = (C.c_void_p * n)(*out_ptrs)
     _check(lib().bh_render_batch(ctx, tables, arr, n, outs, stream))
+
+
+def bh_render_batch_noalloc(ctx, tables, views, out_ptrs, stream=None) -> None:
+    n = len(views)
+    arr = (View * n)(*views)
+    outs = (C.c_void_p * n)(*out_ptrs)
+    _check(lib().bh_render_batch_noalloc(ctx, tables, arr, n, outs, stream))
 
 
 def bh_set_batch_form(ctx, persistent: int) -> None:

@@ -61,6 +61,7 @@ hipError_t launch_render_count(const ViewDev& v, const TablesDev& T, const LutDe
                                hipStream_t s);
 int tile_config_count();
 void tile_config(int i, int* tw, int* th, int* waves, int* ppt);
+hipError_t scratch_address(void** p);
 }  // namespace bh
 
 using namespace bh;
@@ -175,6 +176,10 @@ struct bh_ctx {
   Staging b_stage[2];
   int b_next_stage = 0;
   hipEvent_t b_last = nullptr;  // completion of the last batch that used b_views/b_runs
+  // allocation-free batched launches: the device address of the library's scratch array on
+  // this device, and pinned staging for its records (set up by bh_create)
+  void* scratch = nullptr;
+  Staging na_stage;
   struct GraphEntry {
     hipGraphExec_t exec;
     hipStream_t stream;
@@ -234,6 +239,32 @@ static bh_status ensure_staging(Staging& s, size_t bytes) {
 
 // ---- context -------------------------------------------------------------------------------
 
+// Device address of the scratch array of the allocation-free batched launch, looked up once
+// per device (with that device current) and kept for the life of the process.
+static std::mutex g_scratch_mu;
+static std::map<int, void*> g_scratch;
+
+// Host records staged for one allocation-free launch: views, tile runs, launch order.
+static size_t noalloc_staging_bytes() {
+  return (size_t)BH_NOALLOC_MAX_VIEWS * (sizeof(ViewDev) + sizeof(TileRun) + sizeof(int));
+}
+
+static bh_status noalloc_setup(bh_ctx* c) {
+  {
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    auto it = g_scratch.find(c->device);
+    if (it == g_scratch.end()) {
+      void* p = nullptr;
+      hipError_t e = scratch_address(&p);
+      if (e != hipSuccess || !p)
+        return fail(BH_EDEVICE, std::string("scratch address: ") + hipGetErrorString(e));
+      it = g_scratch.emplace(c->device, p).first;
+    }
+    c->scratch = it->second;
+  }
+  return ensure_staging(c->na_stage, noalloc_staging_bytes());
+}
+
 extern "C" bh_status bh_create(int device, uint64_t budget, bh_ctx** out) {
   if (!out) return fail(BH_EINVAL, "out is NULL");
   int n = 0;
@@ -255,8 +286,12 @@ extern "C" bh_status bh_create(int device, uint64_t budget, bh_ctx** out) {
   } else {
     st = fail(BH_EDEVICE, std::string("band table: ") + hipGetErrorString(e));
   }
+  if (!st) st = noalloc_setup(c.get());
   if (st) {
     dev_free(c.get(), c->lut, sizeof(float4) * c->lut_n);
+    dev_free(c.get(), c->b_counter, c->b_counter ? sizeof(int) * 64 : 0);
+    if (c->na_stage.host) (void)hipHostFree(c->na_stage.host);
+    if (c->na_stage.done) (void)hipEventDestroy(c->na_stage.done);
     return st;
   }
   *out = c.release();
@@ -306,6 +341,8 @@ extern "C" void bh_destroy(bh_ctx* c) {
     if (s.host) (void)hipHostFree(s.host);
     if (s.done) (void)hipEventDestroy(s.done);
   }
+  if (c->na_stage.host) (void)hipHostFree(c->na_stage.host);
+  if (c->na_stage.done) (void)hipEventDestroy(c->na_stage.done);
   delete c;
 }
 
@@ -1109,6 +1146,60 @@ extern "C" bh_status bh_render_batch(bh_ctx* c, const bh_tables* t, const bh_vie
                      c->b_views, c->b_runs, c->b_counter, stg, s, true);
   if (st) return st;
   HIPCHK(hipEventRecord(c->b_last, s));
+  return BH_OK;
+}
+
+// The allocation-free form of bh_render_batch: records in the library's scratch array,
+// staged through the context's pinned buffer, kernels launched directly.  Calls no device
+// or pinned allocation (the scratch address and the staging buffer come from bh_create).
+extern "C" bh_status bh_render_batch_noalloc(bh_ctx* c, const bh_tables* t, const bh_view* views,
+                                             int32_t n, float* const* outs, void* stream) {
+  if (!c || !t || !views || !outs || n < 1) return fail(BH_EINVAL, "bad batch arguments");
+  if (n > BH_NOALLOC_MAX_VIEWS)
+    return fail(BH_EINVAL, "at most " + std::to_string(BH_NOALLOC_MAX_VIEWS) + " views per call");
+  HIPCHK(hipSetDevice(c->device));
+  std::lock_guard<std::mutex> g(c->mu);
+  Staging& stg = c->na_stage;
+  // the previous call's upload out of the staging buffer must have happened
+  if (stg.used) HIPCHK(hipEventSynchronize(stg.done));
+  ViewDev* hv = (ViewDev*)stg.host;
+  TileRun* hr = (TileRun*)(hv + BH_NOALLOC_MAX_VIEWS);
+  int* order = (int*)(hr + BH_NOALLOC_MAX_VIEWS);
+  for (int i = 0; i < n; ++i) {
+    bh_status st = make_view(&views[i], outs[i], nullptr, &hv[i]);
+    if (st) return fail(st, "view " + std::to_string(i) + ": " + g_err);
+  }
+  const int cfg = c->tile_cfg;
+  int tw, th, waves, ppt;
+  tile_config(cfg, &tw, &th, &waves, &ppt);
+  // largest views first (ties by index, as bh_render_batch orders them)
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::sort(order, order + n, [&](int a, int b) {
+    const int64_t pa = (int64_t)views[a].width * views[a].height;
+    const int64_t pb = (int64_t)views[b].width * views[b].height;
+    return pa != pb ? pa > pb : a < b;
+  });
+  int64_t ntiles = 0;
+  for (int k = 0; k < n; ++k) {
+    const int i = order[k];
+    const int tx = (views[i].width + tw - 1) / tw, ty = (views[i].height + th - 1) / th;
+    hr[k] = TileRun{i, 0, (int)ntiles, tx};
+    ntiles += (int64_t)tx * ty;
+    if (ntiles * tw * th > kMaxElems * 2 - 1)
+      return fail(BH_EINVAL, "batch too large: more than 2^32 - 1 pixels in its tiles");
+  }
+  hipStream_t s = (hipStream_t)stream;
+  int* dcounter = (int*)c->scratch;
+  ViewDev* dviews = (ViewDev*)((char*)c->scratch + 256);
+  TileRun* druns = (TileRun*)(dviews + BH_NOALLOC_MAX_VIEWS);
+  HIPCHK(hipMemcpyAsync(dviews, hv, sizeof(ViewDev) * n, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(druns, hr, sizeof(TileRun) * n, hipMemcpyHostToDevice, s));
+  HIPCHK(hipEventRecord(stg.done, s));
+  stg.used = true;
+  int anim = 0;
+  for (int i = 0; i < n; ++i) anim |= hv[i].density_mode != 0;
+  HIPCHK(launch_render_batch(cfg, c->persistent, anim, dviews, druns, n, (int)ntiles, dcounter,
+                             tables_dev(t), lut_dev(c), batch_grid(c, cfg, ntiles), s));
   return BH_OK;
 }
 

@@ -862,6 +862,25 @@ __global__ void __launch_bounds__(256)
                        __uint_as_float(t.bits));
 }
 
+// ---- scratch of the allocation-free batched launch -------------------------------------------
+// Device memory of bh_render_batch_noalloc: the persistent form's claim counter (first 256
+// bytes), then up to kNoAllocViews view records and as many tile runs.  A file-scope device
+// array: each GPU the library runs on holds its own copy until the process ends, and every
+// call on that GPU shares it (it keeps the last call's contents; the counter is reset by a
+// kernel before each persistent launch).  In host code `scratch` only names the symbol: its
+// device address comes from scratch_address(), once per device.
+constexpr int kNoAllocViews = BH_NOALLOC_MAX_VIEWS;
+constexpr size_t kNoAllocHead = 256;
+constexpr size_t kNoAllocBytes =
+    kNoAllocHead + (size_t)kNoAllocViews * (sizeof(ViewDev) + sizeof(TileRun));
+static_assert(sizeof(ViewDev) % 16 == 0, "view records keep the tile runs 16-byte aligned");
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+// Address of `scratch` on the current device (call with that device current).
+hipError_t scratch_address(void** p) {
+  return hipGetSymbolAddress(p, HIP_SYMBOL(scratch));
+}
+
 // ---- host-side launchers ------------------------------------------------------------------
 
 struct TileEntry {
