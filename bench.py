@@ -26,10 +26,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# MI355X: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz.  One FP32 FMA per lane per clock gives
-# 256 * 64 * 2 * 2.4e9 = 78.6 TFLOP/s; the published 157.3 TFLOP/s needs packed-FP32
-# instructions (two FMAs per lane), which this build does not emit.  VALU issue reference:
-# one wave64 instruction per CU per clock, 614.4 G/s in all.
+# MI355X: 157.3 TFLOP/s published FP32 vector peak (packed FP32, two FMAs per lane); one
+# FP32 FMA per lane per clock on 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz gives 78.6 TFLOP/s,
+# the rate without packed-FP32 instructions, which this build does not emit.  VALU issue
+# reference: one wave64 instruction per CU per clock, 614.4 G/s in all.
 FP32_VECTOR_PEAK_TFLOPS = 78.6
 FP32_PACKED_PEAK_TFLOPS = 157.3
 VALU_ISSUE_REF_G = 256 * 2.4
@@ -352,7 +352,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2000)
     ap.add_argument("--legs", default="plain,anim,march,bloom,batch,serve,cpu",
                     help="comma list of plain, anim, march, bloom, batch, serve, cpu")
-    ap.add_argument("--serve-seconds", type=float, default=5.0)
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="seconds of the Poisson arrival stream replayed by the serve leg")
     ap.add_argument("--serve-tiles", type=int, default=262144,
                     help="most tiles (of the serving tile configuration) in one serving launch")
     ap.add_argument("--serve-inflight", type=int, default=6,
@@ -384,6 +385,15 @@ def main():
     W, H = sv.width, sv.height
     log("tables %.3f s, star map %.3f s" % (t_tab, t_star))
 
+    # measurement passes of the roofline, before the timed leg: the footprint counting pass
+    # (distinct star-map texels visited, bytes requested through the caches) and the L2
+    # read-bandwidth probe.  (They also leave the card's clocks up, as a stream of frames
+    # would: after host-side set-up the first frames otherwise time a card still ramping up.)
+    scratch = torch.empty((H, W, 4), dtype=torch.float32, device="cuda")
+    texels, req = bh.bh_footprint_texels(ctx, tables, view, scratch.data_ptr())
+    bw_l2 = bh.bh_probe_l2_read(ctx, 2 << 20, 20)
+    del scratch
+
     wall, kms, out = plain_leg(bh, ctx, tables, view, args.steps, args.warmup)
     img = out.cpu().numpy()
     assert np.isfinite(img).all(), "non-finite pixels"
@@ -392,49 +402,57 @@ def main():
     kernel_ms = float(kms)
     log("plain: %.4f ms/frame wall, kernel %.4f ms (events), %.0f Mpx/s" % (ms_step, kernel_ms, mpx))
 
-    # roofline of the render kernel.  HBM side: algorithmic bytes per launch (image + the
-    # distinct occupied star texels the footprints read + tables), counted live.  ALU side
-    # (the bound the counters show): FP32 FLOPs per pixel and VALU instructions per wave from
-    # the committed rocprofv3 summary times the pixels / waves of one launch.  All over the
-    # live event-timed kernel time.
-    texels = bh.bh_footprint_texels(ctx, tables, view, out.data_ptr())
+    # roofline of the render kernel: t_roof = max(B_HBM / 8 TB/s, B_L2 / BW_L2) against the
+    # live event-timed kernel duration.  B_HBM: the bytes one frame must move at least (the
+    # RGBA32F image, 8 B per distinct star-map texel the footprints visit, the tables and the
+    # band table, each once).  B_L2: the bytes every pixel requests through the caches
+    # (table and band-table fetches, occupancy words, texels, level records, the image), both
+    # counted by the counting pass on this frame; BW_L2 from the probe.  The vector-ALU view
+    # (FLOPs and instruction issue from the committed rocprofv3 counters, if they were taken
+    # on the current kernel sources) is reported beside it: the kernel is bound by VALU issue.
+    t_k = kernel_ms * 1e-3
     bytes_out = 16 * W * H
     bytes_tex = 8 * texels
     bytes_tab = 4 * (512 * 512 + 64 * 32) + 16 * 4096
     alg = bytes_out + bytes_tex + bytes_tab
-    hbm_gbs = alg / (kernel_ms * 1e-3) / 1e9
-    hbm = {"achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": hbm_gbs / HBM_PEAK_GBS, "algorithmic_bytes": alg, "bytes_image": bytes_out,
+    t_hbm = alg / (HBM_PEAK_GBS * 1e9)
+    t_l2 = req / bw_l2
+    t_roof = max(t_hbm, t_l2)
+    hbm = {"achieved": alg / t_k / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": t_hbm / t_k, "algorithmic_bytes": alg, "bytes_image": bytes_out,
            "bytes_star_texels": bytes_tex, "star_texels_touched": texels,
            "bytes_tables_lut": bytes_tab}
+    l2 = {"achieved": req / t_k / 1e9, "peak": bw_l2 / 1e9, "unit": "GB/s", "frac": t_l2 / t_k,
+          "requested_bytes": req, "bytes_per_pixel": req / (W * H),
+          "probe": "bh_probe_l2_read: streaming 16-byte reads of a 2 MiB buffer held in L2"}
     prof = kernel_profile()
+    roof = {"bound": "l2" if t_l2 > t_hbm else "hbm",
+            "achieved": (l2 if t_l2 > t_hbm else hbm)["achieved"],
+            "peak": (l2 if t_l2 > t_hbm else hbm)["peak"], "unit": "GB/s",
+            "frac": t_roof / t_k, "t_roof_us": 1e6 * t_roof, "kernel_us": 1e6 * t_k,
+            "traffic": prof["fetch_bytes"] + prof["write_bytes"] if prof else None,
+            "kernel": "k_render<16,16,1,false>", "kernel_ms": kernel_ms, "hbm": hbm, "l2": l2}
     if prof is not None:
         flops = prof["fp32_flops_per_pixel"] * W * H
-        tf = flops / (kernel_ms * 1e-3) / 1e12
+        tf = flops / t_k / 1e12
         # VALU issue: instructions per 8x8-pixel wave (counters) x waves of one launch
         winst = prof["valu_insts_per_wave"] * math.ceil(W / 8) * math.ceil(H / 8)
-        gi = winst / (kernel_ms * 1e-3) / 1e9
-        roof = {"bound": "alu", "achieved": tf, "peak": FP32_VECTOR_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": tf / FP32_VECTOR_PEAK_TFLOPS,
-                "traffic": prof["fetch_bytes"] + prof["write_bytes"],
-                "kernel": "k_render<16,16,1,false>", "kernel_ms": kernel_ms,
-                "flops_per_pixel": prof["fp32_flops_per_pixel"],
-                "frac_of_packed_fp32_peak": tf / FP32_PACKED_PEAK_TFLOPS,
-                # issue rate beside the FLOP rate; one wave64 VALU instruction per CU per
-                # clock is a reference, not a ceiling (this kernel exceeds it slightly, a
-                # stream of independent FMAs reaches 0.92 of it), so no fraction is claimed
-                "valu_issue": {"achieved": gi, "unit": "G wave64-instructions/s",
-                               "per_cu_per_clock_at_2_4_ghz": gi / VALU_ISSUE_REF_G,
-                               "insts_per_wave": prof["valu_insts_per_wave"]},
-                "valu_busy_pct": prof["valu_busy_pct"], "l2_hit_pct": prof["l2_hit_pct"],
-                "hbm": hbm}
+        gi = winst / t_k / 1e9
+        roof["alu"] = {"achieved": tf, "peak": FP32_PACKED_PEAK_TFLOPS, "unit": "TFLOP/s",
+                       "frac": tf / FP32_PACKED_PEAK_TFLOPS,
+                       "frac_of_non_packed_fp32": tf / FP32_VECTOR_PEAK_TFLOPS,
+                       "flops_per_pixel": prof["fp32_flops_per_pixel"],
+                       "valu_issue": {"achieved": gi, "unit": "G wave64-instructions/s",
+                                      "per_cu_per_clock_at_2_4_ghz": gi / VALU_ISSUE_REF_G,
+                                      "insts_per_wave": prof["valu_insts_per_wave"]},
+                       "valu_busy_pct": prof["valu_busy_pct"], "l2_hit_pct": prof["l2_hit_pct"]}
     else:
-        roof = {"bound": "hbm", "achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": hbm_gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "k_render<16,16,1,false>",
-                "kernel_ms": kernel_ms, "note": "counters not taken on the current kernel",
-                "hbm": hbm}
-    log("roofline: %s %.2f %s (frac %.4f); HBM algorithmic %.1f MB, %.0f GB/s"
-        % (roof["bound"], roof["achieved"], roof["unit"], roof["frac"], alg / 1e6, hbm_gbs))
+        roof["alu"] = None
+        roof["note"] = "counters not taken on the current kernel sources: traffic and alu unset"
+    log("roofline: %s frac %.3f (t_roof %.2f us: HBM %.2f us, L2 %.2f us; kernel %.2f us); "
+        "L2 probe %.0f GB/s, %.0f B/px requested"
+        % (roof["bound"], roof["frac"], 1e6 * t_roof, 1e6 * t_hbm, 1e6 * t_l2, 1e6 * t_k,
+           bw_l2 / 1e9, req / (W * H)))
 
     extra = {}
     if "anim" in legs:

@@ -345,9 +345,17 @@ bh_status bh_march_rays(bh_ctx* ctx, const float* rays_dev, int64_t n, int32_t m
                         float* out_dev, void* hip_stream);
 /* Measurement: render v once (into out_rgba_dev) with a variant of the render kernel that
  * marks every star-map texel the footprints visit, and return how many distinct texels were
- * visited (the star-map bytes one frame must read at least once).  Blocking. */
+ * visited (the star-map bytes one frame must read at least once) and, if req_bytes is not
+ * NULL, the bytes all pixels request through the caches (table and band-table fetches,
+ * occupancy words, texels, level records, image and AOV stores).  Blocking. */
 bh_status bh_footprint_texels(bh_ctx* ctx, const bh_tables* t, const bh_view* v,
-                              float* out_rgba_dev, uint64_t* texels);
+                              float* out_rgba_dev, uint64_t* texels, uint64_t* req_bytes);
+/* Measurement: the read bandwidth of data held in the L2 caches.  Every workgroup (8 per
+ * CU) streams coalesced 16-byte reads over 256 KiB of a zero-filled device buffer of
+ * window_bytes (a power of two in [4 KiB, 4 MiB], so that it fits one XCD's L2), wrapping
+ * around; after three untimed passes, bytes_per_s = bytes read / time of `reps` launches.
+ * Blocking. */
+bh_status bh_probe_l2_read(bh_ctx* ctx, int64_t window_bytes, int32_t reps, double* bytes_per_s);
 /* Blackbody band table: n entries of 4 floats [log2 L_R, log2 L_G, log2 L_B,
  * log2 (L_R + L_G + L_B)] at log2 T = x0 + k dx.  Blocking. */
 bh_status bh_band_table_info(const bh_ctx* ctx, int32_t* n, float* x0, float* dx);

@@ -33,7 +33,7 @@ EXPORTS = [
     "bh_set_tile_config", "bh_set_batch_form", "bh_autotune",
     "bh_serve_start", "bh_submit", "bh_poll", "bh_ticket_image", "bh_ticket_free",
     "bh_serve_drain",
-    "bh_trace_rays", "bh_trace_rays_timed", "bh_march_rays", "bh_footprint_texels", "bh_band_table_info", "bh_band_table_download", "bh_band_eval",
+    "bh_trace_rays", "bh_trace_rays_timed", "bh_march_rays", "bh_footprint_texels", "bh_probe_l2_read", "bh_band_table_info", "bh_band_table_download", "bh_band_eval",
 ]
 
 
@@ -126,7 +126,8 @@ def lib():
             "bh_bloom_apply_display": ([vp, C.POINTER(C.c_float), C.c_float, vp, vp, vp], i32),
             "bh_tonemap": ([vp, vp, vp, i32, i32, C.c_float, vp], i32),
             "bh_render_march": ([vp, C.POINTER(View), i32, vp, vp, vp], i32),
-            "bh_footprint_texels": ([vp, vp, C.POINTER(View), vp, C.POINTER(u64)], i32),
+            "bh_footprint_texels": ([vp, vp, C.POINTER(View), vp, C.POINTER(u64), C.POINTER(u64)], i32),
+            "bh_probe_l2_read": ([vp, i64, i32, C.POINTER(C.c_double)], i32),
             "bh_band_table_info": ([vp, C.POINTER(i32), C.POINTER(C.c_float),
                                     C.POINTER(C.c_float)], i32),
             "bh_band_table_download": ([vp, vp], i32),
@@ -338,10 +339,18 @@ def bh_march_rays(ctx, rays_ptr, n, max_steps, out_ptr, stream=None) -> None:
     _check(lib().bh_march_rays(ctx, rays_ptr, n, max_steps, out_ptr, stream))
 
 
-def bh_footprint_texels(ctx, tables, view: View, out_ptr) -> int:
-    n = C.c_uint64()
-    _check(lib().bh_footprint_texels(ctx, tables, C.byref(view), out_ptr, C.byref(n)))
-    return n.value
+def bh_footprint_texels(ctx, tables, view: View, out_ptr):
+    """(distinct star-map texels the footprints visit, bytes all pixels request)"""
+    n, b = C.c_uint64(), C.c_uint64()
+    _check(lib().bh_footprint_texels(ctx, tables, C.byref(view), out_ptr, C.byref(n), C.byref(b)))
+    return n.value, b.value
+
+
+def bh_probe_l2_read(ctx, window_bytes=2 << 20, reps=20) -> float:
+    """bytes per second of streaming reads of a buffer held in L2"""
+    r = C.c_double()
+    _check(lib().bh_probe_l2_read(ctx, window_bytes, reps, C.byref(r)))
+    return r.value
 
 
 def bh_band_table_info(ctx):

@@ -58,10 +58,12 @@ hipError_t launch_march_rays(const float* rays, int64_t n, int nsteps, float h, 
                              hipStream_t s);
 hipError_t launch_render_count(const ViewDev& v, const TablesDev& T, const LutDev& L,
                                uint32_t* touched, int64_t words, unsigned long long* total,
-                               hipStream_t s);
+                               unsigned long long* l2_bytes, hipStream_t s);
 int tile_config_count();
 void tile_config(int i, int* tw, int* th, int* waves, int* ppt);
 hipError_t scratch_address(void** p);
+hipError_t launch_l2_read(const float4* buf, int64_t n4, int per_wg, int grid, float* sink,
+                          hipStream_t s);
 }  // namespace bh
 
 using namespace bh;
@@ -1286,7 +1288,7 @@ extern "C" bh_status bh_trace_rays_timed(bh_ctx* c, const bh_tables* t, const fl
 }
 
 extern "C" bh_status bh_footprint_texels(bh_ctx* c, const bh_tables* t, const bh_view* v,
-                                         float* out, uint64_t* texels) {
+                                         float* out, uint64_t* texels, uint64_t* req_bytes) {
   if (!c || !t || !texels) return fail(BH_EINVAL, "NULL argument");
   if (!v || !v->stars) return fail(BH_EINVAL, "view without a star map");
   ViewDev vd;
@@ -1298,18 +1300,54 @@ extern "C" bh_status bh_footprint_texels(bh_ctx* c, const bh_tables* t, const bh
   for (int l = 0; l < s->levels; ++l) total += 6ull * (s->n0 >> l) * (s->n0 >> l);
   int64_t words = (int64_t)((total + 31) / 32);
   uint32_t* bits = nullptr;
-  unsigned long long* cnt = nullptr;
+  unsigned long long* cnt = nullptr;  // [0] distinct texels, [1] requested bytes
   HIPCHK(hipMalloc(&bits, sizeof(uint32_t) * words));
-  hipError_t e = hipMalloc(&cnt, sizeof(unsigned long long));
+  hipError_t e = hipMalloc(&cnt, 2 * sizeof(unsigned long long));
   if (e == hipSuccess) e = hipMemset(bits, 0, sizeof(uint32_t) * words);
-  if (e == hipSuccess) e = hipMemset(cnt, 0, sizeof(unsigned long long));
-  if (e == hipSuccess) e = launch_render_count(vd, tables_dev(t), lut_dev(c), bits, words, cnt, nullptr);
-  unsigned long long h = 0;
-  if (e == hipSuccess) e = hipMemcpy(&h, cnt, sizeof(h), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemset(cnt, 0, 2 * sizeof(unsigned long long));
+  if (e == hipSuccess)
+    e = launch_render_count(vd, tables_dev(t), lut_dev(c), bits, words, cnt, cnt + 1, nullptr);
+  unsigned long long h[2] = {0, 0};
+  if (e == hipSuccess) e = hipMemcpy(h, cnt, sizeof(h), hipMemcpyDeviceToHost);
   (void)hipFree(bits);
   if (cnt) (void)hipFree(cnt);
   if (e != hipSuccess) return fail(BH_EDEVICE, std::string("footprint count: ") + hipGetErrorString(e));
-  *texels = h;
+  *texels = h[0];
+  if (req_bytes) *req_bytes = h[1];
+  return BH_OK;
+}
+
+extern "C" bh_status bh_probe_l2_read(bh_ctx* c, int64_t window_bytes, int32_t reps,
+                                      double* bytes_per_s) {
+  if (!c || !bytes_per_s || reps < 1 || window_bytes < 4096 || window_bytes > (4 << 20) ||
+      (window_bytes & (window_bytes - 1)))
+    return fail(BH_EINVAL, "window_bytes must be a power of two in [4 KiB, 4 MiB], reps >= 1");
+  HIPCHK(hipSetDevice(c->device));
+  const int64_t n4 = window_bytes / 16;
+  const int per_wg = 16384;          // 256 KiB per workgroup
+  const int grid = c->cus * 8;       // 8 workgroups of 4 waves per CU
+  float4* buf = nullptr;
+  float* sink = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipMalloc(&buf, window_bytes);
+  if (e == hipSuccess) e = hipMalloc(&sink, sizeof(float) * grid);
+  if (e == hipSuccess) e = hipMemset(buf, 0, window_bytes);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  for (int w = 0; w < 3 && e == hipSuccess; ++w)  // bring the window into every L2
+    e = launch_l2_read(buf, n4, per_wg, grid, sink, nullptr);
+  if (e == hipSuccess) e = hipEventRecord(e0, nullptr);
+  for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_l2_read(buf, n4, per_wg, grid, sink, nullptr);
+  if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.0f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (buf) (void)hipFree(buf);
+  if (sink) (void)hipFree(sink);
+  if (e != hipSuccess) return fail(BH_EDEVICE, std::string("L2 probe: ") + hipGetErrorString(e));
+  *bytes_per_s = 16.0 * per_wg * (double)grid * reps / (ms * 1e-3);
   return BH_OK;
 }
 

@@ -47,13 +47,22 @@ struct Footprint {
   float one;             // 1, not known to the compiler: p_u + c stays one mixed-precision FMA
 };
 
+// Buffers of the measurement variant (COUNT): one bit per star-map texel the footprints
+// visit, and the total of the bytes every pixel requests through the caches (table and band
+// table fetches, occupancy words, texels, level records, image and AOV stores).
+struct CountBufs {
+  uint32_t* touched;
+  unsigned long long* l2_bytes;
+};
+
 template <bool FP16, bool COUNT>
-__device__ __forceinline__ void gather(const void* tex, const Footprint& F, uint32_t* touched,
-                                       float& A, float& B) {
+__device__ __forceinline__ void gather(const void* tex, const Footprint& F, const CountBufs* cnt,
+                                       uint32_t& req, float& A, float& B) {
   uint32_t w0 = 0, w1 = 0, hi = 0;  // lo = w0 + 2^32 w1
   uint32_t off = 0;
   for (int r = 0; r <= F.ny; ++r, off += (uint32_t)F.wpr) {
     const uint32_t* orow = F.occ + off;
+    if (COUNT) req += 8;  // two occupancy words
     // the row's 9 columns from bit x0 & 31 of two consecutive words (a funnel shift)
     uint32_t b = __builtin_amdgcn_alignbit(orow[1], orow[0], (uint32_t)F.sh) & F.span;
     if (r < 3) {
@@ -79,7 +88,8 @@ __device__ __forceinline__ void gather(const void* tex, const Footprint& F, uint
     uint32_t t = (uint32_t)(__mul24(r, nLm9) + idx);  // r nL + c, nL < 2^23
     if (COUNT) {
       uint32_t ta = F.texel0 + t;
-      atomicOr(&touched[ta >> 5], 1u << (ta & 31));
+      atomicOr(&cnt->touched[ta >> 5], 1u << (ta & 31));
+      req += FP16 ? 8 : 16;
     }
     const float fc = (float)c, fr = (float)r;
     if (FP16) {
@@ -125,6 +135,7 @@ struct TraceOut {
   int mcr[2];          // crossing k lies at beam-plane angle alpha + mcr[k] pi (TIMED only)
   int ncross;
   unsigned bits;
+  uint32_t req;        // bytes the table fetches request (read by the measurement variant only)
 };
 
 // singular part of the coordinate time along a ray: t = tau + S(u) + const
@@ -146,6 +157,7 @@ __device__ __forceinline__ TraceOut trace_ray(const TablesDev& T, float u, float
   o.mcr[0] = o.mcr[1] = 0;
   o.bits = 0;
   o.dprime = 0.0f;
+  o.req = 0;
   float udot = -u * cotd;
   float e2 = udot * udot + u * u * (1.0f - u);
   float e = fsqrt(e2);
@@ -158,9 +170,11 @@ __device__ __forceinline__ TraceOut trace_ray(const TablesDev& T, float u, float
   bool bound = e2 < kMu;
   float ua = bound ? apsis_f(e2) : 0.0f;
   float Dl = lookup_D(T, T.D, e2, u, ua, udot);
+  o.req += 16;  // a bilinear fetch reads two pairs of adjacent floats
   float Da = 0.0f, phia = __builtin_inff();
   if (bound) {
     Da = lookup_D_apsis(T, T.D, e2);
+    o.req += 8;
     phia = Da + 0.5f * kPi;
   }
   float ie = 0.0f, t_cam = 0.0f, t_a = 0.0f;
@@ -173,6 +187,7 @@ __device__ __forceinline__ TraceOut trace_ray(const TablesDev& T, float u, float
   float m0 = floorf(phi * (1.0f / kPi));
   float phi0 = phi - kPi * m0;
   float u0 = lookup_U(T, T.U, e2, e, phi0);
+  o.req += 16;
   int sg = (u0 > u) - (u0 < u);
   if (phi0 < phia && u_oc <= u0 && u0 <= u_ic && sg == s) {
     o.ucr[0] = u0;
@@ -188,6 +203,7 @@ __device__ __forceinline__ TraceOut trace_ray(const TablesDev& T, float u, float
     float m1 = floorf(phi * (1.0f / kPi));
     float phi1 = phi - kPi * m1;
     float u1 = lookup_U(T, T.U, e2, e, phi1);
+    o.req += 16;
     if (phi1 < phia && u_oc <= u1 && u1 <= u_ic) {
       float t1 = 0.0f;
       if (TIMED)
@@ -236,6 +252,7 @@ __device__ __forceinline__ TraceOut march_ray(float u, float alpha, float cotd, 
   o.mcr[0] = o.mcr[1] = 0;
   o.bits = 0;
   o.dprime = 0.0f;
+  o.req = 0;
   float w = -u * cotd;
   o.e = fsqrt(w * w + u * u * (1.0f - u));
   if (fabsf(cotd) >= 1e6f) {
@@ -382,13 +399,14 @@ __device__ __forceinline__ float disc_density(const ViewDev& v, float ht, float 
 }
 
 // One pixel; every lane of the wave must call this together (quad exchanges).
-// COUNT: also mark every star-map texel the footprint visits in `touched` (one bit per
-// texel, measurement only).  ANIM: views may have a particle disc (retarded times).
+// COUNT: also mark every star-map texel the footprint visits and add up the bytes the pixel
+// requests (measurement only, see CountBufs).  ANIM: views may have a particle disc
+// (retarded times).
 // MARCH: ray marching (march_ray) in place of TraceRay; no tables are read.
 template <bool COUNT, bool ANIM = false, bool MARCH = false>
 __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& T,
                                              const LutDev& L, int px, int py,
-                                             uint32_t* touched) {
+                                             const CountBufs* cnt) {
 
   // ---- beam initialisation (Section 3.2)
   float qw = (float)px + 0.5f - v.half_w;
@@ -471,6 +489,7 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
     tr = trace_ray<ANIM>(T, v.u_c, delta, alpha, cotd, u_ic, u_oc);
   bits |= tr.bits;
   const bool captured = (tr.bits & BH_CAPTURED_BIT) != 0;
+  uint32_t req = tr.req;  // bytes requested (COUNT only)
 
   // ---- disc (Sections 3.3.3, 3.4.2), front to back
   float cr = 0.0f, cg = 0.0f, cb = 0.0f, trans = 1.0f;
@@ -490,6 +509,7 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
       float om = fsqrt(0.5f * uk * uk * uk);
       float D = dcam * ikt * fdiv(1.0f, 1.0f + om * zeta * ie);
       float4 Lb = band_lookup(L, D * Tp);
+      if (COUNT) req += 32;  // two band-table entries
       float rk = v.rho;
       if (anim) {
         float tk = k == 0 ? tr.tret[0] : tr.tret[1];
@@ -594,10 +614,11 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
       F.Hr = i11 * tw;
       F.H0 = fmaf(i10, cu, i11 * cv);
       F.one = S.one;
+      if (COUNT) req += 12;  // level offsets and scale
       if (S.fp16)
-        gather<true, COUNT>(S.tex, F, touched, A, B);
+        gather<true, COUNT>(S.tex, F, cnt, req, A, B);
       else
-        gather<false, COUNT>(S.tex, F, touched, A, B);
+        gather<false, COUNT>(S.tex, F, cnt, req, A, B);
       const float iscale = S.scale[Lv];
       A *= iscale;
       B *= S.fp16 ? iscale * 1024.0f : iscale;
@@ -618,6 +639,7 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
       float Tpix = fdiv(B, A);
       float4 Lr = band_lookup(L, dcam * Tpix);
       float4 Ln = band_lookup(L, Tpix);
+      if (COUNT) req += 64;
       float sc = trans * v.k_star * fsqrt(om2) * __builtin_amdgcn_rsqf(omp2) * fdiv(A, Ln.w);
       cr += sc * Lr.x;
       cg += sc * Lr.y;
@@ -625,6 +647,12 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
     }
   }
 
+  if (COUNT) {
+    if (px < v.width && py < v.height) req += v.aov ? 32 : 16;
+    unsigned long long t = req;
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+    if ((threadIdx.x & 63) == 0) atomicAdd(cnt->l2_bytes, t);
+  }
   if (px < v.width && py < v.height) {
     size_t idx = (size_t)py * v.width + px;
     v.out[idx] = make_float4(cr, cg, cb, 1.0f);
@@ -647,7 +675,7 @@ struct TileCfg {
 
 template <int TW, int TH, int PPT, bool COUNT = false, bool ANIM = false, bool MARCH = false>
 __device__ __forceinline__ void render_tile(const ViewDev& v, const TablesDev& T, const LutDev& L,
-                                            int tx0, int ty0, uint32_t* touched = nullptr) {
+                                            int tx0, int ty0, const CountBufs* cnt = nullptr) {
   using C = TileCfg<TW, TH, PPT>;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int q = lane >> 2;
@@ -659,7 +687,7 @@ __device__ __forceinline__ void render_tile(const ViewDev& v, const TablesDev& T
     int px = tx0 + 8 * bx + ox, py = ty0 + 8 * by + oy;
     // skip 8x8 blocks entirely outside the image (uniform per wave)
     if (tx0 + 8 * bx >= v.width || ty0 + 8 * by >= v.height) continue;
-    render_pixel<COUNT, ANIM, MARCH>(v, T, L, px, py, touched);
+    render_pixel<COUNT, ANIM, MARCH>(v, T, L, px, py, cnt);
   }
 }
 
@@ -813,11 +841,10 @@ __global__ void k_reset_counter(int* c) { *c = 0; }
 // Measurement variant of the plain launch (16x16 tiles): marks the star-map texels that
 // the footprints visit.
 __global__ void __launch_bounds__(256)
-    k_render_count(ViewDev v, TablesDev T, LutDev L, int tiles_x, int ntiles,
-                   uint32_t* __restrict__ touched) {
+    k_render_count(ViewDev v, TablesDev T, LutDev L, int tiles_x, int ntiles, CountBufs cnt) {
   int tile = blockIdx.x;
   if (tile >= ntiles) return;
-  render_tile<16, 16, 1, true>(v, T, L, (tile % tiles_x) * 16, (tile / tiles_x) * 16, touched);
+  render_tile<16, 16, 1, true>(v, T, L, (tile % tiles_x) * 16, (tile / tiles_x) * 16, &cnt);
 }
 
 __global__ void k_popcount(const uint32_t* __restrict__ bits, int64_t n,
@@ -960,10 +987,10 @@ hipError_t launch_render_batch(int cfg, int persistent, int anim, const ViewDev*
 
 hipError_t launch_render_count(const ViewDev& v, const TablesDev& T, const LutDev& L,
                                uint32_t* touched, int64_t words, unsigned long long* total,
-                               hipStream_t s) {
+                               unsigned long long* l2_bytes, hipStream_t s) {
   int tiles_x = (v.width + 15) / 16, ntiles = tiles_x * ((v.height + 15) / 16);
   hipLaunchKernelGGL(k_render_count, dim3(ntiles), dim3(256), 0, s, v, T, L, tiles_x, ntiles,
-                     touched);
+                     CountBufs{touched, l2_bytes});
   hipLaunchKernelGGL(k_popcount, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, s, touched,
                      words, total);
   return hipGetLastError();
