@@ -25,7 +25,9 @@ class OrcView(C.Structure):
                 ("disc_T0", C.c_double), ("disc_T_exp", C.c_double),
                 ("disc_opacity", C.c_double), ("k_disc", C.c_double), ("k_star", C.c_double),
                 ("time", C.c_double), ("disc_density", C.c_int32), ("n_particles", C.c_int32),
-                ("particles", C.POINTER(C.c_double))]
+                ("particles", C.POINTER(C.c_double)),
+                ("area", C.POINTER(C.c_double)), ("area_n0", C.c_int32),
+                ("area_exact", C.c_int32), ("k_area", C.c_double)]
 
 
 class OrcRay(C.Structure):
@@ -43,6 +45,8 @@ PIXEL_DTYPE = np.dtype([
     ("x", "<i4"), ("y", "<i4"), ("n_cross", "<i4"), ("branch_bits", "<i4"),
     ("captured", "<i4"), ("star_zeroed", "<i4"), ("degenerate", "<i4"), ("mip_level", "<i4"),
     ("pad0", "<i4"), ("pad1", "<i4"), ("t_ret", "<f8", 2), ("hit_az", "<f8", 2), ("density", "<f8", 2),
+    ("area_rgb", "<f8", 3), ("area_A", "<f8"), ("area_T", "<f8"), ("area_exact_A", "<f8"),
+    ("area_exact_T", "<f8"),
 ])
 
 _lib = None
@@ -109,6 +113,11 @@ def lib():
         L.orc_hermite_first_root.argtypes = [C.c_double] * 5
         L.orc_render_quads_m.argtypes = [C.POINTER(OrcView), dp, C.c_int32, C.c_int32,
                                          C.POINTER(C.c_int32), C.c_int64, C.c_void_p, C.c_int]
+        L.orc_area_texels.restype = C.c_int64
+        L.orc_area_texels.argtypes = [C.c_int32]
+        L.orc_area_build.argtypes = [fp, C.c_int32, dp]
+        L.orc_area_filter.argtypes = [dp, C.c_int32, dp, dp, dp, dp, dp]
+        L.orc_area_exact.argtypes = [dp, C.c_int32, dp, dp, dp, dp, dp]
         L.orc_bloom.argtypes = [dp, C.c_int32, C.c_int32, C.c_int32, dp, dp]
         L.orc_tonemap.argtypes = [dp, C.c_int64, C.c_double, C.c_void_p, dp]
         for f in ("orc_sizeof_pixel", "orc_sizeof_ray", "orc_sizeof_view"):
@@ -298,6 +307,41 @@ def cubemap_level(tex: np.ndarray, n0: int, level: int) -> np.ndarray:
     return tex[off:off + 6 * nl * nl].reshape(6, nl, nl, 4)
 
 
+def area_levels(it: np.ndarray) -> np.ndarray:
+    """FP64 area-map levels (all mip levels concatenated), shape (texels, 2) = (I, I T), from
+    level-0 (I, T) texels shaped (6, n0, n0, 2)."""
+    it = np.ascontiguousarray(it, np.float32)
+    n0 = it.shape[1]
+    out = np.zeros((lib().orc_area_texels(n0), 2), np.float64)
+    if lib().orc_area_build(it.ctypes.data_as(C.POINTER(C.c_float)), n0, _dp(out)):
+        raise ValueError("orc_area_build rejected the map")
+    return out
+
+
+def area_level(levels: np.ndarray, n0: int, level: int) -> np.ndarray:
+    """View of one area-map level as (6, nL, nL, 2)."""
+    off = sum(6 * (n0 >> l) ** 2 for l in range(level))
+    nl = n0 >> level
+    return levels[off:off + 6 * nl * nl].reshape(6, nl, nl, 2)
+
+
+def _area_call(fn, levels, n0, d, dw, dh):
+    a = [np.ascontiguousarray(x, np.float64) for x in (d, dw, dh)]
+    A, B = C.c_double(), C.c_double()
+    fn(_dp(levels), n0, _dp(a[0]), _dp(a[1]), _dp(a[2]), C.byref(A), C.byref(B))
+    return A.value, B.value
+
+
+def area_filter(levels, n0, d, dw, dh):
+    """Anisotropic filter of the footprint d + w dw + h dh, |w|, |h| <= 1/2: (mean I, mean I T)."""
+    return _area_call(lib().orc_area_filter, levels, n0, d, dw, dh)
+
+
+def area_exact(levels, n0, d, dw, dh):
+    """Exact mean of the level-0 map over the same footprint: (mean I, mean I T)."""
+    return _area_call(lib().orc_area_exact, levels, n0, d, dw, dh)
+
+
 def to_orc_view(v) -> OrcView:
     o = OrcView()
     o.r_s = v.r_s
@@ -322,13 +366,21 @@ def to_orc_view(v) -> OrcView:
 
 
 def render_quads(view, quads: np.ndarray, cube: np.ndarray = None, n0: int = 0,
-                 tables: Tables = None, nthreads: int = None, march: int = 0) -> np.ndarray:
+                 tables: Tables = None, nthreads: int = None, march: int = 0,
+                 area: np.ndarray = None, area_n0: int = 0, area_exact: bool = False) -> np.ndarray:
     """Render the 4 pixels of every quad (x0, y0); returns a PIXEL_DTYPE array (4 per quad).
-    march > 0 replaces TraceRay by ray marching with at most that many steps."""
+    march > 0 replaces TraceRay by ray marching with at most that many steps.  area: levels
+    from area_levels (area_exact also fills the exact footprint means)."""
     q = np.ascontiguousarray(quads, np.int32)
     nq = q.shape[0]
     out = np.zeros(4 * nq, PIXEL_DTYPE)
     ov = to_orc_view(view)
+    if area is not None:
+        ov._area = np.ascontiguousarray(area, np.float64)
+        ov.area = _dp(ov._area)
+        ov.area_n0 = area_n0
+        ov.area_exact = 1 if area_exact else 0
+        ov.k_area = getattr(view, "k_area", 1.0)
     if march > 0:
         rc = lib().orc_render_quads_m(C.byref(ov), _dp(cube) if cube is not None else None, n0,
                                       march, q.ctypes.data_as(C.POINTER(C.c_int32)), nq,

@@ -49,6 +49,11 @@ typedef struct {
   int32_t disc_density;
   int32_t n_particles;
   const double* particles;  /* n_particles triples (r_peri, r_apo, phi0) */
+  /* area sources (Section 3.3.2): the map's levels from orc_area_build, or NULL */
+  const double* area;
+  int32_t area_n0;
+  int32_t area_exact;     /* 1: also compute the exact footprint mean (diagnostic) */
+  double k_area;
 } orc_view;
 
 /* Result of tracing one ray in its orbital plane. */
@@ -90,6 +95,10 @@ typedef struct {
   double t_ret[2];        /* retarded time of each crossing (animated disc only) */
   double hit_az[2];       /* disc azimuth of each crossing (animated disc only) */
   double density[2];      /* particle density at each crossing (animated disc only) */
+  double area_rgb[3];     /* received light of the area map (before the disc's
+                             transmittance) */
+  double area_A, area_T;  /* filtered radiance and colour temperature of the footprint */
+  double area_exact_A, area_exact_T;  /* the exact footprint mean (if area_exact) */
 } orc_pixel;
 
 /* ---- geometry of rays (Section 3.3.1) --------------------------------------------- */
@@ -134,6 +143,16 @@ double orc_planck(double lambda, double T);          /* spectral radiance B_lamb
 int64_t orc_cubemap_texels(int32_t n0);              /* texel count over all mip levels */
 int orc_cubemap_build(const float* dirs, const float* inten, const float* temp, int64_t n,
                       int32_t n0, double* texels);   /* texels: orc_cubemap_texels * 4 */
+
+/* ---- area sources (Section 3.3.2 "Emitted light", Section 3.4.1 closing note) -------- */
+int64_t orc_area_texels(int32_t n0);                 /* texel count over all mip levels */
+/* it: level-0 (I, T) per texel, 6 n0^2 pairs; levels: orc_area_texels * 2 (I, I T) */
+int orc_area_build(const float* it, int32_t n0, double* levels);
+/* footprint {d + w dw + h dh : |w|, |h| <= 1/2}: A = mean I, B = mean I T */
+void orc_area_filter(const double* levels, int32_t n0, const double* d, const double* dw,
+                     const double* dh, double* A, double* B);   /* the anisotropic filter */
+void orc_area_exact(const double* levels, int32_t n0, const double* d, const double* dw,
+                    const double* dh, double* A, double* B);    /* the exact mean, level 0 */
 
 /* ---- whole pixels --------------------------------------------------------------------- */
 /* quads: (x0, y0) pairs with even coordinates; out: 4 pixels per quad in the order

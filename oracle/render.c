@@ -45,6 +45,10 @@
  *   star colour_b = k_star (Omega/Omega') A L_b(D_cam T_pix) / sum_b L_b(T_pix), T_pix = B/A
  *   (static stars: k' = [1, 0, 0, 0]).  If any member of the quad is captured the star
  *   term is zero for the whole quad.
+ * Area sources (area.c): the same quad differences give the footprint; the filtered
+ *   (A, B) = mean (I, I T) give area colour_b = k_area A L_b(D_cam T_pix) / sum_b L_b(T_pix),
+ *   without Omega/Omega'; zero for a quad with a captured member, as for stars.  Both sky
+ *   terms are seen through the disc's remaining transmittance.
  */
 #include <math.h>
 #include <pthread.h>
@@ -336,7 +340,34 @@ static void shade_quad(const ctx_t* c, int32_t x0, int32_t y0, orc_pixel* out) {
           p->star_rgb[b] = v->k_star * p->omega_ratio * A * Lr[b] / norm;
       }
     }
-    for (int b = 0; b < 3; ++b) p->rgb[b] = p->disc_rgb[b] + trans * p->star_rgb[b];
+    /* area sources: the footprint mean of the map, one Doppler shift per pixel as for
+       stars, no lensing amplification (Section 3.4.1) */
+    if (v->area && !any_captured) {
+      int mw0 = (m & 2), mw1 = (m & 2) | 1, mh0 = (m & 1), mh1 = (m & 1) | 2;
+      double dw[3], dh[3], A, B;
+      for (int i = 0; i < 3; ++i) {
+        dw[i] = r[mw1].dprime[i] - r[mw0].dprime[i];
+        dh[i] = r[mh1].dprime[i] - r[mh0].dprime[i];
+      }
+      orc_area_filter(v->area, v->area_n0, o->dprime, dw, dh, &A, &B);
+      p->area_A = A;
+      if (A > 0.0) {
+        double Tpix = B / A, Lr[3], Ln[3];
+        p->area_T = Tpix;
+        orc_band_radiance(o->d_cam * Tpix, Lr);
+        orc_band_radiance(Tpix, Ln);
+        double norm = Ln[0] + Ln[1] + Ln[2];
+        if (norm > 0.0)
+          for (int b = 0; b < 3; ++b) p->area_rgb[b] = v->k_area * A * Lr[b] / norm;
+      }
+      if (v->area_exact) {
+        orc_area_exact(v->area, v->area_n0, o->dprime, dw, dh, &A, &B);
+        p->area_exact_A = A;
+        p->area_exact_T = A > 0.0 ? B / A : 0.0;
+      }
+    }
+    for (int b = 0; b < 3; ++b)
+      p->rgb[b] = p->disc_rgb[b] + trans * (p->star_rgb[b] + p->area_rgb[b]);
   }
 }
 

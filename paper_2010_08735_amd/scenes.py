@@ -16,7 +16,14 @@ Input recipes (all RNG draws use numpy's PCG64 ``default_rng(seed)`` in the orde
   the image "up" axis the projection of +z (or +x when the camera looks along z);
 * disc particles (animated disc): mid radius ~ U(r_in + 1, r_out - 1), relative
   half-width of the radial excursion ~ U(0, 0.05), initial phase ~ U(0, 2 pi), each drawn
-  as a whole array in that order; pericentre = mid (1 - w), apocentre = mid (1 + w).
+  as a whole array in that order; pericentre = mid (1 - w), apocentre = mid (1 + w);
+* area-source sky (nebulae): `blobs` Gaussian patches with centre z ~ U(-1, 1), azimuth
+  ~ U(0, 2 pi), angular width sigma ~ U(sigma_lo, sigma_hi) rad, peak radiance
+  10**U(-1, 0), temperature ~ U(3000, 15000) K, each drawn as a whole array in that order,
+  over a floor of radiance 0.02 at 6000 K; texel (face, x, y) of the level-0 map holds
+  the radiance I and the radiance-weighted temperature T at its centre direction (face
+  2k + (d_k < 0), U = d_{(k+1)%3} / |d_k|, V = d_{(k+2)%3} / |d_k|, centre at
+  U = (x + 1/2) 2 / n0 - 1, V = (y + 1/2) 2 / n0 - 1).
 """
 from __future__ import annotations
 
@@ -54,6 +61,7 @@ class View:
     disc_density: int = DENSITY_UNIFORM
     time: float = 0.0
     particles: Optional["ParticleSet"] = None
+    k_area: float = 1.0                 # exposure of an area-source map, when one is given
 
     def pixels(self) -> int:
         return self.width * self.height
@@ -106,6 +114,36 @@ def star_field(n: int, seed: int) -> StarField:
     dirs = np.stack([s * np.cos(az), s * np.sin(az), z], axis=1)
     return StarField(dirs.astype(np.float32), inten.astype(np.float32),
                      temp.astype(np.float32), seed)
+
+
+def area_map(n0: int, seed: int, blobs: int = 24, sigma_lo: float = 0.10,
+             sigma_hi: float = 0.35) -> np.ndarray:
+    """Level-0 texels of an area-source cube map, float32 (6, n0, n0, 2) = (I, T)."""
+    rng = np.random.default_rng(seed)
+    z = rng.uniform(-1.0, 1.0, blobs)
+    az = rng.uniform(0.0, 2.0 * math.pi, blobs)
+    sig = rng.uniform(sigma_lo, sigma_hi, blobs)
+    peak = 10.0 ** rng.uniform(-1.0, 0.0, blobs)
+    temp = rng.uniform(3000.0, 15000.0, blobs)
+    s = np.sqrt(np.maximum(0.0, 1.0 - z * z))
+    centres = np.stack([s * np.cos(az), s * np.sin(az), z], axis=1)
+    c = (np.arange(n0) + 0.5) * (2.0 / n0) - 1.0
+    uu, vv = np.meshgrid(c, c, indexing="xy")          # [y, x]
+    out = np.zeros((6, n0, n0, 2), np.float32)
+    for f in range(6):
+        k, sgn = f // 2, (-1.0 if f % 2 else 1.0)
+        d = np.zeros((n0, n0, 3))
+        d[..., k] = sgn
+        d[..., (k + 1) % 3] = uu
+        d[..., (k + 2) % 3] = vv
+        d /= np.linalg.norm(d, axis=-1, keepdims=True)
+        ang = np.arccos(np.clip(d @ centres.T, -1.0, 1.0))  # (n0, n0, blobs)
+        g = peak * np.exp(-0.5 * (ang / sig) ** 2)
+        I = 0.02 + g.sum(-1)
+        IT = 0.02 * 6000.0 + (g * temp).sum(-1)
+        out[f, ..., 0] = I
+        out[f, ..., 1] = IT / I
+    return out
 
 
 # ----------------------------------------------------------------------------------------

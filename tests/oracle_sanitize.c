@@ -97,6 +97,28 @@ int main(void) {
   if (orc_render_quads_t(&v, cube, N0, D, Dt, dn, U, Ut, ne, nphi, quads, nq, px, 4)) bad = 1;
   FINITE(orc_ellipk(0.5));
 
+  /* area sources: the map's levels, the filter and the exact mean, then whole pixels */
+  float it[6 * 8 * 8 * 2];
+  for (int i = 0; i < 6 * 8 * 8; ++i) {
+    it[2 * i] = 0.1f + (float)(i % 13) * 0.05f;
+    it[2 * i + 1] = 4000.0f + (float)(i % 5) * 500.0f;
+  }
+  double* area = calloc((size_t)orc_area_texels(8) * 2, sizeof(double));
+  if (orc_area_build(it, 8, area)) bad = 1;
+  double dd[3] = {0.3, 0.9, -0.2}, aw[3] = {0.2, 0.0, 0.1}, ah[3] = {0.0, 0.05, 0.4}, A, B;
+  orc_area_filter(area, 8, dd, aw, ah, &A, &B);
+  FINITE(A + B);
+  orc_area_exact(area, 8, dd, aw, ah, &A, &B);
+  FINITE(A + B);
+  v.disc_density = 0;
+  v.area = area;
+  v.area_n0 = 8;
+  v.area_exact = 1;
+  v.k_area = 1.0;
+  if (orc_render_quads(&v, cube, N0, D, dn, U, ne, nphi, quads, nq, px, 4)) bad = 1;
+  for (int i = 0; i < 4 * nq; ++i) FINITE(px[i].rgb[0] + px[i].area_exact_A);
+  free(area);
+
   /* post-process */
   double img[8 * 8 * 4], out[8 * 8 * 4], w[4] = {0.7, 0.2, 0.07, 0.03};
   for (int i = 0; i < 8 * 8 * 4; ++i) img[i] = (i % 7) * 0.1;
