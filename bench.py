@@ -431,7 +431,7 @@ def main():
             "peak": (l2 if t_l2 > t_hbm else hbm)["peak"], "unit": "GB/s",
             "frac": t_roof / t_k, "t_roof_us": 1e6 * t_roof, "kernel_us": 1e6 * t_k,
             "traffic": prof["fetch_bytes"] + prof["write_bytes"] if prof else None,
-            "kernel": "k_render<16,16,1,false>", "kernel_ms": kernel_ms, "hbm": hbm, "l2": l2}
+            "kernel": "k_render<16,16,1,0>", "kernel_ms": kernel_ms, "hbm": hbm, "l2": l2}
     if prof is not None:
         flops = prof["fp32_flops_per_pixel"] * W * H
         tf = flops / t_k / 1e12

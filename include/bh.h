@@ -181,6 +181,36 @@ bh_status bh_build_stars(bh_ctx* ctx, const bh_star_field* f, void* hip_stream, 
 bh_status bh_stars_download(const bh_stars* s, int32_t level, float* host_texels);
 bh_status bh_release_stars(bh_stars* s);
 
+/* ---- area sources (Section 3.3.2 "Emitted light"; Section 3.4.1, closing note) -------
+ * Extended sources such as nebulae and galaxies, stored in a cube map that is read over
+ * each pixel's footprint with anisotropic filtering (unlike point stars, whose light the
+ * star map's gather keeps sharp).  A texel holds a radiance I (summed over the three
+ * bands, in the units of k_star's star intensities) and a blackbody colour temperature T.
+ * A pixel receives k_area x A x L_b(D_cam T_pix) / sum_b L_b(T_pix): A and A T_pix are the
+ * footprint means of I and I T, D_cam the camera's Doppler factor for static sources; no
+ * lensing amplification Omega / Omega' applies (the beam's subtended area changes in
+ * inverse proportion).  The filter: the footprint is the parallelogram of directions
+ * d' + w d_w d' + h d_h d', |w|, |h| <= 1/2 (the screen-space differences of the escape
+ * direction over the pixel's 2x2 quad); an N x 2 grid of probes (N = ceil(2 l_major /
+ * l_minor) in [1, 16], lengths in level-0 texels) reads the box mip pyramid trilinearly at
+ * level log2(max(l_major / N, l_minor / 2)) - 1, each probe on the face of its own
+ * direction.  Quads with a captured member receive no area light (as for stars). */
+typedef struct bh_area bh_area;
+/* texels_dev: device array of 6 * face_size^2 (I, T) float pairs, laid out as the star
+ * map (face 2k + (d_k < 0), column from U = d_{(k+1)%3} / |d_k|, row from V =
+ * d_{(k+2)%3} / |d_k|, row-major per face), I >= 0 and T >= 0 finite; face_size a power
+ * of two in [1, 4096].  Builds the map and its mip levels (box means of I and I T) on
+ * hip_stream and synchronises it; texels_dev may be freed afterwards.  BH_EINVAL for a bad
+ * size, a NULL pointer or an invalid texel (the check runs on the device).  Every call
+ * builds a new map; bh_release_area frees it (callers must not release a map that queued
+ * work still reads). */
+bh_status bh_build_area(bh_ctx* ctx, const float* texels_dev, int32_t face_size,
+                        void* hip_stream, bh_area** out);
+/* Copy mip level `level` as float (face, y, x, [I, I T]) to host_texels
+ * (6 * (face_size >> level)^2 * 2 floats).  Blocking. */
+bh_status bh_area_download(const bh_area* area, int32_t level, float* host_texels);
+bh_status bh_release_area(bh_area* area);
+
 /* ---- rendering (Sections 3.2-3.4) ---------------------------------------------------- */
 
 #define BH_T_POWER 0  /* T' = T0 (r' / 3 r_s)^T_exp                                        */
@@ -212,6 +242,8 @@ typedef struct {
   int32_t pad1;
   double time;          /* the camera's coordinate time (units of r_s / c)                */
   const bh_particles* particles; /* required with BH_DENSITY_PARTICLES                    */
+  const bh_area* area;  /* area-source sky (nebulae, galaxies), or NULL                   */
+  double k_area;        /* exposure applied to area radiances, finite                      */
 } bh_view;
 
 #define BH_DENSITY_UNIFORM 0
@@ -234,7 +266,8 @@ typedef struct {
 
 /* Render one view: out_rgba_dev receives width*height float4 (R, G, B, 1) in row-major
  * order, row 0 at the top; colour = k_disc x disc band radiances composited front to back
- * over k_star x lensed, Doppler-shifted star light.  aov_dev may be NULL. */
+ * over k_star x lensed, Doppler-shifted star light plus the view's area-source light.
+ * aov_dev may be NULL. */
 bh_status bh_render(bh_ctx* ctx, const bh_tables* t, const bh_view* v, float* out_rgba_dev,
                     float* aov_dev, void* hip_stream);
 
@@ -262,7 +295,7 @@ bh_status bh_render_batch(bh_ctx* ctx, const bh_tables* t, const bh_view* views,
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc): bh_render_batch without any allocation.
  * The launch's view records, tile runs and work counter live in a fixed device array of
- * the library (256 B + 512 x 304 B = 152 KiB, one per GPU, held until the process ends), so n is at
+ * the library (256 B + 512 x 336 B = 168 KiB, one per GPU, held until the process ends), so n is at
  * most BH_NOALLOC_MAX_VIEWS (BH_EINVAL above); the records are uploaded through pinned host
  * memory that bh_create sets up, and the kernels are launched directly (no graph is
  * built).  Same kernels as bh_render_batch with the same tile configuration and launch

@@ -28,6 +28,7 @@ EXPORTS = [
     "bh_bloom_create", "bh_bloom_apply", "bh_bloom_release", "bh_bloom_apply_display",
     "bh_tonemap",
     "bh_build_stars", "bh_stars_download", "bh_release_stars",
+    "bh_build_area", "bh_area_download", "bh_release_area",
     "bh_render", "bh_render_march", "bh_render_batch", "bh_render_batch_noalloc",
     "bh_tile_config_count", "bh_tile_config_get",
     "bh_set_tile_config", "bh_set_batch_form", "bh_autotune",
@@ -63,7 +64,8 @@ class View(C.Structure):
                 ("disc_T0", C.c_double), ("disc_T_exp", C.c_double),
                 ("disc_opacity", C.c_double), ("k_disc", C.c_double), ("k_star", C.c_double),
                 ("stars", C.c_void_p), ("disc_density", C.c_int32), ("pad1", C.c_int32),
-                ("time", C.c_double), ("particles", C.c_void_p)]
+                ("time", C.c_double), ("particles", C.c_void_p),
+                ("area", C.c_void_p), ("k_area", C.c_double)]
 
 
 class TileConfig(C.Structure):
@@ -102,6 +104,9 @@ def lib():
             "bh_build_stars": ([vp, C.POINTER(StarField), vp, C.POINTER(vp)], i32),
             "bh_stars_download": ([vp, i32, vp], i32),
             "bh_release_stars": ([vp], i32),
+            "bh_build_area": ([vp, vp, i32, vp, C.POINTER(vp)], i32),
+            "bh_area_download": ([vp, i32, vp], i32),
+            "bh_release_area": ([vp], i32),
             "bh_render": ([vp, vp, C.POINTER(View), vp, vp, vp], i32),
             "bh_render_batch": ([vp, vp, C.POINTER(View), i32, C.POINTER(vp), vp], i32),
             "bh_render_batch_noalloc": ([vp, vp, C.POINTER(View), i32, C.POINTER(vp), vp], i32),
@@ -211,6 +216,20 @@ def bh_stars_download(stars, level, host_ptr) -> None:
 
 def bh_release_stars(stars) -> None:
     _check(lib().bh_release_stars(stars))
+
+
+def bh_build_area(ctx, texels_ptr, face_size, stream=None) -> int:
+    out = C.c_void_p()
+    _check(lib().bh_build_area(ctx, texels_ptr, face_size, stream, C.byref(out)))
+    return out.value
+
+
+def bh_area_download(area, level, host_ptr) -> None:
+    _check(lib().bh_area_download(area, level, host_ptr))
+
+
+def bh_release_area(area) -> None:
+    _check(lib().bh_release_area(area))
 
 
 def bh_render(ctx, tables, view: View, out_ptr, aov_ptr=None, stream=None) -> None:
@@ -369,9 +388,9 @@ def bh_band_eval(ctx, temps_ptr, n, out_ptr, stream=None) -> None:
 
 # ---- helpers ------------------------------------------------------------------------------
 
-def make_view(v, stars=None, particles=None) -> View:
+def make_view(v, stars=None, particles=None, area=None) -> View:
     """bh View record from a scenes.View (same field names); `particles` is the handle from
-    bh_create_particles for a view with a particle disc."""
+    bh_create_particles for a view with a particle disc, `area` one from bh_build_area."""
     o = View()
     o.r_s = v.r_s
     o.cam_pos[:] = list(v.cam_pos)
@@ -387,6 +406,8 @@ def make_view(v, stars=None, particles=None) -> View:
     o.disc_density = getattr(v, "disc_density", BH_DENSITY_UNIFORM)
     o.time = getattr(v, "time", 0.0)
     o.particles = particles
+    o.area = area
+    o.k_area = getattr(v, "k_area", 1.0)
     return o
 
 

@@ -51,6 +51,20 @@ struct StarsDev {
   int pad[3];
 };
 
+// ---- area-source map (nebulae, galaxies) ----------------------------------------------
+// (I, I T) per texel: radiance and radiance-weighted colour temperature; level L (size
+// n0 >> L, n0 a power of two) starts at texel 8 (n0^2 - nL^2), within it face-major rows.
+struct AreaDev {
+  const float2* tex;      // null: no area map
+  int n0, levels;
+  float k_area;
+  int pad[3];
+};
+
+// Optional per-view work the render kernels are specialised for (a kernel without a
+// feature carries none of its code or registers): a particle disc, an area-source map.
+constexpr int kFeatParticles = 1, kFeatArea = 2;
+
 // ---- per-view constant block (host computes it in FP64 from bh_view) -----------------
 // The camera axes and the velocity direction are passed split into their parts transverse
 // to the radial direction e_x' and their radial components: a beam's transverse part is then
@@ -80,7 +94,13 @@ struct ViewDev {
   // inserted before the star-map fields it shifted their offsets and the render measured
   // 2.6% slower at 1920x1080.
   float er[4];
+  AreaDev area;
 };
+
+// the features a view uses
+__host__ __device__ inline int view_features(const ViewDev& v) {
+  return (v.density_mode != 0 ? kFeatParticles : 0) | (v.area.tex ? kFeatArea : 0);
+}
 
 // Bloom launch record: the image's box pyramid, levels 0 (the image) .. levels <= 16, and
 // the weights w_0 .. w_levels of the mipmap filters (Section 3.4.3)

@@ -44,7 +44,8 @@ hipError_t launch_star_unpack(const void* in, int64_t count, float scale, int fp
                               hipStream_t s);
 hipError_t launch_render(int cfg, const ViewDev& v, const TablesDev& T, const LutDev& L,
                          hipStream_t s);
-hipError_t launch_render_batch(int cfg, int persistent, int anim, const ViewDev* views,
+hipError_t launch_area_build(const float* it, int n0, float2* tex, int* bad, hipStream_t s);
+hipError_t launch_render_batch(int cfg, int persistent, int feat, const ViewDev* views,
                                const TileRun* runs, int nruns, int ntiles, int* counter,
                                const TablesDev& T, const LutDev& L, int grid, hipStream_t s);
 hipError_t launch_trace_rays(const TablesDev& T, const float* rays, int64_t n, float4* out,
@@ -146,6 +147,13 @@ struct bh_stars {
   int refs = 1;
 };
 
+struct bh_area {
+  bh_ctx* ctx;
+  float2* tex = nullptr;  // (I, I T), all levels (see area.hip)
+  int n0 = 0, levels = 0;
+  size_t bytes = 0;
+};
+
 struct Staging {
   void* host = nullptr;   // pinned
   size_t cap = 0;
@@ -164,6 +172,7 @@ struct bh_ctx {
   std::map<std::string, bh_tables*> tables;
   std::map<StarKey, bh_stars*> stars;
   std::set<bh_particles*> particles;
+  std::set<bh_area*> areas;
   std::set<bh_bloom*> blooms;
   float4* lut = nullptr;
   int lut_n = 4096;
@@ -330,6 +339,10 @@ extern "C" void bh_destroy(bh_ctx* c) {
     dev_free(c, b->P, 0);
     dev_free(c, b->U, 0);
     delete b;
+  }
+  for (bh_area* a : c->areas) {
+    dev_free(c, a->tex, 0);
+    delete a;
   }
   for (bh_particles* p : c->particles) {
     dev_free(c, p->dev, 0);
@@ -816,6 +829,70 @@ extern "C" bh_status bh_release_stars(bh_stars* s) {
   return BH_OK;
 }
 
+// ---- area sources ----------------------------------------------------------------------------
+
+extern "C" bh_status bh_build_area(bh_ctx* c, const float* texels, int32_t n0, void* stream,
+                                   bh_area** out) {
+  if (!c || !texels || !out) return fail(BH_EINVAL, "NULL argument");
+  if (n0 < 1 || n0 > 4096 || (n0 & (n0 - 1)))
+    return fail(BH_EINVAL, "face_size must be a power of two <= 4096");
+  HIPCHK(hipSetDevice(c->device));
+  hipStream_t hs = (hipStream_t)stream;
+  int levels = 0;
+  while ((n0 >> levels) >= 1) ++levels;
+  const size_t texels_all = 8ull * n0 * n0 - 2;  // 6 (n0^2 + (n0/2)^2 + ... + 1)
+  auto* a = new bh_area;
+  a->ctx = c;
+  a->n0 = n0;
+  a->levels = levels;
+  a->bytes = sizeof(float2) * texels_all;
+  int* bad = nullptr;
+  bh_status st = dev_alloc(c, a->bytes, (void**)&a->tex);
+  if (!st) st = dev_alloc(c, sizeof(int), (void**)&bad);
+  hipError_t e = hipSuccess;
+  int hbad = 0;
+  if (!st) {
+    e = launch_fill_int(bad, 1, 0, hs);
+    if (e == hipSuccess) e = launch_area_build(texels, n0, a->tex, bad, hs);
+    if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, hs);
+    if (e == hipSuccess) e = hipStreamSynchronize(hs);
+  }
+  dev_free(c, bad, bad ? sizeof(int) : 0);
+  if (st || e != hipSuccess || hbad) {
+    dev_free(c, a->tex, a->tex ? a->bytes : 0);
+    delete a;
+    if (st) return st;
+    if (e != hipSuccess) return fail(BH_EDEVICE, std::string("area build: ") + hipGetErrorString(e));
+    return fail(BH_EINVAL, "area texels must be finite with I >= 0 and T >= 0");
+  }
+  std::lock_guard<std::mutex> g(c->mu);
+  c->areas.insert(a);
+  *out = a;
+  return BH_OK;
+}
+
+extern "C" bh_status bh_area_download(const bh_area* a, int32_t level, float* host) {
+  if (!a || !host) return fail(BH_EINVAL, "NULL argument");
+  if (level < 0 || level >= a->levels) return fail(BH_EINVAL, "bad level");
+  HIPCHK(hipSetDevice(a->ctx->device));
+  const int64_t n0 = a->n0, nl = n0 >> level;
+  const int64_t off = 8 * (n0 * n0 - nl * nl);
+  HIPCHK(hipMemcpy(host, a->tex + off, sizeof(float2) * 6 * nl * nl, hipMemcpyDeviceToHost));
+  return BH_OK;
+}
+
+extern "C" bh_status bh_release_area(bh_area* a) {
+  if (!a) return fail(BH_EINVAL, "NULL area");
+  bh_ctx* c = a->ctx;
+  std::lock_guard<std::mutex> g(c->mu);
+  if (!c->areas.erase(a)) return fail(BH_EINVAL, "unknown area map");
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  dev_free(c, a->tex, a->bytes);
+  delete a;
+  return BH_OK;
+}
+
 // ---- views ---------------------------------------------------------------------------------
 
 static bool finite_all(const double* p, int n) {
@@ -854,6 +931,7 @@ static bh_status make_view(const bh_view* v, float* out, float* aov, ViewDev* o)
     return fail(BH_EINVAL, "bad disc_density");
   if (v->disc_density == BH_DENSITY_PARTICLES && (!v->particles || !std::isfinite(v->time)))
     return fail(BH_EINVAL, "a particle disc needs particles and a finite time");
+  if (v->area && !std::isfinite(v->k_area)) return fail(BH_EINVAL, "k_area must be finite");
   const double* R = v->cam_rot;
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) {
@@ -921,6 +999,12 @@ static bh_status make_view(const bh_view* v, float* out, float* aov, ViewDev* o)
     o->stars.fp16 = s->fp16;
     o->stars.one = 1.0f;
     o->stars.tw0 = 2.0f / (float)s->n0;
+  }
+  if (v->area) {
+    o->area.tex = v->area->tex;
+    o->area.n0 = v->area->n0;
+    o->area.levels = v->area->levels;
+    o->area.k_area = (float)v->k_area;
   }
   o->out = (float4*)out;
   o->aov = (float4*)aov;
@@ -1046,15 +1130,15 @@ static bh_status enqueue_batch(bh_ctx* c, int cfg, int pers, const TablesDev& T,
   }
   int grid = batch_grid(c, cfg, ntiles);
   int nruns = (int)runs.size();
-  int anim = 0;
-  for (const ViewDev& vd : vds) anim |= vd.density_mode != 0;
+  int feat = 0;  // the union of the views' features selects the kernel
+  for (const ViewDev& vd : vds) feat |= view_features(vd);
   LutDev L = lut_dev(c);
   if (!use_graph) {
-    HIPCHK(launch_render_batch(cfg, pers, anim, dviews, druns, nruns, ntiles, counter, T, L,
+    HIPCHK(launch_render_batch(cfg, pers, feat, dviews, druns, nruns, ntiles, counter, T, L,
                                grid, s));
     return BH_OK;
   }
-  bh_ctx::GraphKey key{cfg * 4 + pers * 2 + anim, ntiles, nruns, grid, (uintptr_t)counter,
+  bh_ctx::GraphKey key{cfg * 8 + pers * 4 + feat, ntiles, nruns, grid, (uintptr_t)counter,
                        (const void*)T.D, (const void*)T.U, (const void*)T.Dt, (const void*)T.Ut,
                        T.d_n, T.u_ne, T.u_nphi};
   auto it = c->graphs.find(key);
@@ -1063,7 +1147,7 @@ static bh_status enqueue_batch(bh_ctx* c, int cfg, int pers, const TablesDev& T,
     HIPCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
     hipGraph_t graph;
     HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-    hipError_t e = launch_render_batch(cfg, pers, anim, dviews, druns, nruns, ntiles, counter,
+    hipError_t e = launch_render_batch(cfg, pers, feat, dviews, druns, nruns, ntiles, counter,
                                        T, L, grid, cap);
     hipError_t e2 = hipStreamEndCapture(cap, &graph);
     (void)hipStreamDestroy(cap);
@@ -1198,9 +1282,9 @@ extern "C" bh_status bh_render_batch_noalloc(bh_ctx* c, const bh_tables* t, cons
   HIPCHK(hipMemcpyAsync(druns, hr, sizeof(TileRun) * n, hipMemcpyHostToDevice, s));
   HIPCHK(hipEventRecord(stg.done, s));
   stg.used = true;
-  int anim = 0;
-  for (int i = 0; i < n; ++i) anim |= hv[i].density_mode != 0;
-  HIPCHK(launch_render_batch(cfg, c->persistent, anim, dviews, druns, n, (int)ntiles, dcounter,
+  int feat = 0;
+  for (int i = 0; i < n; ++i) feat |= view_features(hv[i]);
+  HIPCHK(launch_render_batch(cfg, c->persistent, feat, dviews, druns, n, (int)ntiles, dcounter,
                              tables_dev(t), lut_dev(c), batch_grid(c, cfg, ntiles), s));
   return BH_OK;
 }

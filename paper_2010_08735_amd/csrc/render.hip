@@ -403,7 +403,107 @@ __device__ __forceinline__ float disc_density(const ViewDev& v, float ht, float 
 // requests (measurement only, see CountBufs).  ANIM: views may have a particle disc
 // (retarded times).
 // MARCH: ray marching (march_ray) in place of TraceRay; no tables are read.
-template <bool COUNT, bool ANIM = false, bool MARCH = false>
+// ---- area sources (Section 3.3.2 "Emitted light": nebulae and galaxies in a cube map) ----
+// The paper reads them with the texture unit's anisotropic filtering over the beam's
+// footprint; this is that filter written out.  The footprint is the parallelogram of
+// directions d' + w d_w d' + h d_h d', |w|, |h| <= 1/2 (the pixel's box); its two axes are
+// measured in level-0 texels on the face of d' (face Jacobian, Euclidean length); an
+// N_maj x 2 grid of probes (N_maj = clamp(ceil(2 l_maj / l_min), 1, 16) along the longer
+// axis) sits at the cell centres of the parallelogram, and every probe reads level
+// lambda = log2(max(l_maj / N_maj, l_min / 2)) - 1 trilinearly; the result is the probes'
+// mean of (I, I T).  Each probe takes the face of its own direction, so footprints cross
+// cube edges; bilinear coordinates are clamped to the face's outermost texel centres.
+
+// both channels of level L, bilinear, at direction p
+__device__ __forceinline__ float2 area_bilinear(const AreaDev& M, int L, float p0, float p1,
+                                                float p2) {
+  const float a0 = fabsf(p0), a1 = fabsf(p1), a2 = fabsf(p2);
+  int k = 0;
+  float m = a0;
+  if (a1 > m) { k = 1; m = a1; }
+  if (a2 > m) { k = 2; m = a2; }
+  const float pk = k == 0 ? p0 : (k == 1 ? p1 : p2);
+  const float pa = k == 0 ? p1 : (k == 1 ? p2 : p0);
+  const float pb = k == 0 ? p2 : (k == 1 ? p0 : p1);
+  const int face = 2 * k + (pk < 0.0f);
+  const float im = fdiv(1.0f, m);
+  const int nL = M.n0 >> L;
+  const uint32_t level0 = 8u * ((uint32_t)M.n0 * (uint32_t)M.n0 - (uint32_t)nL * (uint32_t)nL);
+  const float2* t = M.tex + level0 + (uint32_t)face * (uint32_t)nL * (uint32_t)nL;
+  if (nL == 1) return t[0];
+  const float fn = (float)nL, top = fn - 1.0f;
+  const float x = clampf(fmaf(0.5f * fn, fmaf(pa, im, 1.0f), -0.5f), 0.0f, top);
+  const float y = clampf(fmaf(0.5f * fn, fmaf(pb, im, 1.0f), -0.5f), 0.0f, top);
+  const int i0 = min((int)x, nL - 2), j0 = min((int)y, nL - 2);
+  const float fx = x - (float)i0, fy = y - (float)j0;
+  const float2* r0 = t + (uint32_t)j0 * (uint32_t)nL + (uint32_t)i0;
+  const float2 a = r0[0], b = r0[1], c = r0[nL], e = r0[nL + 1];
+  const float2 lo = make_float2(fmaf(fx, b.x - a.x, a.x), fmaf(fx, b.y - a.y, a.y));
+  const float2 hi = make_float2(fmaf(fx, e.x - c.x, c.x), fmaf(fx, e.y - c.y, c.y));
+  return make_float2(fmaf(fy, hi.x - lo.x, lo.x), fmaf(fy, hi.y - lo.y, lo.y));
+}
+
+// length, in level-0 texels, of the face-coordinate change along direction change (x0, x1,
+// x2) at d' on face axis k (im = 1 / |d'_k|, sg = sign of d'_k, (U, V) of d')
+__device__ __forceinline__ float area_axis(int k, float im, float sg, float U, float V, float x0,
+                                           float x1, float x2, float half_n0) {
+  const float xk = k == 0 ? x0 : (k == 1 ? x1 : x2);
+  const float xa = k == 0 ? x1 : (k == 1 ? x2 : x0);
+  const float xb = k == 0 ? x2 : (k == 1 ? x0 : x1);
+  const float dU = (xa - U * sg * xk) * im, dV = (xb - V * sg * xk) * im;
+  return half_n0 * fsqrt(dU * dU + dV * dV);
+}
+
+// mean (I, I T) of the map over the footprint of d' with axes dw, dh
+__device__ __forceinline__ void area_filter(const AreaDev& M, float d0, float d1, float d2,
+                                            float w0, float w1, float w2, float h0, float h1,
+                                            float h2, float& A, float& B) {
+  const float a0 = fabsf(d0), a1 = fabsf(d1), a2 = fabsf(d2);
+  int k = 0;
+  float m = a0;
+  if (a1 > m) { k = 1; m = a1; }
+  if (a2 > m) { k = 2; m = a2; }
+  const float dk = k == 0 ? d0 : (k == 1 ? d1 : d2);
+  const float da = k == 0 ? d1 : (k == 1 ? d2 : d0);
+  const float db = k == 0 ? d2 : (k == 1 ? d0 : d1);
+  const float im = fdiv(1.0f, m), sg = dk < 0.0f ? -1.0f : 1.0f;
+  const float U = da * im, V = db * im, half_n0 = 0.5f * (float)M.n0;
+  const float la = area_axis(k, im, sg, U, V, w0, w1, w2, half_n0);
+  const float lb = area_axis(k, im, sg, U, V, h0, h1, h2, half_n0);
+  const bool swap = lb > la;
+  const float lmaj = swap ? lb : la, lmin = swap ? la : lb;
+  const float j0 = swap ? h0 : w0, j1 = swap ? h1 : w1, j2 = swap ? h2 : w2;   // major axis
+  const float n0_ = swap ? w0 : h0, n1 = swap ? w1 : h1, n2 = swap ? w2 : h2;  // minor axis
+  int nmaj = 16;
+  if (lmin > 0.0f) nmaj = (int)clampf(ceilf(fdiv(2.0f * lmaj, lmin)), 1.0f, 16.0f);
+  const float fmaj = (float)nmaj;
+  const float sp = fmaxf(fdiv(lmaj, fmaj), 0.5f * lmin);
+  float lam = sp > 0.0f ? __log2f(sp) - 1.0f : 0.0f;
+  lam = clampf(lam, 0.0f, (float)(M.levels - 1));
+  const int L0 = (int)lam, L1 = min(L0 + 1, M.levels - 1);
+  const float fr = lam - (float)L0;
+  float sa = 0.0f, sb = 0.0f;
+  const float inv = fdiv(1.0f, fmaj);
+  for (int i = 0; i < nmaj; ++i) {
+    const float ta = fmaf((float)i + 0.5f, inv, -0.5f);
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const float tb = b == 0 ? -0.25f : 0.25f;
+      const float p0 = fmaf(tb, n0_, fmaf(ta, j0, d0));
+      const float p1 = fmaf(tb, n1, fmaf(ta, j1, d1));
+      const float p2 = fmaf(tb, n2, fmaf(ta, j2, d2));
+      const float2 v0 = area_bilinear(M, L0, p0, p1, p2);
+      const float2 v1 = area_bilinear(M, L1, p0, p1, p2);
+      sa += fmaf(fr, v1.x - v0.x, v0.x);
+      sb += fmaf(fr, v1.y - v0.y, v0.y);
+    }
+  }
+  const float in = 0.5f * inv;
+  A = sa * in;
+  B = sb * in;
+}
+
+template <bool COUNT, bool ANIM = false, bool MARCH = false, bool AREA = false>
 __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& T,
                                              const LutDev& L, int px, int py,
                                              const CountBufs* cnt) {
@@ -647,6 +747,21 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
     }
   }
 
+  // ---- area sources: the footprint's mean radiance, one Doppler shift per pixel as for
+  // stars, no lensing amplification (Section 3.4.1)
+  if (AREA && v.area.tex && !cap) {
+    float A, B;
+    area_filter(v.area, dp0, dp1, dp2, dw0, dw1, dw2, dh0, dh1, dh2, A, B);
+    if (A > 0.0f) {
+      const float Tpix = fdiv(B, A);
+      const float4 Lr = band_lookup(L, dcam * Tpix), Ln = band_lookup(L, Tpix);
+      const float sc = trans * v.area.k_area * fdiv(A, Ln.w);
+      cr += sc * Lr.x;
+      cg += sc * Lr.y;
+      cb += sc * Lr.z;
+    }
+  }
+
   if (COUNT) {
     if (px < v.width && py < v.height) req += v.aov ? 32 : 16;
     unsigned long long t = req;
@@ -673,7 +788,8 @@ struct TileCfg {
   static_assert(kWaves <= 16, "the particle loop keeps one LDS slot per wave, 16 at most");
 };
 
-template <int TW, int TH, int PPT, bool COUNT = false, bool ANIM = false, bool MARCH = false>
+template <int TW, int TH, int PPT, bool COUNT = false, bool ANIM = false, bool MARCH = false,
+          bool AREA = false>
 __device__ __forceinline__ void render_tile(const ViewDev& v, const TablesDev& T, const LutDev& L,
                                             int tx0, int ty0, const CountBufs* cnt = nullptr) {
   using C = TileCfg<TW, TH, PPT>;
@@ -687,7 +803,7 @@ __device__ __forceinline__ void render_tile(const ViewDev& v, const TablesDev& T
     int px = tx0 + 8 * bx + ox, py = ty0 + 8 * by + oy;
     // skip 8x8 blocks entirely outside the image (uniform per wave)
     if (tx0 + 8 * bx >= v.width || ty0 + 8 * by >= v.height) continue;
-    render_pixel<COUNT, ANIM, MARCH>(v, T, L, px, py, cnt);
+    render_pixel<COUNT, ANIM, MARCH, AREA>(v, T, L, px, py, cnt);
   }
 }
 
@@ -718,12 +834,13 @@ static inline int xcd_grid(int tiles_x, int tiles_y) {
 // animated variant would otherwise take 92 scalar registers and fit only 7 waves; held to
 // 8 it spills a few scalars into vector-register lanes and runs 7% faster.  (The
 // persistent batch kernel is left unbounded: held to 8 waves it would spill to memory.)
-template <int TW, int TH, int PPT, bool ANIM>
+template <int TW, int TH, int PPT, int FEAT>
 __global__ void __launch_bounds__((TW / 8) * (TH / 8) * 64 / PPT, 8)
     k_render(ViewDev v, TablesDev T, LutDev L, int tiles_x, int tiles_y) {
   int col, row;
   if (!xcd_tile(blockIdx.x, tiles_x, tiles_y, &col, &row)) return;
-  render_tile<TW, TH, PPT, false, ANIM>(v, T, L, col * TW, row * TH);
+  render_tile<TW, TH, PPT, false, (FEAT & kFeatParticles) != 0, false, (FEAT & kFeatArea) != 0>(
+      v, T, L, col * TW, row * TH);
 }
 
 // The render with ray marching in place of TraceRay (16x16 tiles, one pixel per thread).
@@ -754,7 +871,7 @@ __device__ __forceinline__ TileRun find_run(const TileRun* __restrict__ runs, in
   return r;
 }
 
-template <int TW, int TH, int PPT, bool ANIM>
+template <int TW, int TH, int PPT, int FEAT>
 __device__ __forceinline__ void render_flat_tile(const ViewDev* __restrict__ views,
                                                  const TileRun* __restrict__ runs, int nruns,
                                                  int it, const TablesDev& T, const LutDev& L) {
@@ -763,7 +880,8 @@ __device__ __forceinline__ void render_flat_tile(const ViewDev* __restrict__ vie
   // fields are read through the reference as they are needed (wave-uniform scalar loads):
   // a copy of the whole record would hold ~65 scalar registers across the tile
   const ViewDev& v = views[r.view];
-  render_tile<TW, TH, PPT, false, ANIM>(v, T, L, (tile % r.tiles_x) * TW,
+  render_tile<TW, TH, PPT, false, (FEAT & kFeatParticles) != 0, false, (FEAT & kFeatArea) != 0>(
+      v, T, L, (tile % r.tiles_x) * TW,
                                         (tile / r.tiles_x) * TH);
 }
 
@@ -778,7 +896,7 @@ __device__ __forceinline__ void render_flat_tile(const ViewDev* __restrict__ vie
 // waves it would spill; the host sizes the grid to 7 waves per SIMD.
 constexpr int kBatchThreads = 256;
 
-template <int TW, int TH, int PPT, bool ANIM>
+template <int TW, int TH, int PPT, int FEAT>
 __global__ void __launch_bounds__(kBatchThreads, 7)
     k_render_batch(const ViewDev* __restrict__ views, const TileRun* __restrict__ runs,
                    int nruns, int ntiles, int* __restrict__ counter, TablesDev T, LutDev L) {
@@ -814,7 +932,8 @@ __global__ void __launch_bounds__(kBatchThreads, 7)
       for (int blk = 0; blk < kBlocks; ++blk) {
         const int bx = tx0 + 8 * (blk % C::kBX), by = ty0 + 8 * (blk / C::kBX);
         if (bx >= v.width || by >= v.height) continue;    // block outside the image
-        render_pixel<false, ANIM>(v, T, L, bx + ox, by + oy, nullptr);
+        render_pixel<false, (FEAT & kFeatParticles) != 0, false, (FEAT & kFeatArea) != 0>(
+            v, T, L, bx + ox, by + oy, nullptr);
       }
     }
   }
@@ -825,7 +944,7 @@ __global__ void __launch_bounds__(kBatchThreads, 7)
 // are dealt to the 8 XCDs in turn, as in the plain launch.
 constexpr int kXChunk = kXBW * kXBH;
 
-template <int TW, int TH, int PPT, bool ANIM>
+template <int TW, int TH, int PPT, int FEAT>
 __global__ void __launch_bounds__((TW / 8) * (TH / 8) * 64 / PPT, 8)
     k_render_list(const ViewDev* __restrict__ views, const TileRun* __restrict__ runs,
                   int nruns, int ntiles, TablesDev T, LutDev L) {
@@ -833,7 +952,7 @@ __global__ void __launch_bounds__((TW / 8) * (TH / 8) * 64 / PPT, 8)
   int k = b >> 3;
   int it = (k / kXChunk) * (8 * kXChunk) + (b & 7) * kXChunk + k % kXChunk;
   if (it >= ntiles) return;
-  render_flat_tile<TW, TH, PPT, ANIM>(views, runs, nruns, it, T, L);
+  render_flat_tile<TW, TH, PPT, FEAT>(views, runs, nruns, it, T, L);
 }
 
 __global__ void k_reset_counter(int* c) { *c = 0; }
@@ -912,45 +1031,45 @@ hipError_t scratch_address(void** p) {
 
 struct TileEntry {
   int tw, th, waves, ppt;
-  // index 0: static disc, 1: views that may carry a particle disc
-  void (*plain[2])(const ViewDev&, const TablesDev&, const LutDev&, hipStream_t);
-  void (*batch[2])(const ViewDev*, const TileRun*, int, int, int*, const TablesDev&,
+  // indexed by the features the views may use: kFeatParticles | kFeatArea
+  void (*plain[4])(const ViewDev&, const TablesDev&, const LutDev&, hipStream_t);
+  void (*batch[4])(const ViewDev*, const TileRun*, int, int, int*, const TablesDev&,
                    const LutDev&, int grid, hipStream_t);
-  void (*list[2])(const ViewDev*, const TileRun*, int, int, const TablesDev&, const LutDev&,
+  void (*list[4])(const ViewDev*, const TileRun*, int, int, const TablesDev&, const LutDev&,
                   hipStream_t);
 };
 
-template <int TW, int TH, int PPT, bool ANIM>
+template <int TW, int TH, int PPT, int FEAT>
 static void launch_plain(const ViewDev& v, const TablesDev& T, const LutDev& L, hipStream_t s) {
   using C = TileCfg<TW, TH, PPT>;
   int tiles_x = (v.width + TW - 1) / TW, tiles_y = (v.height + TH - 1) / TH;
-  hipLaunchKernelGGL((k_render<TW, TH, PPT, ANIM>), dim3(xcd_grid(tiles_x, tiles_y)),
+  hipLaunchKernelGGL((k_render<TW, TH, PPT, FEAT>), dim3(xcd_grid(tiles_x, tiles_y)),
                      dim3(C::kThreads), 0, s, v, T, L, tiles_x, tiles_y);
 }
 
-template <int TW, int TH, int PPT, bool ANIM>
+template <int TW, int TH, int PPT, int FEAT>
 static void launch_batch(const ViewDev* views, const TileRun* runs, int nruns, int ntiles,
                          int* counter, const TablesDev& T, const LutDev& L, int grid,
                          hipStream_t s) {
   hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, counter);
-  hipLaunchKernelGGL((k_render_batch<TW, TH, PPT, ANIM>), dim3(grid), dim3(kBatchThreads), 0, s,
+  hipLaunchKernelGGL((k_render_batch<TW, TH, PPT, FEAT>), dim3(grid), dim3(kBatchThreads), 0, s,
                      views, runs, nruns, ntiles, counter, T, L);
 }
 
-template <int TW, int TH, int PPT, bool ANIM>
+template <int TW, int TH, int PPT, int FEAT>
 static void launch_list(const ViewDev* views, const TileRun* runs, int nruns, int ntiles,
                         const TablesDev& T, const LutDev& L, hipStream_t s) {
   using C = TileCfg<TW, TH, PPT>;
   int grid = (ntiles + 8 * kXChunk - 1) / (8 * kXChunk) * (8 * kXChunk);
-  hipLaunchKernelGGL((k_render_list<TW, TH, PPT, ANIM>), dim3(grid), dim3(C::kThreads), 0, s,
+  hipLaunchKernelGGL((k_render_list<TW, TH, PPT, FEAT>), dim3(grid), dim3(C::kThreads), 0, s,
                      views, runs, nruns, ntiles, T, L);
 }
 
+#define BH_FEATS(F, TW, TH, PPT) \
+  {F<TW, TH, PPT, 0>, F<TW, TH, PPT, 1>, F<TW, TH, PPT, 2>, F<TW, TH, PPT, 3>}
 #define BH_TILE(TW, TH, PPT)                                                                \
-  {TW, TH, TileCfg<TW, TH, PPT>::kWaves, PPT,                                               \
-   {launch_plain<TW, TH, PPT, false>, launch_plain<TW, TH, PPT, true>},                     \
-   {launch_batch<TW, TH, PPT, false>, launch_batch<TW, TH, PPT, true>},                     \
-   {launch_list<TW, TH, PPT, false>, launch_list<TW, TH, PPT, true>}}
+  {TW, TH, TileCfg<TW, TH, PPT>::kWaves, PPT, BH_FEATS(launch_plain, TW, TH, PPT),          \
+   BH_FEATS(launch_batch, TW, TH, PPT), BH_FEATS(launch_list, TW, TH, PPT)}
 
 static const TileEntry kTiles[] = {
     BH_TILE(16, 16, 1), BH_TILE(32, 8, 1), BH_TILE(16, 8, 1), BH_TILE(8, 8, 1),
@@ -967,17 +1086,17 @@ void tile_config(int i, int* tw, int* th, int* waves, int* ppt) {
 
 hipError_t launch_render(int cfg, const ViewDev& v, const TablesDev& T, const LutDev& L,
                          hipStream_t s) {
-  kTiles[cfg].plain[v.density_mode != 0](v, T, L, s);
+  kTiles[cfg].plain[view_features(v)](v, T, L, s);
   return hipGetLastError();
 }
 
 // persistent != 0: `grid` persistent workgroups pulling tiles from an atomic counter;
 // otherwise one workgroup per tile.
-hipError_t launch_render_batch(int cfg, int persistent, int anim, const ViewDev* views,
+hipError_t launch_render_batch(int cfg, int persistent, int feat, const ViewDev* views,
                                const TileRun* runs, int nruns, int ntiles, int* counter,
                                const TablesDev& T, const LutDev& L, int grid, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  int a = anim != 0;
+  const int a = feat & (kFeatParticles | kFeatArea);
   if (persistent)
     kTiles[cfg].batch[a](views, runs, nruns, ntiles, counter, T, L, grid, s);
   else

@@ -14,12 +14,12 @@ import numpy as np
 from paper_2010_08735_amd import bh
 
 
-def render_gpu(ctx, tables, view, stars=None, aov=True, particles=None):
+def render_gpu(ctx, tables, view, stars=None, aov=True, particles=None, area=None):
     import torch
     W, H = view.width, view.height
     out = torch.full((H, W, 4), float("nan"), dtype=torch.float32, device="cuda")
     a = torch.full((H, W, 4), float("nan"), dtype=torch.float32, device="cuda") if aov else None
-    v = bh.make_view(view, stars, particles)
+    v = bh.make_view(view, stars, particles, area)
     bh.bh_render(ctx, tables, v, out.data_ptr(), a.data_ptr() if aov else None,
                  bh.current_stream())
     torch.cuda.synchronize()
