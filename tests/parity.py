@@ -44,6 +44,14 @@ def gpu_at(rgb, aov, px):
     }
 
 
+def oracle_as_gpu(px):
+    """An oracle rendering in the form gpu_at returns, to compare two oracle modes with the
+    same masks and tolerances (the method's own error next to the GPU's)."""
+    return {"rgb": px["rgb"], "captured": px["captured"] != 0, "ncross": px["n_cross"],
+            "mip": np.where(px["mip_level"] >= 0, px["mip_level"], 255),
+            "dprime": px["delta_prime"], "u0": px["u_cross"][:, 0], "u1": px["u_cross"][:, 1]}
+
+
 def mask_of(px, g):
     cap_o = px["captured"] != 0
     m = (cap_o != g["captured"]) | (px["n_cross"] != g["ncross"])

@@ -161,10 +161,15 @@ def test_small_static_view_full_frame(gpu_ctx, gpu_tables, orc, orc_tables, smal
     assert parity.frac_within(pt, g, 2e-2, "star") > 0.99
     assert parity.frac_within(pt, g, 2e-2, "all") > 0.995
     # exact geodesics: the method's own accuracy (paper bound 1e-3 on delta' and u); star
-    # pixels also see sub-pixel star displacements from the table's delta' error
+    # pixels also see sub-pixel star displacements from the table's delta' error, so the GPU
+    # must match what the method itself reaches: the oracle's own table mode against exact
+    # mode, with the same masks, within one percentage point
     assert se["dprime_max"] < 1e-3 and se["u_max"] < 1e-3
+    meth = parity.frac_within(pe, parity.oracle_as_gpu(pt), 3e-2, "star")
+    _report({"small_star_within_3e-2": {"gpu": parity.frac_within(pe, g, 3e-2, "star"),
+                                        "oracle_tables": meth}})
     assert parity.frac_within(pe, g, 5e-2, "disc") > 0.99
-    assert parity.frac_within(pe, g, 3e-2, "star") > 0.97
+    assert parity.frac_within(pe, g, 3e-2, "star") > min(0.97, meth - 0.01)
     assert parity.frac_within(pe, g, 3e-2, "all") > 0.99
 
 
@@ -186,8 +191,16 @@ def test_boosted_orbit_view_sampled(gpu_ctx, gpu_tables, orc, orc_tables, big_fi
     assert parity.frac_within(pt, g, 2e-2, "star") > 0.99
     assert parity.frac_within(pt, g, 2e-2, "all") > 0.995
     assert se["dprime_max"] < 1e-3 and se["u_max"] < 1e-3
+    # Exact mode: at 1080p a pixel is 1e-3 rad, and the tables' delta' error (p99 4e-5 rad
+    # on these star pixels) moves gathered stars by a few hundredths of a pixel, magnified
+    # near the shadow where Omega/Omega' is large.  The oracle's own table mode therefore
+    # keeps only about 95% of star pixels within 3e-2 of exact mode (p99 0.10), and that is
+    # the bar: the GPU must reach the method's own fraction within one percentage point.
+    meth = parity.frac_within(pe, parity.oracle_as_gpu(pt), 3e-2, "star")
+    gpu = parity.frac_within(pe, g, 3e-2, "star")
+    _report({"boosted_star_within_3e-2": {"gpu": gpu, "oracle_tables": meth}})
     assert parity.frac_within(pe, g, 5e-2, "disc") > 0.99
-    assert parity.frac_within(pe, g, 3e-2, "star") > 0.92
+    assert gpu > meth - 0.01 and meth > 0.9
     assert parity.frac_within(pe, g, 3e-2, "all") > 0.98
 
 
