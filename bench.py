@@ -350,8 +350,8 @@ def main():
     # 20 warm-up frames time a card still ramping up, ~8% slower at 1080p
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=2000)
-    ap.add_argument("--legs", default="plain,anim,march,bloom,batch,serve,cpu",
-                    help="comma list of plain, anim, march, bloom, batch, serve, cpu")
+    ap.add_argument("--legs", default="plain,anim,area,march,bloom,batch,serve,cpu",
+                    help="comma list of plain, anim, area, march, bloom, batch, serve, cpu")
     ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="seconds of the Poisson arrival stream replayed by the serve leg")
     ap.add_argument("--serve-tiles", type=int, default=262144,
@@ -472,6 +472,22 @@ def main():
                              "mpx_per_s": W * H * n_a / awall / 1e6}
         bh.bh_release_particles(ph)
         log("animated:", json.dumps(extra["animated"]))
+    if "area" in legs:
+        # the same frame under an area-source sky (nebulae, Section 3.3.2) read by the
+        # anisotropic footprint filter, stars and disc unchanged
+        n_area = 512
+        tex = torch.from_numpy(scenes.area_map(n_area, 21)).cuda()
+        ah = bh.bh_build_area(ctx, tex.data_ptr(), n_area, bh.current_stream())
+        torch.cuda.synchronize()
+        del tex
+        n_ar = max(10, args.steps // 4)
+        rwall, rkms, _ = plain_leg(bh, ctx, tables, bh.make_view(sv, stars, None, ah), n_ar,
+                                   args.warmup)
+        extra["area"] = {"face_size": n_area, "map_bytes": 8 * (8 * n_area * n_area - 2),
+                         "ms_per_frame": 1e3 * rwall / n_ar, "kernel_ms": float(rkms),
+                         "mpx_per_s": W * H * n_ar / rwall / 1e6}
+        bh.bh_release_area(ah)
+        log("area:", json.dumps(extra["area"]))
     if "bloom" in legs:
         extra["bloom"] = bloom_leg(bh, scenes, ctx, out, W, H)
         log("bloom:", json.dumps(extra["bloom"]))

@@ -843,13 +843,15 @@ __global__ void __launch_bounds__((TW / 8) * (TH / 8) * 64 / PPT, 8)
       v, T, L, col * TW, row * TH);
 }
 
-// The render with ray marching in place of TraceRay (16x16 tiles, one pixel per thread).
+// The render with ray marching in place of TraceRay (16x16 tiles, one pixel per thread);
+// AREA: the view has an area-source map.
+template <bool AREA>
 __global__ void __launch_bounds__(256)
     k_render_march(ViewDev v, LutDev L, int tiles_x, int tiles_y) {
   int col, row;
   if (!xcd_tile(blockIdx.x, tiles_x, tiles_y, &col, &row)) return;
   TablesDev none{};
-  render_tile<16, 16, 1, false, false, true>(v, none, L, col * 16, row * 16);
+  render_tile<16, 16, 1, false, false, true, AREA>(v, none, L, col * 16, row * 16);
 }
 
 // The run holding flat tile index `it` (wave-uniform): the last run whose start is <= it.
@@ -1117,8 +1119,12 @@ hipError_t launch_render_count(const ViewDev& v, const TablesDev& T, const LutDe
 
 hipError_t launch_render_march(const ViewDev& v, const LutDev& L, hipStream_t s) {
   int tiles_x = (v.width + 15) / 16, tiles_y = (v.height + 15) / 16;
-  hipLaunchKernelGGL(k_render_march, dim3(xcd_grid(tiles_x, tiles_y)), dim3(256), 0, s, v, L,
-                     tiles_x, tiles_y);
+  if (v.area.tex)
+    hipLaunchKernelGGL(k_render_march<true>, dim3(xcd_grid(tiles_x, tiles_y)), dim3(256), 0, s,
+                       v, L, tiles_x, tiles_y);
+  else
+    hipLaunchKernelGGL(k_render_march<false>, dim3(xcd_grid(tiles_x, tiles_y)), dim3(256), 0, s,
+                       v, L, tiles_x, tiles_y);
   return hipGetLastError();
 }
 

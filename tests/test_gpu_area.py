@@ -143,6 +143,32 @@ def test_area_batch_equals_plain(gpu_ctx, gpu_tables, area_scene, small_scene):
     bh.bh_set_batch_form(gpu_ctx, 0)
 
 
+def test_area_light_with_ray_marching(gpu_ctx, orc, area_scene):
+    """The ray-marching render (the Section 5 ablation) reads the area map the same way:
+    against the oracle's marcher at the same step budget, area light only."""
+    import torch
+    n0, it, h, lv = area_scene
+    v = scenes.small_static_view()
+    v.width = v.height = 64
+    v.disc_opacity = 0.0
+    W = H = 64
+    out = torch.full((H, W, 4), float("nan"), dtype=torch.float32, device="cuda")
+    a = torch.full((H, W, 4), float("nan"), dtype=torch.float32, device="cuda")
+    bh.bh_render_march(gpu_ctx, bh.make_view(v, None, None, h), 100, out.data_ptr(),
+                       a.data_ptr(), bh.current_stream())
+    torch.cuda.synchronize()
+    rgb, aov = out.cpu().numpy(), a.cpu().numpy()
+    pm = orc.render_quads(v, scenes.all_quads(W, H), march=100, area=lv, area_n0=n0)
+    g = parity.gpu_at(rgb, aov, pm)
+    m = parity.mask_of(pm, g)
+    lit = ~m & (pm["star_zeroed"] == 0) & (pm["area_A"] > 0)
+    r = _frame_stats(pm, g, lit)
+    s = {"lit": int(lit.sum()), "rel_p99": float(np.percentile(r, 99)), "rel_max": float(r.max())}
+    _report({"march": s})
+    assert lit.sum() > 2500
+    assert s["rel_p99"] < 1e-4 and s["rel_max"] < 1e-3
+
+
 def test_area_rejects_invalid_maps(gpu_ctx):
     it = scenes.area_map(8, 1)
     for bad in ("negative", "nan"):
