@@ -29,9 +29,12 @@
  * Anisotropic filter (orc_area_filter), the method's approximation of that mean, in the
  * manner of texture hardware: the footprint's two axes d_w d', d_h d' are measured in
  * level-0 texels on the face of d' (the face Jacobian of the star filter, Euclidean
- * length); the longer is the major axis.  N_min = 2 probes across the minor axis and
- * N_maj = clamp(ceil(2 l_maj / l_min), 1, 16) along the major one sit at the centres of an
- * N_maj x N_min grid over the parallelogram; all probes read level
+ * length); the longer is the major axis.  Probes sit at the centres of an N_maj x N_min
+ * grid over the parallelogram, spaced no closer than half a level-0 texel: with
+ * s = max(l_min / 2, 1/2), N_maj = clamp(ceil(l_maj / s), 1, 16) along the major axis and
+ * N_min = clamp(ceil(l_min / s), 1, 2) across it (for l_min >= 1 that is
+ * ceil(2 l_maj / l_min) by 2; a footprint below a texel takes a single probe, as texture
+ * hardware does when magnifying); all probes read level
  * lambda = log2(max(l_maj / N_maj, l_min / N_min)) - 1 (one level sharper than the probe
  * spacing), clamped to [0, levels - 1], trilinearly: bilinear on levels floor(lambda) and
  * floor(lambda) + 1, mixed by the fraction.  Bilinear reads take the face of the probe's
@@ -157,12 +160,10 @@ void orc_area_filter(const double* levels, int32_t n0, const double* d, const do
     lmaj = lb;
     lmin = la;
   }
-  const int nmin = 2;
-  int nmaj = 16;
-  if (lmin > 0.0) {
-    double r = ceil(2.0 * lmaj / lmin);
-    nmaj = r < 1.0 ? 1 : (r > 16.0 ? 16 : (int)r);
-  }
+  double spc = fmax(0.5 * lmin, 0.5);
+  double r = ceil(lmaj / spc);
+  int nmaj = r < 1.0 ? 1 : (r > 16.0 ? 16 : (int)r);
+  int nmin = lmin / spc > 1.0 ? 2 : 1;
   double s = fmax(lmaj / nmaj, lmin / nmin);
   double lam = s > 0.0 ? log2(s) - 1.0 : 0.0;
   lam = fmin(fmax(lam, 0.0), (double)(nl - 1));

@@ -192,8 +192,9 @@ def test_area_filter_reproduces_maps_linear_in_face_coordinates(orc):
 def test_area_filter_level_of_detail(orc):
     """A checkerboard level 0 has every level >= 1 uniform at 1/2.  An isotropic footprint
     8 level-0 texels wide takes N_maj = 2 probes and lambda = log2(8 / 2) - 1 = 1: level 1
-    only, hence exactly 1/2; 0.2 texels wide around a texel centre it reads level 0, close
-    to that texel's 0 or 1."""
+    only, hence exactly 1/2.  A footprint 0.2 texels wide takes a single probe (probes are
+    spaced no closer than half a level-0 texel): at a texel's centre it reads exactly that
+    texel's 0 or 1 from level 0."""
     n0 = 32
     it = np.empty((6, n0, n0, 2), np.float32)
     ii, jj = np.meshgrid(np.arange(n0), np.arange(n0), indexing="xy")
@@ -207,7 +208,7 @@ def test_area_filter_level_of_detail(orc):
         assert abs(A - 0.5) < 1e-12, (width, A)
     s = 0.2 * 2 / n0
     A, _ = orc.area_filter(lv, n0, d, np.array([s, 0, 0]), np.array([0, s, 0]))
-    assert abs(A - 1.0) < 0.25, A      # texel (17, 12): (17 + 12) % 2 = 1
+    assert A == 1.0, A      # texel (17, 12): (17 + 12) % 2 = 1
 
 
 def test_area_filter_is_close_to_the_exact_mean_on_smooth_maps(orc):
