@@ -398,42 +398,50 @@ __device__ __forceinline__ float disc_density(const ViewDev& v, float ht, float 
   return rho;
 }
 
-// One pixel; every lane of the wave must call this together (quad exchanges).
-// COUNT: also mark every star-map texel the footprint visits and add up the bytes the pixel
-// requests (measurement only, see CountBufs).  ANIM: views may have a particle disc
-// (retarded times).
-// MARCH: ray marching (march_ray) in place of TraceRay; no tables are read.
 // ---- area sources (Section 3.3.2 "Emitted light": nebulae and galaxies in a cube map) ----
 // The paper reads them with the texture unit's anisotropic filtering over the beam's
 // footprint; this is that filter written out.  The footprint is the parallelogram of
 // directions d' + w d_w d' + h d_h d', |w|, |h| <= 1/2 (the pixel's box); its two axes are
 // measured in level-0 texels on the face of d' (face Jacobian, Euclidean length); an
-// N_maj x 2 grid of probes (N_maj = clamp(ceil(2 l_maj / l_min), 1, 16) along the longer
-// axis) sits at the cell centres of the parallelogram, and every probe reads level
-// lambda = log2(max(l_maj / N_maj, l_min / 2)) - 1 trilinearly; the result is the probes'
+// N_maj x N_min grid of probes sits at the cell centres of the parallelogram, spaced no
+// closer than half a level-0 texel: with s = max(l_min / 2, 1/2), N_maj = clamp(ceil(l_maj /
+// s), 1, 16) along the longer axis and N_min = clamp(ceil(l_min / s), 1, 2) across it (so
+// N_maj = ceil(2 l_maj / l_min) by 2 once l_min >= 1); every probe reads level
+// lambda = log2(max(l_maj / N_maj, l_min / N_min)) - 1 trilinearly; the result is the probes'
 // mean of (I, I T).  Each probe takes the face of its own direction, so footprints cross
 // cube edges; bilinear coordinates are clamped to the face's outermost texel centres.
 
-// both channels of level L, bilinear, at direction p
-__device__ __forceinline__ float2 area_bilinear(const AreaDev& M, int L, float p0, float p1,
-                                                float p2) {
+// Cube face of a direction: axis k = argmax |p_k| (the lowest on ties), face 2k + (p_k < 0);
+// (pk, pa, pb) = (p_k, p_{(k+1)%3}, p_{(k+2)%3})
+struct FaceOf {
+  int k, face;
+  float pk, pa, pb, m;  // m = |p_k|
+};
+
+__device__ __forceinline__ FaceOf face_of(float p0, float p1, float p2) {
   const float a0 = fabsf(p0), a1 = fabsf(p1), a2 = fabsf(p2);
-  int k = 0;
-  float m = a0;
-  if (a1 > m) { k = 1; m = a1; }
-  if (a2 > m) { k = 2; m = a2; }
-  const float pk = k == 0 ? p0 : (k == 1 ? p1 : p2);
-  const float pa = k == 0 ? p1 : (k == 1 ? p2 : p0);
-  const float pb = k == 0 ? p2 : (k == 1 ? p0 : p1);
-  const int face = 2 * k + (pk < 0.0f);
-  const float im = fdiv(1.0f, m);
+  FaceOf f;
+  f.k = 0;
+  f.m = a0;
+  if (a1 > f.m) { f.k = 1; f.m = a1; }
+  if (a2 > f.m) { f.k = 2; f.m = a2; }
+  f.pk = f.k == 0 ? p0 : (f.k == 1 ? p1 : p2);
+  f.pa = f.k == 0 ? p1 : (f.k == 1 ? p2 : p0);
+  f.pb = f.k == 0 ? p2 : (f.k == 1 ? p0 : p1);
+  f.face = 2 * f.k + (f.pk < 0.0f);
+  return f;
+}
+
+// both channels of level L, bilinear, at face coordinates (U, V) of `face`
+__device__ __forceinline__ float2 area_fetch(const AreaDev& M, int L, int face, float U,
+                                             float V) {
   const int nL = M.n0 >> L;
   const uint32_t level0 = 8u * ((uint32_t)M.n0 * (uint32_t)M.n0 - (uint32_t)nL * (uint32_t)nL);
   const float2* t = M.tex + level0 + (uint32_t)face * (uint32_t)nL * (uint32_t)nL;
   if (nL == 1) return t[0];
   const float fn = (float)nL, top = fn - 1.0f;
-  const float x = clampf(fmaf(0.5f * fn, fmaf(pa, im, 1.0f), -0.5f), 0.0f, top);
-  const float y = clampf(fmaf(0.5f * fn, fmaf(pb, im, 1.0f), -0.5f), 0.0f, top);
+  const float x = clampf(fmaf(0.5f * fn, U + 1.0f, -0.5f), 0.0f, top);
+  const float y = clampf(fmaf(0.5f * fn, V + 1.0f, -0.5f), 0.0f, top);
   const int i0 = min((int)x, nL - 2), j0 = min((int)y, nL - 2);
   const float fx = x - (float)i0, fy = y - (float)j0;
   const float2* r0 = t + (uint32_t)j0 * (uint32_t)nL + (uint32_t)i0;
@@ -443,13 +451,11 @@ __device__ __forceinline__ float2 area_bilinear(const AreaDev& M, int L, float p
   return make_float2(fmaf(fy, hi.x - lo.x, lo.x), fmaf(fy, hi.y - lo.y, lo.y));
 }
 
-// length, in level-0 texels, of the face-coordinate change along direction change (x0, x1,
-// x2) at d' on face axis k (im = 1 / |d'_k|, sg = sign of d'_k, (U, V) of d')
-__device__ __forceinline__ float area_axis(int k, float im, float sg, float U, float V, float x0,
-                                           float x1, float x2, float half_n0) {
-  const float xk = k == 0 ? x0 : (k == 1 ? x1 : x2);
-  const float xa = k == 0 ? x1 : (k == 1 ? x2 : x0);
-  const float xb = k == 0 ? x2 : (k == 1 ? x0 : x1);
+// length, in level-0 texels, of the face-coordinate change along direction change (xk, xa,
+// xb) (components in the face's axis order) at d' (im = 1 / |d'_k|, sg = sign of d'_k,
+// (U, V) of d')
+__device__ __forceinline__ float area_axis(float im, float sg, float U, float V, float xk,
+                                           float xa, float xb, float half_n0) {
   const float dU = (xa - U * sg * xk) * im, dV = (xb - V * sg * xk) * im;
   return half_n0 * fsqrt(dU * dU + dV * dV);
 }
@@ -458,51 +464,92 @@ __device__ __forceinline__ float area_axis(int k, float im, float sg, float U, f
 __device__ __forceinline__ void area_filter(const AreaDev& M, float d0, float d1, float d2,
                                             float w0, float w1, float w2, float h0, float h1,
                                             float h2, float& A, float& B) {
-  const float a0 = fabsf(d0), a1 = fabsf(d1), a2 = fabsf(d2);
-  int k = 0;
-  float m = a0;
-  if (a1 > m) { k = 1; m = a1; }
-  if (a2 > m) { k = 2; m = a2; }
-  const float dk = k == 0 ? d0 : (k == 1 ? d1 : d2);
-  const float da = k == 0 ? d1 : (k == 1 ? d2 : d0);
-  const float db = k == 0 ? d2 : (k == 1 ? d0 : d1);
-  const float im = fdiv(1.0f, m), sg = dk < 0.0f ? -1.0f : 1.0f;
-  const float U = da * im, V = db * im, half_n0 = 0.5f * (float)M.n0;
-  const float la = area_axis(k, im, sg, U, V, w0, w1, w2, half_n0);
-  const float lb = area_axis(k, im, sg, U, V, h0, h1, h2, half_n0);
+  const FaceOf c = face_of(d0, d1, d2);
+  const int k = c.k;
+  auto perm = [k](float x0, float x1, float x2, float& xk, float& xa, float& xb) {
+    xk = k == 0 ? x0 : (k == 1 ? x1 : x2);
+    xa = k == 0 ? x1 : (k == 1 ? x2 : x0);
+    xb = k == 0 ? x2 : (k == 1 ? x0 : x1);
+  };
+  float wk, wa, wb, hk, ha, hb;
+  perm(w0, w1, w2, wk, wa, wb);
+  perm(h0, h1, h2, hk, ha, hb);
+  const float im = fdiv(1.0f, c.m), sg = c.pk < 0.0f ? -1.0f : 1.0f;
+  const float U = c.pa * im, V = c.pb * im, half_n0 = 0.5f * (float)M.n0;
+  const float la = area_axis(im, sg, U, V, wk, wa, wb, half_n0);
+  const float lb = area_axis(im, sg, U, V, hk, ha, hb, half_n0);
   const bool swap = lb > la;
   const float lmaj = swap ? lb : la, lmin = swap ? la : lb;
-  const float j0 = swap ? h0 : w0, j1 = swap ? h1 : w1, j2 = swap ? h2 : w2;   // major axis
-  const float n0_ = swap ? w0 : h0, n1 = swap ? w1 : h1, n2 = swap ? w2 : h2;  // minor axis
-  int nmaj = 16;
-  if (lmin > 0.0f) nmaj = (int)clampf(ceilf(fdiv(2.0f * lmaj, lmin)), 1.0f, 16.0f);
-  const float fmaj = (float)nmaj;
-  const float sp = fmaxf(fdiv(lmaj, fmaj), 0.5f * lmin);
+  // the axes in world order (probes whose face is looked up) and in the face's order
+  const float j0 = swap ? h0 : w0, j1 = swap ? h1 : w1, j2 = swap ? h2 : w2;   // major
+  const float n0_ = swap ? w0 : h0, n1 = swap ? w1 : h1, n2 = swap ? w2 : h2;  // minor
+  const float jk = swap ? hk : wk, ja = swap ? ha : wa, jb = swap ? hb : wb;
+  const float nk = swap ? wk : hk, na = swap ? wa : ha, nb = swap ? wb : hb;
+  const float spc = fmaxf(0.5f * lmin, 0.5f), ispc = fdiv(1.0f, spc);
+  const int nmaj = (int)clampf(ceilf(lmaj * ispc), 1.0f, 16.0f);
+  const int nmin = lmin * ispc > 1.0f ? 2 : 1;
+  const float fmaj = (float)nmaj, fmin = (float)nmin;
+  const float sp = fmaxf(fdiv(lmaj, fmaj), fdiv(lmin, fmin));
   float lam = sp > 0.0f ? __log2f(sp) - 1.0f : 0.0f;
   lam = clampf(lam, 0.0f, (float)(M.levels - 1));
   const int L0 = (int)lam, L1 = min(L0 + 1, M.levels - 1);
   const float fr = lam - (float)L0;
+  const bool two = fr > 0.0f && L1 != L0;  // the second level has weight
+  // The directions on one face form a convex set of (w, h) (an intersection of half-planes),
+  // so when the parallelogram's four corners lie on the face of d', every probe does too and
+  // its face coordinates follow from the axes in the face's order without a face lookup.
+  bool one_face = true;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const float sa_ = (q & 1) ? 0.5f : -0.5f, sb_ = (q & 2) ? 0.5f : -0.5f;
+    const FaceOf f = face_of(fmaf(sb_, n0_, fmaf(sa_, j0, d0)), fmaf(sb_, n1, fmaf(sa_, j1, d1)),
+                             fmaf(sb_, n2, fmaf(sa_, j2, d2)));
+    one_face = one_face && f.face == c.face;
+  }
   float sa = 0.0f, sb = 0.0f;
   const float inv = fdiv(1.0f, fmaj);
   for (int i = 0; i < nmaj; ++i) {
     const float ta = fmaf((float)i + 0.5f, inv, -0.5f);
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
-      const float tb = b == 0 ? -0.25f : 0.25f;
-      const float p0 = fmaf(tb, n0_, fmaf(ta, j0, d0));
-      const float p1 = fmaf(tb, n1, fmaf(ta, j1, d1));
-      const float p2 = fmaf(tb, n2, fmaf(ta, j2, d2));
-      const float2 v0 = area_bilinear(M, L0, p0, p1, p2);
-      const float2 v1 = area_bilinear(M, L1, p0, p1, p2);
-      sa += fmaf(fr, v1.x - v0.x, v0.x);
-      sb += fmaf(fr, v1.y - v0.y, v0.y);
+      if (b >= nmin) break;
+      const float tb = nmin == 1 ? 0.0f : (b == 0 ? -0.25f : 0.25f);
+      int face;
+      float pu, pv;
+      if (one_face) {
+        const float pk = fmaf(tb, nk, fmaf(ta, jk, c.pk));
+        const float ip = fdiv(1.0f, fabsf(pk));
+        pu = fmaf(tb, na, fmaf(ta, ja, c.pa)) * ip;
+        pv = fmaf(tb, nb, fmaf(ta, jb, c.pb)) * ip;
+        face = c.face;
+      } else {
+        const FaceOf f = face_of(fmaf(tb, n0_, fmaf(ta, j0, d0)), fmaf(tb, n1, fmaf(ta, j1, d1)),
+                                 fmaf(tb, n2, fmaf(ta, j2, d2)));
+        const float ip = fdiv(1.0f, f.m);
+        pu = f.pa * ip;
+        pv = f.pb * ip;
+        face = f.face;
+      }
+      const float2 v0 = area_fetch(M, L0, face, pu, pv);
+      float2 v = v0;
+      if (two) {
+        const float2 v1 = area_fetch(M, L1, face, pu, pv);
+        v = make_float2(fmaf(fr, v1.x - v0.x, v0.x), fmaf(fr, v1.y - v0.y, v0.y));
+      }
+      sa += v.x;
+      sb += v.y;
     }
   }
-  const float in = 0.5f * inv;
+  const float in = inv * (nmin == 1 ? 1.0f : 0.5f);
   A = sa * in;
   B = sb * in;
 }
 
+// One pixel; every lane of the wave must call this together (quad exchanges).
+// COUNT: also mark every star-map texel the footprint visits and add up the bytes the pixel
+// requests (measurement only, see CountBufs).  ANIM: views may have a particle disc
+// (retarded times).
+// MARCH: ray marching (march_ray) in place of TraceRay; no tables are read.
 template <bool COUNT, bool ANIM = false, bool MARCH = false, bool AREA = false>
 __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& T,
                                              const LutDev& L, int px, int py,
@@ -829,13 +876,19 @@ static inline int xcd_grid(int tiles_x, int tiles_y) {
   return ((nblk + 7) / 8) * 8 * kXBW * kXBH;
 }
 
+// Resident waves per SIMD the one-launch and per-tile kernels are held to (the register
+// budget the compiler keeps to): 8, and 6 for the area-source variants, whose probe loop
+// spilled 20 vector registers to memory at 8 waves and ran 17% faster at 6 without spills.
+template <int FEAT>
+constexpr int kMinWaves = (FEAT & kFeatArea) ? 6 : 8;
+
 // One launch per view, tiles in the XCD-aware order above.
 // At least 8 resident waves per SIMD: the register budget the compiler keeps to.  The
 // animated variant would otherwise take 92 scalar registers and fit only 7 waves; held to
 // 8 it spills a few scalars into vector-register lanes and runs 7% faster.  (The
 // persistent batch kernel is left unbounded: held to 8 waves it would spill to memory.)
 template <int TW, int TH, int PPT, int FEAT>
-__global__ void __launch_bounds__((TW / 8) * (TH / 8) * 64 / PPT, 8)
+__global__ void __launch_bounds__((TW / 8) * (TH / 8) * 64 / PPT, kMinWaves<FEAT>)
     k_render(ViewDev v, TablesDev T, LutDev L, int tiles_x, int tiles_y) {
   int col, row;
   if (!xcd_tile(blockIdx.x, tiles_x, tiles_y, &col, &row)) return;
@@ -947,7 +1000,7 @@ __global__ void __launch_bounds__(kBatchThreads, 7)
 constexpr int kXChunk = kXBW * kXBH;
 
 template <int TW, int TH, int PPT, int FEAT>
-__global__ void __launch_bounds__((TW / 8) * (TH / 8) * 64 / PPT, 8)
+__global__ void __launch_bounds__((TW / 8) * (TH / 8) * 64 / PPT, kMinWaves<FEAT>)
     k_render_list(const ViewDev* __restrict__ views, const TileRun* __restrict__ runs,
                   int nruns, int ntiles, TablesDev T, LutDev L) {
   int b = blockIdx.x;
