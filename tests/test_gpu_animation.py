@@ -167,3 +167,33 @@ def test_bad_particles_and_views_are_rejected(gpu_ctx, gpu_tables):
     with pytest.raises(bh.BhError) as ei:   # particle disc without particles
         bh.bh_render(gpu_ctx, gpu_tables, bh.make_view(v, None, None), out.data_ptr())
     assert ei.value.status == bh.BH_EINVAL
+
+
+def test_animated_disc_under_an_area_sky(gpu_ctx, gpu_tables, orc, orc_time_tables, particles):
+    """The kernels specialised for both optional features (particle disc and area map):
+    the animated frame under the seeded nebula sky, every pixel against the oracle in table
+    mode with time channels; the sky shows through the half-transparent disc."""
+    import torch
+    v, h = particles
+    n0 = 32
+    it = scenes.area_map(n0, 23)
+    t = torch.from_numpy(it).cuda()
+    ah = bh.bh_build_area(gpu_ctx, t.data_ptr(), n0, bh.current_stream())
+    torch.cuda.synchronize()
+    try:
+        v2 = scenes.animated_disc_view()
+        v2.k_area = 2.0
+        rgb, aov = parity.render_gpu(gpu_ctx, gpu_tables, v2, None, particles=h, area=ah)
+    finally:
+        bh.bh_release_area(ah)
+    quads = scenes.all_quads(v2.width, v2.height)
+    pt = orc.render_quads(v2, quads, tables=orc_time_tables, area=orc.area_levels(it),
+                          area_n0=n0)
+    g = parity.gpu_at(rgb, aov, pt)
+    st = parity.compare(pt, g, "table+area")
+    lit = (pt["area_A"] > 0) & ~parity.mask_of(pt, g)
+    _report({"anim_area_table": st, "area_lit": int(lit.sum())})
+    assert np.isfinite(rgb).all() and st["masked_fraction"] < 0.02
+    assert lit.sum() > 5000
+    assert parity.frac_within(pt, g, 1e-3, "disc") > 0.99
+    assert parity.frac_within(pt, g, 2e-3, "all") > 0.99
