@@ -143,6 +143,33 @@ def test_area_batch_equals_plain(gpu_ctx, gpu_tables, area_scene, small_scene):
     bh.bh_set_batch_form(gpu_ctx, 0)
 
 
+def test_area_serving_equals_plain(gpu_ctx, gpu_tables, area_scene, small_scene):
+    """Served frames with and without an area map, split over small launches that mix
+    them, equal the single-view renders bit for bit."""
+    import torch
+    n0, it, h, lv = area_scene
+    field, sn0, sh, cube = small_scene
+    ctx = bh.bh_create(0, 0)
+    try:
+        bh.bh_serve_start(ctx, 0, 2, 64)
+        views = scenes.batch_views(6, 8)
+        areas = [h if i % 2 == 0 else None for i in range(len(views))]
+        outs = [torch.zeros((v.height, v.width, 4), dtype=torch.float32, device="cuda")
+                for v in views]
+        torch.cuda.synchronize()
+        tickets = [bh.bh_submit(ctx, gpu_tables, bh.make_view(v, sh, None, a), o.data_ptr())
+                   for v, a, o in zip(views, areas, outs)]
+        bh.bh_serve_drain(ctx)
+        for t in tickets:
+            done, _ = bh.bh_poll(ctx, t)
+            assert done
+        for v, a, o in zip(views, areas, outs):
+            ref, _ = parity.render_gpu(gpu_ctx, gpu_tables, v, sh, aov=False, area=a)
+            assert np.array_equal(o.cpu().numpy(), ref)
+    finally:
+        bh.bh_destroy(ctx)
+
+
 def test_area_light_with_ray_marching(gpu_ctx, orc, area_scene):
     """The ray-marching render (the Section 5 ablation) reads the area map the same way:
     against the oracle's marcher at the same step budget, area light only."""
