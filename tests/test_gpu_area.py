@@ -209,6 +209,23 @@ def test_area_rejects_invalid_maps(gpu_ctx):
         assert e.value.status == bh.BH_EINVAL
     import torch
     t = torch.from_numpy(it).cuda()
-    with pytest.raises(bh.BhError) as e:
-        bh.bh_build_area(gpu_ctx, t.data_ptr(), 6, bh.current_stream())
-    assert e.value.status == bh.BH_EINVAL
+    for bad_size in (6, 0, 8192):
+        with pytest.raises(bh.BhError) as e:
+            bh.bh_build_area(gpu_ctx, t.data_ptr(), bad_size, bh.current_stream())
+        assert e.value.status == bh.BH_EINVAL
+
+
+def test_area_view_with_bad_exposure_is_rejected(gpu_ctx, gpu_tables, area_scene):
+    import torch
+    n0, it, h, lv = area_scene
+    v = scenes.small_static_view()
+    out = torch.zeros((v.height, v.width, 4), dtype=torch.float32, device="cuda")
+    for k in (float("nan"), float("inf")):
+        v.k_area = k
+        with pytest.raises(bh.BhError) as e:
+            bh.bh_render(gpu_ctx, gpu_tables, bh.make_view(v, None, None, h), out.data_ptr(),
+                         None, bh.current_stream())
+        assert e.value.status == bh.BH_EINVAL
+    v.k_area = float("nan")   # ignored without an area map
+    bh.bh_render(gpu_ctx, gpu_tables, bh.make_view(v), out.data_ptr(), None, bh.current_stream())
+    torch.cuda.synchronize()
