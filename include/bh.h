@@ -55,9 +55,18 @@ typedef struct bh_particles bh_particles;
 bh_status bh_create(int device, uint64_t hbm_budget_bytes, bh_ctx** out);
 /* Wait for outstanding work, cancel queued requests, free every resource. */
 void bh_destroy(bh_ctx* ctx);
-const char* bh_last_error(void);
+/* The calling thread's last failure message (owned by the library, valid until this thread's
+ * next failing call).  ctx may be NULL: messages are kept per thread, not per context. */
+const char* bh_last_error(const bh_ctx* ctx);
 /* Device bytes currently allocated by the library on this context. */
 uint64_t bh_bytes_in_use(const bh_ctx* ctx);
+/* Release any handle the library returned (tables, star maps, area maps, particles, bloom
+ * pyramids): the same as the release call of its type.  Tables and star maps are
+ * reference-counted (one release per build call that returned them); the others are
+ * freed.  BH_EINVAL for NULL or any address that is not a live handle of this library
+ * (the library keeps a registry of live handles and never reads through the address
+ * before finding it there). */
+bh_status bh_release(void* handle);
 
 /* ---- precomputed tables (Section 3.3.2 "Escape angle", 3.3.3 "Intersections",
  *      Algorithm 1 Precompute, Appendix A) -------------------------------------------- */
@@ -160,22 +169,20 @@ bh_status bh_bloom_apply_display(bh_bloom* b, const float* weights, float exposu
 #define BH_TEXEL_FP16 0     /* RGBA16F texels: I (per-level power-of-two scale), T, p_u, p_v */
 #define BH_TEXEL_FP32 1     /* RGBA32F texels                                             */
 
-typedef struct {
-  const float* dir_xyz_dev;     /* n x 3 directions (any length > 0), device               */
-  const float* intensity_dev;   /* n, emitted intensity summed over the three bands, >= 0  */
-  const float* temperature_dev; /* n, blackbody temperature in K                           */
-  int64_t n;
-  int32_t face_size;            /* level-0 texels per cube face edge, power of two         */
-  int32_t texel_format;         /* BH_TEXEL_*                                              */
-} bh_star_field;
 
-/* Splat the stars into a cube map (one texel holds the intensity sum, the
+/* dir_xyz_dev: n x 3 directions (any length > 0), intensity_dev: n emitted intensities
+ * summed over the three bands (>= 0), temperature_dev: n blackbody temperatures in K, all
+ * device arrays; face_size: level-0 texels per cube face edge, a power of two <= 8192;
+ * texel_format: BH_TEXEL_*.
+ * Splat the stars into a cube map (one texel holds the intensity sum, the
  * intensity-weighted mean temperature and the intensity-weighted mean position of the
  * stars inside it) and build every mip level with the same rule.  Deterministic.
  * A field whose arrays hash to a resident map of the same star count, face size and
  * format returns that map (its count incremented) without building anything.
  * Synchronises hip_stream before returning. */
-bh_status bh_build_stars(bh_ctx* ctx, const bh_star_field* f, void* hip_stream, bh_stars** out);
+bh_status bh_build_stars(bh_ctx* ctx, const float* dir_xyz_dev, const float* intensity_dev,
+                         const float* temperature_dev, int64_t n, int32_t face_size,
+                         int32_t texel_format, void* hip_stream, bh_stars** out);
 /* Copy mip level `level` as float (face, y, x, [I, T, p_u, p_v]) to host_texels
  * (6 * (face_size >> level)^2 * 4 floats).  Blocking. */
 bh_status bh_stars_download(const bh_stars* s, int32_t level, float* host_texels);

@@ -22,7 +22,7 @@ BH_DENSITY_UNIFORM, BH_DENSITY_PARTICLES = 0, 1
 
 # every symbol include/bh.h declares
 EXPORTS = [
-    "bh_create", "bh_destroy", "bh_last_error", "bh_bytes_in_use",
+    "bh_create", "bh_destroy", "bh_last_error", "bh_bytes_in_use", "bh_release",
     "bh_precompute_tables", "bh_tables_download", "bh_tables_download_time", "bh_release_tables",
     "bh_create_particles", "bh_release_particles",
     "bh_bloom_create", "bh_bloom_apply", "bh_bloom_release", "bh_bloom_apply_display",
@@ -47,12 +47,6 @@ class BhError(RuntimeError):
 class TableParams(C.Structure):
     _fields_ = [("d_n", C.c_int32), ("u_ne", C.c_int32), ("u_nphi", C.c_int32),
                 ("precision", C.c_int32), ("fp64_band", C.c_double), ("step", C.c_double)]
-
-
-class StarField(C.Structure):
-    _fields_ = [("dir_xyz_dev", C.c_void_p), ("intensity_dev", C.c_void_p),
-                ("temperature_dev", C.c_void_p), ("n", C.c_int64), ("face_size", C.c_int32),
-                ("texel_format", C.c_int32)]
 
 
 class View(C.Structure):
@@ -93,7 +87,8 @@ def lib():
         sig = {
             "bh_create": ([C.c_int, u64, C.POINTER(vp)], i32),
             "bh_destroy": ([vp], None),
-            "bh_last_error": ([], C.c_char_p),
+            "bh_last_error": ([vp], C.c_char_p),
+            "bh_release": ([vp], i32),
             "bh_bytes_in_use": ([vp], u64),
             "bh_precompute_tables": ([vp, C.POINTER(TableParams), vp, C.POINTER(vp)], i32),
             "bh_tables_download": ([vp, vp, vp], i32),
@@ -101,7 +96,7 @@ def lib():
             "bh_create_particles": ([vp, vp, i32, C.POINTER(vp)], i32),
             "bh_release_particles": ([vp], i32),
             "bh_release_tables": ([vp], i32),
-            "bh_build_stars": ([vp, C.POINTER(StarField), vp, C.POINTER(vp)], i32),
+            "bh_build_stars": ([vp, vp, vp, vp, i64, i32, i32, vp, C.POINTER(vp)], i32),
             "bh_stars_download": ([vp, i32, vp], i32),
             "bh_release_stars": ([vp], i32),
             "bh_build_area": ([vp, vp, i32, vp, C.POINTER(vp)], i32),
@@ -148,7 +143,7 @@ def lib():
 
 def _check(status):
     if status != BH_OK:
-        msg = lib().bh_last_error()
+        msg = lib().bh_last_error(None)
         raise BhError(status, msg.decode() if msg else "")
     return status
 
@@ -202,11 +197,16 @@ def bh_release_particles(particles) -> None:
     _check(lib().bh_release_particles(particles))
 
 
+def bh_release(handle) -> None:
+    """Release any handle (tables, star map, area map, particles, bloom pyramid)."""
+    _check(lib().bh_release(handle))
+
+
 def bh_build_stars(ctx, dir_ptr, inten_ptr, temp_ptr, n, face_size, texel_format=BH_TEXEL_FP16,
                    stream=None) -> int:
-    f = StarField(dir_ptr, inten_ptr, temp_ptr, n, face_size, texel_format)
     out = C.c_void_p()
-    _check(lib().bh_build_stars(ctx, C.byref(f), stream, C.byref(out)))
+    _check(lib().bh_build_stars(ctx, dir_ptr, inten_ptr, temp_ptr, n, face_size, texel_format,
+                                stream, C.byref(out)))
     return out.value
 
 

@@ -90,7 +90,21 @@ constexpr int64_t kMaxElems = (int64_t)1 << 31;
       return fail(BH_EDEVICE, std::string(#expr) + " failed: " + hipGetErrorString(e_));    \
   } while (0)
 
-extern "C" const char* bh_last_error(void) { return g_err.c_str(); }
+extern "C" const char* bh_last_error(const bh_ctx*) { return g_err.c_str(); }
+
+// Live handles of every context, by address and type, so that bh_release can dispatch on any
+// handle, and reject an address that is not one, without reading through it.
+enum HandleKind { kTables, kStars, kParticles, kBloom, kArea };
+static std::mutex g_handles_mu;
+static std::unordered_map<const void*, HandleKind> g_handles;
+static void handle_add(const void* h, HandleKind k) {
+  std::lock_guard<std::mutex> g(g_handles_mu);
+  g_handles[h] = k;
+}
+static void handle_drop(const void* h) {
+  std::lock_guard<std::mutex> g(g_handles_mu);
+  g_handles.erase(h);
+}
 
 // ---- resources -----------------------------------------------------------------------------
 
@@ -325,6 +339,7 @@ extern "C" void bh_destroy(bh_ctx* c) {
     dev_free(c, kv.second->U, 0);
     dev_free(c, kv.second->Dt, 0);
     dev_free(c, kv.second->Ut, 0);
+    handle_drop(kv.second);
     delete kv.second;
   }
   for (auto& kv : c->stars) {
@@ -333,19 +348,23 @@ extern "C" void bh_destroy(bh_ctx* c) {
     dev_free(c, kv.second->level_off_dev, 0);
     dev_free(c, kv.second->occ, 0);
     dev_free(c, kv.second->occ_off_dev, 0);
+    handle_drop(kv.second);
     delete kv.second;
   }
   for (bh_bloom* b : c->blooms) {
     dev_free(c, b->P, 0);
     dev_free(c, b->U, 0);
+    handle_drop(b);
     delete b;
   }
   for (bh_area* a : c->areas) {
     dev_free(c, a->tex, 0);
+    handle_drop(a);
     delete a;
   }
   for (bh_particles* p : c->particles) {
     dev_free(c, p->dev, 0);
+    handle_drop(p);
     delete p;
   }
   dev_free(c, c->lut, 0);
@@ -424,6 +443,7 @@ extern "C" bh_status bh_precompute_tables(bh_ctx* c, const bh_table_params* pin,
     return fail(BH_EDEVICE, std::string("precompute: ") + hipGetErrorString(e));
   }
   c->tables[key] = t;
+  handle_add(t, kTables);
   *out = t;
   return BH_OK;
 }
@@ -466,6 +486,7 @@ extern "C" bh_status bh_release_tables(bh_tables* t) {
   dev_free(c, t->U, sizeof(float) * (size_t)t->p.u_ne * t->p.u_nphi);
   dev_free(c, t->Dt, sizeof(float) * (size_t)t->p.d_n * t->p.d_n);
   dev_free(c, t->Ut, sizeof(float) * (size_t)t->p.u_ne * t->p.u_nphi);
+  handle_drop(t);
   delete t;
   return BH_OK;
 }
@@ -548,6 +569,7 @@ extern "C" bh_status bh_create_particles(bh_ctx* c, const double* tr, int32_t n,
     return fail(BH_EDEVICE, std::string("hipMemcpy: ") + hipGetErrorString(e));
   }
   c->particles.insert(p);
+  handle_add(p, kParticles);
   *out = p;
   return BH_OK;
 }
@@ -560,6 +582,7 @@ extern "C" bh_status bh_release_particles(bh_particles* p) {
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();  // launches may still read the records
   dev_free(c, p->dev, p->bytes);
+  handle_drop(p);
   delete p;
   return BH_OK;
 }
@@ -602,6 +625,7 @@ extern "C" bh_status bh_bloom_create(bh_ctx* c, int32_t width, int32_t height, i
   }
   std::lock_guard<std::mutex> g(c->mu);
   c->blooms.insert(b);
+  handle_add(b, kBloom);
   *out = b;
   return BH_OK;
 }
@@ -669,21 +693,24 @@ extern "C" bh_status bh_bloom_release(bh_bloom* b) {
   (void)hipDeviceSynchronize();  // launches may still use the pyramid
   dev_free(c, b->P, sizeof(float4) * b->elems);
   dev_free(c, b->U, sizeof(float4) * b->elems);
+  handle_drop(b);
   delete b;
   return BH_OK;
 }
 
 // ---- stars ---------------------------------------------------------------------------------
 
-extern "C" bh_status bh_build_stars(bh_ctx* c, const bh_star_field* f, void* stream,
-                                    bh_stars** out) {
-  if (!c || !f || !out) return fail(BH_EINVAL, "NULL argument");
-  if (f->n < 0 || (f->n > 0 && (!f->dir_xyz_dev || !f->intensity_dev || !f->temperature_dev)))
+extern "C" bh_status bh_build_stars(bh_ctx* c, const float* dir_xyz_dev,
+                                    const float* intensity_dev, const float* temperature_dev,
+                                    int64_t n, int32_t face_size, int32_t texel_format,
+                                    void* stream, bh_stars** out) {
+  if (!c || !out) return fail(BH_EINVAL, "NULL argument");
+  if (n < 0 || (n > 0 && (!dir_xyz_dev || !intensity_dev || !temperature_dev)))
     return fail(BH_EINVAL, "bad star arrays");
-  if (f->n >= (int64_t)1 << 31) return fail(BH_EINVAL, "at most 2^31 - 1 stars");
-  int n0 = f->face_size;
+  if (n >= (int64_t)1 << 31) return fail(BH_EINVAL, "at most 2^31 - 1 stars");
+  int n0 = face_size;
   if (n0 < 1 || n0 > 8192 || (n0 & (n0 - 1))) return fail(BH_EINVAL, "face_size must be a power of two <= 8192");
-  if (f->texel_format != BH_TEXEL_FP16 && f->texel_format != BH_TEXEL_FP32)
+  if (texel_format != BH_TEXEL_FP16 && texel_format != BH_TEXEL_FP32)
     return fail(BH_EINVAL, "bad texel_format");
   HIPCHK(hipSetDevice(c->device));
   hipStream_t hs = (hipStream_t)stream;
@@ -695,7 +722,7 @@ extern "C" bh_status bh_build_stars(bh_ctx* c, const bh_star_field* f, void* str
     if (hst) return hst;
     hipError_t e = hipMemsetAsync(acc, 0, sizeof(unsigned long long), hs);
     if (e == hipSuccess)
-      e = launch_star_hash(f->dir_xyz_dev, f->intensity_dev, f->temperature_dev, f->n, acc, hs);
+      e = launch_star_hash(dir_xyz_dev, intensity_dev, temperature_dev, n, acc, hs);
     unsigned long long h = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&h, acc, sizeof(h), hipMemcpyDeviceToHost, hs);
     if (e == hipSuccess) e = hipStreamSynchronize(hs);
@@ -704,7 +731,7 @@ extern "C" bh_status bh_build_stars(bh_ctx* c, const bh_star_field* f, void* str
     hash = h;
   }
   std::lock_guard<std::mutex> g(c->mu);
-  StarKey key{hash, f->n, n0, f->texel_format};
+  StarKey key{hash, n, n0, texel_format};
   auto found = c->stars.find(key);
   if (found != c->stars.end()) {
     found->second->refs++;
@@ -721,7 +748,7 @@ extern "C" bh_status bh_build_stars(bh_ctx* c, const bh_star_field* f, void* str
     ooff[l] = (uint32_t)owords;
     owords += 6ull * (n0 >> l) * ((((n0 >> l) + 31) >> 5) + 1);
   }
-  int fp16 = f->texel_format == BH_TEXEL_FP16;
+  int fp16 = texel_format == BH_TEXEL_FP16;
   size_t tsz = fp16 ? 8 : 16;
   auto* s = new bh_stars;
   s->ctx = c;
@@ -740,7 +767,7 @@ extern "C" bh_status bh_build_stars(bh_ctx* c, const bh_star_field* f, void* str
   if (!st) st = dev_alloc(c, boff, (void**)&s->occ_off_dev);
   s->occ_bytes = bocc;
   // build scratch (freed below)
-  int64_t ntex0 = 6ll * n0 * n0, n = f->n;
+  int64_t ntex0 = 6ll * n0 * n0;
   size_t bhead = sizeof(int) * ntex0, bnext = sizeof(int) * std::max<int64_t>(n, 1),
          bpos = sizeof(float2) * std::max<int64_t>(n, 1), bmaster = sizeof(float4) * total,
          bmax = sizeof(unsigned) * 64;
@@ -762,7 +789,7 @@ extern "C" bh_status bh_build_stars(bh_ctx* c, const bh_star_field* f, void* str
     if (e == hipSuccess) e = launch_fill_int(head, ntex0, -1, hs);
     if (e == hipSuccess) e = launch_fill_int((int*)maxbits, 64, 0, hs);
     if (e == hipSuccess)
-      e = launch_star_build(f->dir_xyz_dev, f->intensity_dev, f->temperature_dev, n, n0, levels,
+      e = launch_star_build(dir_xyz_dev, intensity_dev, temperature_dev, n, n0, levels,
                             off.data(), head, next, pos, master, maxbits, s->scale, fp16, s->tex,
                             hs);
     if (e == hipSuccess)
@@ -786,6 +813,7 @@ extern "C" bh_status bh_build_stars(bh_ctx* c, const bh_star_field* f, void* str
   }
   s->bytes = btex + bsc + 2 * boff + bocc;
   c->stars[key] = s;
+  handle_add(s, kStars);
   *out = s;
   return BH_OK;
 }
@@ -825,6 +853,7 @@ extern "C" bh_status bh_release_stars(bh_stars* s) {
   dev_free(c, s->level_off_dev, sizeof(uint32_t) * s->levels);
   dev_free(c, s->occ, s->occ_bytes);
   dev_free(c, s->occ_off_dev, sizeof(uint32_t) * s->levels);
+  handle_drop(s);
   delete s;
   return BH_OK;
 }
@@ -867,6 +896,7 @@ extern "C" bh_status bh_build_area(bh_ctx* c, const float* texels, int32_t n0, v
   }
   std::lock_guard<std::mutex> g(c->mu);
   c->areas.insert(a);
+  handle_add(a, kArea);
   *out = a;
   return BH_OK;
 }
@@ -889,8 +919,27 @@ extern "C" bh_status bh_release_area(bh_area* a) {
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
   dev_free(c, a->tex, a->bytes);
+  handle_drop(a);
   delete a;
   return BH_OK;
+}
+
+extern "C" bh_status bh_release(void* h) {
+  HandleKind k;
+  {
+    std::lock_guard<std::mutex> g(g_handles_mu);
+    auto it = g_handles.find(h);
+    if (it == g_handles.end()) return fail(BH_EINVAL, "not a live handle");
+    k = it->second;
+  }
+  switch (k) {
+    case kTables: return bh_release_tables((bh_tables*)h);
+    case kStars: return bh_release_stars((bh_stars*)h);
+    case kParticles: return bh_release_particles((bh_particles*)h);
+    case kBloom: return bh_bloom_release((bh_bloom*)h);
+    case kArea: return bh_release_area((bh_area*)h);
+  }
+  return fail(BH_EINVAL, "not a live handle");
 }
 
 // ---- views ---------------------------------------------------------------------------------

@@ -60,12 +60,12 @@ def _c_layout(tmp_path, struct, fields):
     return vals[0], dict(zip(fields, vals[1:]))
 
 
-@pytest.mark.parametrize("name", ["View", "TableParams", "StarField", "TileConfig", "ServeParams"])
+@pytest.mark.parametrize("name", ["View", "TableParams", "TileConfig", "ServeParams"])
 def test_structs_match_header_layout(tmp_path, name):
     """The ctypes records of the binding have the C layout of include/bh.h, field by field."""
     import ctypes as C
     cls = getattr(bh, name)
-    cname = {"View": "bh_view", "TableParams": "bh_table_params", "StarField": "bh_star_field",
+    cname = {"View": "bh_view", "TableParams": "bh_table_params",
              "TileConfig": "bh_tile_config", "ServeParams": "bh_serve_params"}[name]
     fields = [f[0] for f in cls._fields_]
     size, offs = _c_layout(tmp_path, cname, fields)
@@ -81,7 +81,17 @@ def test_serve_start_rejects_launches_past_the_work_item_range(lib):
     p = bh.ServeParams(0, 0, 1 << 22)
     rc = lib.bh_serve_start(None, C.byref(p))
     assert rc == bh.BH_EINVAL
-    assert b"max_tiles_per_launch" in lib.bh_last_error()
+    assert b"max_tiles_per_launch" in lib.bh_last_error(None)
     p = bh.ServeParams(0, 0, (1 << 22) - 1)
     assert lib.bh_serve_start(None, C.byref(p)) == bh.BH_EINVAL
-    assert b"NULL context" in lib.bh_last_error()
+    assert b"NULL context" in lib.bh_last_error(None)
+
+
+def test_generic_release_rejects_addresses_that_are_not_handles(lib):
+    """bh_release looks an address up among the live handles before touching it: NULL, a
+    host buffer and a misaligned address are refused with BH_EINVAL and a message."""
+    import ctypes as C
+    buf = (C.c_uint64 * 8)()
+    for addr in (None, C.addressof(buf), C.addressof(buf) + 3):
+        assert lib.bh_release(addr) == bh.BH_EINVAL
+        assert b"not a live handle" in lib.bh_last_error(None)

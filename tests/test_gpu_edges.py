@@ -102,3 +102,35 @@ def test_camera_just_outside_the_horizon(gpu_ctx, gpu_tables, orc, orc_tables, s
     pt, g = _full_frame(gpu_ctx, gpu_tables, orc, orc_tables, v, small_scene, "horizon")
     cap = (pt["captured"] != 0).mean()
     assert 0.2 < cap < 0.9, cap
+
+
+def test_generic_release_frees_every_handle_type(gpu_ctx):
+    """bh_release frees tables, star maps, area maps, particles and bloom pyramids like the
+    typed release calls: the context's device bytes return to where they were, and a
+    second release of the same address is refused."""
+    import torch
+    from conftest import gpu_star_map
+    ctx = bh.bh_create(0, 0)
+    try:
+        base = bh.bh_bytes_in_use(ctx)
+        field = scenes.star_field(2000, 5)
+        it = scenes.area_map(16, 3)
+        t = torch.from_numpy(np.ascontiguousarray(it, np.float32)).cuda()
+        handles = [
+            bh.bh_precompute_tables(ctx, d_n=64, u_ne=16, u_nphi=8),
+            gpu_star_map(ctx, field, 32, bh.BH_TEXEL_FP16),
+            bh.bh_build_area(ctx, t.data_ptr(), 16, bh.current_stream()),
+            bh.bh_create_particles(ctx, [[6.0, 9.0, 0.5], [4.0, 4.0, 1.0]]),
+            bh.bh_bloom_create(ctx, 64, 32, 3),
+        ]
+        torch.cuda.synchronize()
+        assert bh.bh_bytes_in_use(ctx) > base
+        for h in handles:
+            bh.bh_release(h)
+        assert bh.bh_bytes_in_use(ctx) == base
+        for h in handles:
+            with pytest.raises(bh.BhError) as e:
+                bh.bh_release(h)
+            assert e.value.status == bh.BH_EINVAL
+    finally:
+        bh.bh_destroy(ctx)
