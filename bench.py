@@ -145,13 +145,17 @@ def batch_leg(bh, ctx, tables, views, reps):
 
 
 def serve_leg(bh, scenes, tables_of, fields, duration, rate, seed, budget, max_tiles,
-              inflight, tile_config):
+              inflight, tile_config, orbits="circular"):
     """Poisson arrivals for `duration` seconds through bh_submit/bh_poll (library-allocated
     images inside the HBM budget), then the same requests submitted all at once, twice: the
-    first pass allocates the server's images, the second runs on its recycled images."""
+    first pass allocates the server's images, the second runs on its recycled images.
+    Cameras on circular orbits, or freely falling on the orbits of Appendix C."""
     import torch
-    reqs = scenes.serve_requests(rate=rate, duration=duration, seed=seed)
-    out = {"requests": len(reqs), "rate_per_s": rate, "duration_s": duration,
+    if orbits == "freefall":
+        reqs = scenes.freefall_requests(rate=rate, duration=duration, seed=seed + 1)
+    else:
+        reqs = scenes.serve_requests(rate=rate, duration=duration, seed=seed)
+    out = {"requests": len(reqs), "rate_per_s": rate, "duration_s": duration, "orbits": orbits,
            "max_tiles_per_launch": max_tiles, "max_inflight_launches": inflight,
            "tile_config": tile_config}
     ctx = bh.bh_create(0, budget)
@@ -360,6 +364,8 @@ def main():
                     help="serving launches kept in flight")
     ap.add_argument("--serve-tile-config", type=int, default=0,
                     help="tile configuration index of the serving launches")
+    ap.add_argument("--serve-orbits", choices=("circular", "freefall"), default="circular",
+                    help="serve leg cameras: circular orbits, or free fall (Appendix C)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the beam tracer runs on a single MI355X here "
@@ -506,7 +512,7 @@ def main():
         tab = lambda c: bh.bh_precompute_tables(c, 512, 64, 32, bh.BH_TAB_FP64_BAND, 0.05)
         extra["served"] = serve_leg(bh, scenes, tab, fields, args.serve_seconds, 200.0, 4,
                                     64 << 30, args.serve_tiles, args.serve_inflight,
-                                    args.serve_tile_config)
+                                    args.serve_tile_config, args.serve_orbits)
         log("serve:", json.dumps(extra["served"]))
 
     if "calib" in legs:

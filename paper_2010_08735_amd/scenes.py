@@ -202,6 +202,117 @@ def aimed_view(pos, vel, width, height, **kw) -> View:
 
 
 # ----------------------------------------------------------------------------------------
+# freely falling cameras (Appendix C, "Position"); units r_s = 1, u = 1 / r
+
+@dataclasses.dataclass
+class OrbitState:
+    """Camera on a timelike geodesic in its orbital plane: coordinate time t, radius r,
+    in-plane angle psi, and their proper-time rates (Appendix C).  Arrays of one shape."""
+    tau: np.ndarray
+    t: np.ndarray
+    r: np.ndarray
+    psi: np.ndarray
+    dr: np.ndarray       # dr / dtau
+    dt: np.ndarray       # dt / dtau = e / (1 - u)
+    dpsi: np.ndarray     # dpsi / dtau = l u^2
+
+
+def orbit_constants(r0: float, delta0: float, v0: float) -> Tuple[float, float]:
+    """Energy e and angular momentum l per unit mass of the geodesic that starts at radius
+    r0 with speed v0 (measured by the static observer there) in the direction delta0,
+    moving towards increasing psi (Appendix C): e^2 from the Lorentz factor against the
+    static observer, l^2 from tan(delta) = r dpsi / dr.  delta is the coordinate angle
+    from the outward radial direction; the static observer sees the angle
+    atan(sqrt(1 - u) tan(delta)), as radial lengths are stretched by 1 / sqrt(1 - u)."""
+    u0 = 1.0 / r0
+    if not (r0 > 1.0 and 0.0 <= v0 < 1.0 and 0.0 <= delta0 <= math.pi):
+        raise ValueError("need r0 > 1, 0 <= v0 < 1, 0 <= delta0 <= pi")
+    e2 = (1.0 - u0) / (1.0 - v0 * v0)
+    s = math.sin(delta0)
+    if s == 0.0 or v0 == 0.0:
+        return math.sqrt(e2), 0.0
+    cot = math.cos(delta0) / s
+    l2 = (e2 + u0 - 1.0) / (u0 * u0 * (1.0 - u0 + cot * cot))
+    return math.sqrt(e2), math.sqrt(l2)
+
+
+def camera_orbit(r0: float, delta0: float, v0: float, taus, step: float = 0.5) -> OrbitState:
+    """States of the Appendix C camera at the proper times `taus` (ascending, from 0).
+
+    r follows the second-order radial equation d2r/dtau2 = (2 l^2 u^3 - 3 l^2 u^4 - u^2)/2,
+    t and psi the first integrals dt/dtau = e/(1-u) and dpsi/dtau = l u^2; one classical
+    RK4 integration of (t, r, dr/dtau, psi) in proper time, with steps of at most `step`,
+    stopped at each requested time.  Raises if the camera reaches r <= 1.05."""
+    taus = np.asarray(taus, np.float64)
+    if taus.ndim != 1 or (taus.size and (taus[0] < 0 or np.any(np.diff(taus) < 0))):
+        raise ValueError("taus must be ascending and non-negative")
+    e, l = orbit_constants(r0, delta0, v0)
+    u0 = 1.0 / r0
+    if l > 0.0:
+        dr0 = l * u0 * math.cos(delta0) / math.sin(delta0)   # tan(delta) = r dpsi / dr
+    else:
+        dr0 = math.copysign(math.sqrt(max(0.0, e * e + u0 - 1.0)), math.cos(delta0))
+
+    def f(y):
+        t, r, v, psi = y
+        u = 1.0 / r
+        return (e / (1.0 - u), v, 0.5 * (2.0 * l * l * u ** 3 - 3.0 * l * l * u ** 4 - u * u),
+                l * u * u)
+
+    def rk4(y, h):
+        k1 = f(y)
+        k2 = f(tuple(a + 0.5 * h * b for a, b in zip(y, k1)))
+        k3 = f(tuple(a + 0.5 * h * b for a, b in zip(y, k2)))
+        k4 = f(tuple(a + h * b for a, b in zip(y, k3)))
+        return tuple(a + h / 6.0 * (p + 2.0 * q + 2.0 * w + z)
+                     for a, p, q, w, z in zip(y, k1, k2, k3, k4))
+
+    y, now = (0.0, float(r0), dr0, 0.0), 0.0
+    out = np.empty((taus.size, 4))
+    for k, target in enumerate(taus):
+        while now < target:
+            h = min(step, target - now)
+            y = rk4(y, h)
+            now = target if h == target - now else now + h
+            if y[1] <= 1.05:
+                raise ValueError("the camera falls into the hole at tau = %.3f" % now)
+        out[k] = y
+    u = 1.0 / out[:, 1]
+    return OrbitState(taus, out[:, 0], out[:, 1], out[:, 3], out[:, 2], e / (1.0 - u),
+                      l * u * u)
+
+
+def orbit_position_velocity(st: OrbitState, chi: float) -> Tuple[np.ndarray, np.ndarray]:
+    """Cartesian position r (cos chi cos psi, sin psi, sin chi cos psi) of the orbit of
+    inclination chi, and the camera's velocity measured by the static observer, from its
+    radial and in-plane components (Appendix C, camera speed in the static orthonormal
+    basis) along the radial and psi unit vectors."""
+    c, s = math.cos(chi), math.sin(chi)
+    cp, sp = np.cos(st.psi), np.sin(st.psi)
+    rhat = np.stack([c * cp, sp, s * cp], axis=-1)
+    phat = np.stack([-c * sp, cp, -s * sp], axis=-1)
+    u = 1.0 / st.r
+    v_r = st.dr / ((1.0 - u) * st.dt)
+    v_psi = st.dpsi / (u * np.sqrt(1.0 - u) * st.dt)
+    return st.r[:, None] * rhat, v_r[:, None] * rhat + v_psi[:, None] * phat
+
+
+def orbit_views(r0: float, delta0: float, v0: float, chi: float, taus, width: int, height: int,
+                **kw) -> List[View]:
+    """Frames of a freely falling camera (Appendix C) at proper times `taus`, each aimed at
+    the hole's apparent direction; the view's `time` is the camera's coordinate time t,
+    which drives the animated disc."""
+    st = camera_orbit(r0, delta0, v0, taus)
+    pos, vel = orbit_position_velocity(st, chi)
+    out = []
+    for k in range(len(st.tau)):
+        v = aimed_view(pos[k], vel[k], width, height, **kw)
+        v.time = float(st.t[k])
+        out.append(v)
+    return out
+
+
+# ----------------------------------------------------------------------------------------
 # the workloads
 
 def small_static_view() -> View:
@@ -311,6 +422,59 @@ def serve_requests(rate: float = 200.0, duration: float = 60.0, seed: int = 4,
         v = aimed_view(r[k] * rhat, speed * tang, w, h,
                        disc_r_in=float(r_in[k]), disc_r_out=float(r_out[k]))
         out.append(Request(arrivals[k], v, int(field[k])))
+    return out
+
+
+def freefall_requests(rate: float = 200.0, duration: float = 60.0, seed: int = 5,
+                      sessions: int = 16, time_scale: float = 100.0,
+                      resolutions=SERVE_RESOLUTIONS, weights=SERVE_WEIGHTS) -> List[Request]:
+    """Poisson arrivals spread over `sessions` freely falling cameras (Appendix C), each on
+    a seeded bound orbit that stays within r in [4, 100]: r0 ~ U(8, 30), coordinate angle
+    delta0 ~ U(1.2, 1.9), speed v0 ~ U(0.95, 1.15) times the circular speed at r0,
+    inclination chi ~ U(-1.2, 1.2) and the orbital plane turned by a uniform angle about z.
+    A request's frame is the camera at proper time (arrival time x `time_scale`), aimed at
+    the hole, with the camera's coordinate time as the view's `time`; orbits that leave the
+    range are drawn again."""
+    rng = np.random.default_rng(seed)
+    t, arrivals = 0.0, []
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= duration:
+            break
+        arrivals.append(t)
+    n = len(arrivals)
+    owner = rng.integers(0, sessions, n)
+    res = rng.choice(len(resolutions), size=n, p=weights)
+    field = rng.integers(0, len(SERVE_FIELDS), n)
+    out: List[Optional[Request]] = [None] * n
+    grid = np.arange(0.0, duration * time_scale + 2.0, 2.0)
+    for k in range(sessions):
+        mine = np.nonzero(owner == k)[0]
+        while True:
+            r0 = rng.uniform(8.0, 30.0)
+            d0 = rng.uniform(1.2, 1.9)
+            u0 = 1.0 / r0
+            v0 = math.sqrt(u0 / (2.0 * (1.0 - u0))) * rng.uniform(0.95, 1.15)
+            chi, turn = rng.uniform(-1.2, 1.2), rng.uniform(0.0, 2.0 * math.pi)
+            r_in, r_out = rng.uniform(3.0, 6.0), rng.uniform(10.0, 30.0)
+            taus = np.array([arrivals[j] * time_scale for j in mine])
+            both = np.union1d(grid, taus)
+            try:
+                st = camera_orbit(r0, d0, v0, both)
+            except ValueError:
+                continue
+            if st.r.min() >= 4.0 and st.r.max() <= 100.0:
+                break
+        pos, vel = orbit_position_velocity(st, chi)
+        c, s = math.cos(turn), math.sin(turn)
+        rz = np.array([[c, -s, 0.0], [s, c, 0.0], [0.0, 0.0, 1.0]])
+        pos, vel = pos @ rz.T, vel @ rz.T
+        at = np.searchsorted(both, taus)
+        for j, i in zip(mine, at):
+            w, h = resolutions[res[j]]
+            v = aimed_view(pos[i], vel[i], w, h, disc_r_in=float(r_in), disc_r_out=float(r_out))
+            v.time = float(st.t[i])
+            out[j] = Request(arrivals[j], v, int(field[j]))
     return out
 
 
