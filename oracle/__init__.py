@@ -27,7 +27,9 @@ class OrcView(C.Structure):
                 ("time", C.c_double), ("disc_density", C.c_int32), ("n_particles", C.c_int32),
                 ("particles", C.POINTER(C.c_double)),
                 ("area", C.POINTER(C.c_double)), ("area_n0", C.c_int32),
-                ("area_exact", C.c_int32), ("k_area", C.c_double)]
+                ("area_exact", C.c_int32), ("k_area", C.c_double),
+                ("area_bands", C.c_int32), ("ct_n", C.c_int32 * 3),
+                ("ctable", C.POINTER(C.c_double))]
 
 
 class OrcRay(C.Structure):
@@ -46,7 +48,7 @@ PIXEL_DTYPE = np.dtype([
     ("captured", "<i4"), ("star_zeroed", "<i4"), ("degenerate", "<i4"), ("mip_level", "<i4"),
     ("pad0", "<i4"), ("pad1", "<i4"), ("t_ret", "<f8", 2), ("hit_az", "<f8", 2), ("density", "<f8", 2),
     ("area_rgb", "<f8", 3), ("area_A", "<f8"), ("area_T", "<f8"), ("area_exact_A", "<f8"),
-    ("area_exact_T", "<f8"),
+    ("area_exact_T", "<f8"), ("area_chroma", "<f8", 2),
 ])
 
 _lib = None
@@ -118,6 +120,19 @@ def lib():
         L.orc_area_build.argtypes = [fp, C.c_int32, dp]
         L.orc_area_filter.argtypes = [dp, C.c_int32, dp, dp, dp, dp, dp]
         L.orc_area_exact.argtypes = [dp, C.c_int32, dp, dp, dp, dp, dp]
+        L.orc_area_build_bands.argtypes = [fp, C.c_int32, dp]
+        L.orc_area_filter_bands.argtypes = [dp, C.c_int32, dp, dp, dp, dp]
+        L.orc_area_exact_bands.argtypes = [dp, C.c_int32, dp, dp, dp, dp]
+        L.orc_absorption.restype = C.c_double
+        L.orc_absorption.argtypes = [C.c_int, C.c_double]
+        L.orc_chroma_project.argtypes = [C.c_double, C.c_double, dp]
+        L.orc_band_cct.restype = C.c_double
+        L.orc_band_cct.argtypes = [C.c_double, C.c_double]
+        L.orc_spectrum_of.argtypes = [C.c_double, C.c_double, dp]
+        L.orc_color_shift.argtypes = [C.c_double, C.c_double, C.c_double, dp]
+        L.orc_cshift_table.argtypes = [C.c_int32, C.c_int32, C.c_int32, dp, C.c_int]
+        L.orc_cshift_lookup.argtypes = [dp, C.c_int32, C.c_int32, C.c_int32, C.c_double,
+                                        C.c_double, C.c_double, dp]
         L.orc_bloom.argtypes = [dp, C.c_int32, C.c_int32, C.c_int32, dp, dp]
         L.orc_tonemap.argtypes = [dp, C.c_int64, C.c_double, C.c_void_p, dp]
         for f in ("orc_sizeof_pixel", "orc_sizeof_ray", "orc_sizeof_view"):
@@ -342,6 +357,89 @@ def area_exact(levels, n0, d, dw, dh):
     return _area_call(lib().orc_area_exact, levels, n0, d, dw, dh)
 
 
+def area_levels_bands(rgbx: np.ndarray) -> np.ndarray:
+    """FP64 band-map levels, shape (texels, 3) = (R, G, B), from level-0 texels shaped
+    (6, n0, n0, 4) = (R, G, B, unused)."""
+    rgbx = np.ascontiguousarray(rgbx, np.float32)
+    n0 = rgbx.shape[1]
+    out = np.zeros((lib().orc_area_texels(n0), 3), np.float64)
+    if lib().orc_area_build_bands(rgbx.ctypes.data_as(C.POINTER(C.c_float)), n0, _dp(out)):
+        raise ValueError("orc_area_build_bands rejected the map")
+    return out
+
+
+def area_level_bands(levels: np.ndarray, n0: int, level: int) -> np.ndarray:
+    """View of one band-map level as (6, nL, nL, 3)."""
+    off = sum(6 * (n0 >> l) ** 2 for l in range(level))
+    nl = n0 >> level
+    return levels[off:off + 6 * nl * nl].reshape(6, nl, nl, 3)
+
+
+def _bands_call(fn, levels, n0, d, dw, dh):
+    a = [np.ascontiguousarray(x, np.float64) for x in (d, dw, dh)]
+    out = np.zeros(3)
+    fn(_dp(levels), n0, _dp(a[0]), _dp(a[1]), _dp(a[2]), _dp(out))
+    return out
+
+
+def area_filter_bands(levels, n0, d, dw, dh):
+    """The anisotropic filter on a band map: mean (R, G, B) over the footprint."""
+    return _bands_call(lib().orc_area_filter_bands, levels, n0, d, dw, dh)
+
+
+def area_exact_bands(levels, n0, d, dw, dh):
+    """Exact mean (R, G, B) of the level-0 band map over the footprint."""
+    return _bands_call(lib().orc_area_exact_bands, levels, n0, d, dw, dh)
+
+
+# ---- light of any colour under the Doppler shift (Section 3.4.2) ---------------------------
+
+CSHIFT_DIMS = (128, 128, 128)   # nodes in r, g and log2 D (D from 1/8 to 8)
+
+
+def absorption(k: int, lam: float) -> float:
+    return lib().orc_absorption(k, lam)
+
+
+def chroma_project(r: float, g: float):
+    out = np.zeros(2)
+    lib().orc_chroma_project(r, g, _dp(out))
+    return float(out[0]), float(out[1])
+
+
+def band_cct(r: float, g: float) -> float:
+    return lib().orc_band_cct(r, g)
+
+
+def spectrum_of(r: float, g: float):
+    """(T, a1, a2) of the spectrum B_T (1 - a1 A1 - a2 A2) chosen for chromaticity (r, g)."""
+    out = np.zeros(3)
+    lib().orc_spectrum_of(r, g, _dp(out))
+    return tuple(float(x) for x in out)
+
+
+def color_shift(r: float, g: float, D: float) -> np.ndarray:
+    """C_b(r, g, D): received band radiances per unit emitted band sum."""
+    out = np.zeros(3)
+    lib().orc_color_shift(r, g, D, _dp(out))
+    return out
+
+
+def cshift_table(nr: int = 128, ng: int = 128, nd: int = 128, nthreads: int = None) -> np.ndarray:
+    """log2 C_b at the table's nodes, shape (nr, ng, nd, 3)."""
+    out = np.zeros((nr, ng, nd, 3))
+    lib().orc_cshift_table(nr, ng, nd, _dp(out), nthreads or threads())
+    return out
+
+
+def cshift_lookup(tab: np.ndarray, r: float, g: float, D: float) -> np.ndarray:
+    nr, ng, nd = tab.shape[:3]
+    tab = np.ascontiguousarray(tab, np.float64)
+    out = np.zeros(3)
+    lib().orc_cshift_lookup(_dp(tab), nr, ng, nd, r, g, D, _dp(out))
+    return out
+
+
 def to_orc_view(v) -> OrcView:
     o = OrcView()
     o.r_s = v.r_s
@@ -367,10 +465,13 @@ def to_orc_view(v) -> OrcView:
 
 def render_quads(view, quads: np.ndarray, cube: np.ndarray = None, n0: int = 0,
                  tables: Tables = None, nthreads: int = None, march: int = 0,
-                 area: np.ndarray = None, area_n0: int = 0, area_exact: bool = False) -> np.ndarray:
+                 area: np.ndarray = None, area_n0: int = 0, area_exact: bool = False,
+                 area_bands: bool = False, ctable: np.ndarray = None) -> np.ndarray:
     """Render the 4 pixels of every quad (x0, y0); returns a PIXEL_DTYPE array (4 per quad).
     march > 0 replaces TraceRay by ray marching with at most that many steps.  area: levels
-    from area_levels (area_exact also fills the exact footprint means)."""
+    from area_levels (area_exact also fills the exact footprint means), or from
+    area_levels_bands with area_bands, whose colour shift reads `ctable` (cshift_table) or,
+    if None, is computed exactly."""
     q = np.ascontiguousarray(quads, np.int32)
     nq = q.shape[0]
     out = np.zeros(4 * nq, PIXEL_DTYPE)
@@ -381,6 +482,11 @@ def render_quads(view, quads: np.ndarray, cube: np.ndarray = None, n0: int = 0,
         ov.area_n0 = area_n0
         ov.area_exact = 1 if area_exact else 0
         ov.k_area = getattr(view, "k_area", 1.0)
+        ov.area_bands = 1 if area_bands else 0
+        if area_bands and ctable is not None:
+            ov._ct = np.ascontiguousarray(ctable, np.float64)
+            ov.ct_n[:] = list(ov._ct.shape[:3])
+            ov.ctable = _dp(ov._ct)
     if march > 0:
         rc = lib().orc_render_quads_m(C.byref(ov), _dp(cube) if cube is not None else None, n0,
                                       march, q.ctypes.data_as(C.POINTER(C.c_int32)), nq,

@@ -13,6 +13,8 @@
  * mean of its four children in both channels (a box pyramid of an intensive quantity, so
  * every level has the same map mean).  Layout as the star cubemap: level L after all lower
  * levels, ((face * nL + y) * nL + x) * 2 doubles; faces and (U, V) as in emission.c.
+ * Band maps (light of any colour, spectrum.c) hold the band radiances (R, G, B) per texel
+ * instead: 3 doubles per texel, the same pyramid and filters on all three channels.
  *
  * Footprint (reading).  The pixel's beam covers the parallelogram of directions
  * p(w, h) = d' + w d_w d' + h d_h d', (w, h) in [-1/2, 1/2]^2, with the same fine quad
@@ -70,6 +72,26 @@ static int64_t level_offset(int32_t n0, int L) {
   return off;
 }
 
+/* levels 1 .. of an nch-channel map whose level 0 is filled: box means of four children */
+static void build_mips(int32_t n0, int nch, double* levels) {
+  int nl = area_levels(n0);
+  for (int L = 1; L < nl; ++L) {
+    int32_t nc = n0 >> (L - 1), nL = n0 >> L;
+    const double* src = levels + nch * level_offset(n0, L - 1);
+    double* dst = levels + nch * level_offset(n0, L);
+    for (int f = 0; f < 6; ++f)
+      for (int32_t y = 0; y < nL; ++y)
+        for (int32_t x = 0; x < nL; ++x)
+          for (int c = 0; c < nch; ++c) {
+            double s = 0.0;
+            for (int dy = 0; dy < 2; ++dy)
+              for (int dx = 0; dx < 2; ++dx)
+                s += src[nch * (((int64_t)f * nc + 2 * y + dy) * nc + 2 * x + dx) + c];
+            dst[nch * (((int64_t)f * nL + y) * nL + x) + c] = 0.25 * s;
+          }
+  }
+}
+
 int orc_area_build(const float* it, int32_t n0, double* levels) {
   if (n0 < 1 || (n0 & (n0 - 1))) return 1;
   int64_t n = 6LL * n0 * n0;
@@ -79,22 +101,20 @@ int orc_area_build(const float* it, int32_t n0, double* levels) {
     levels[2 * t] = I;
     levels[2 * t + 1] = I * T;
   }
-  int nl = area_levels(n0);
-  for (int L = 1; L < nl; ++L) {
-    int32_t nc = n0 >> (L - 1), nL = n0 >> L;
-    const double* src = levels + 2 * level_offset(n0, L - 1);
-    double* dst = levels + 2 * level_offset(n0, L);
-    for (int f = 0; f < 6; ++f)
-      for (int32_t y = 0; y < nL; ++y)
-        for (int32_t x = 0; x < nL; ++x)
-          for (int c = 0; c < 2; ++c) {
-            double s = 0.0;
-            for (int dy = 0; dy < 2; ++dy)
-              for (int dx = 0; dx < 2; ++dx)
-                s += src[2 * (((int64_t)f * nc + 2 * y + dy) * nc + 2 * x + dx) + c];
-            dst[2 * (((int64_t)f * nL + y) * nL + x) + c] = 0.25 * s;
-          }
-  }
+  build_mips(n0, 2, levels);
+  return 0;
+}
+
+int orc_area_build_bands(const float* rgbx, int32_t n0, double* levels) {
+  if (n0 < 1 || (n0 & (n0 - 1))) return 1;
+  int64_t n = 6LL * n0 * n0;
+  for (int64_t t = 0; t < n; ++t)
+    for (int c = 0; c < 3; ++c) {
+      double v = rgbx[4 * t + c];
+      if (!(v >= 0.0) || isinf(v)) return 2;
+      levels[3 * t + c] = v;
+    }
+  build_mips(n0, 3, levels);
   return 0;
 }
 
@@ -110,16 +130,16 @@ static int face_of(const double* p, int* k, double* U, double* V) {
   return 2 * kk + (p[kk] < 0.0);
 }
 
-/* bilinear read of both channels of level L at direction p */
-static void bilinear(const double* levels, int32_t n0, int L, const double* p, double out[2]) {
+/* bilinear read of the nch channels of level L at direction p */
+static void bilinear(const double* levels, int nch, int32_t n0, int L, const double* p,
+                     double* out) {
   int k;
   double U, V;
   int f = face_of(p, &k, &U, &V);
   int32_t nL = n0 >> L;
-  const double* t = levels + 2 * (level_offset(n0, L) + (int64_t)f * nL * nL);
+  const double* t = levels + nch * (level_offset(n0, L) + (int64_t)f * nL * nL);
   if (nL == 1) {
-    out[0] = t[0];
-    out[1] = t[1];
+    for (int c = 0; c < nch; ++c) out[c] = t[c];
     return;
   }
   double x = 0.5 * (U + 1.0) * nL - 0.5, y = 0.5 * (V + 1.0) * nL - 0.5;
@@ -129,10 +149,11 @@ static void bilinear(const double* levels, int32_t n0, int L, const double* p, d
   if (i0 > nL - 2) i0 = nL - 2;
   if (j0 > nL - 2) j0 = nL - 2;
   double fx = x - i0, fy = y - j0;
-  for (int c = 0; c < 2; ++c) {
-    double a = t[2 * ((int64_t)j0 * nL + i0) + c], b = t[2 * ((int64_t)j0 * nL + i0 + 1) + c];
-    double d = t[2 * ((int64_t)(j0 + 1) * nL + i0) + c];
-    double e = t[2 * ((int64_t)(j0 + 1) * nL + i0 + 1) + c];
+  for (int c = 0; c < nch; ++c) {
+    double a = t[nch * ((int64_t)j0 * nL + i0) + c];
+    double b = t[nch * ((int64_t)j0 * nL + i0 + 1) + c];
+    double d = t[nch * ((int64_t)(j0 + 1) * nL + i0) + c];
+    double e = t[nch * ((int64_t)(j0 + 1) * nL + i0 + 1) + c];
     out[c] = (1.0 - fy) * ((1.0 - fx) * a + fx * b) + fy * ((1.0 - fx) * d + fx * e);
   }
 }
@@ -148,8 +169,8 @@ static double axis_texels(const double* d, const double* a, int32_t n0) {
   return 0.5 * n0 * sqrt(dU * dU + dV * dV);
 }
 
-void orc_area_filter(const double* levels, int32_t n0, const double* d, const double* dw,
-                     const double* dh, double* A, double* B) {
+static void filter_n(const double* levels, int nch, int32_t n0, const double* d,
+                     const double* dw, const double* dh, double* out) {
   int nl = area_levels(n0);
   double la = axis_texels(d, dw, n0), lb = axis_texels(d, dh, n0);
   const double *maj = dw, *mn = dh;
@@ -170,19 +191,30 @@ void orc_area_filter(const double* levels, int32_t n0, const double* d, const do
   int L0 = (int)floor(lam);
   int L1 = L0 + 1 < nl ? L0 + 1 : L0;
   double fr = lam - L0;
-  double sa = 0.0, sb = 0.0;
+  double sum[3] = {0.0, 0.0, 0.0};
   for (int a = 0; a < nmaj; ++a)
     for (int b = 0; b < nmin; ++b) {
       double ta = (a + 0.5) / nmaj - 0.5, tb = (b + 0.5) / nmin - 0.5;
-      double p[3], v0[2], v1[2];
+      double p[3], v0[3], v1[3];
       for (int i = 0; i < 3; ++i) p[i] = d[i] + ta * maj[i] + tb * mn[i];
-      bilinear(levels, n0, L0, p, v0);
-      bilinear(levels, n0, L1, p, v1);
-      sa += (1.0 - fr) * v0[0] + fr * v1[0];
-      sb += (1.0 - fr) * v0[1] + fr * v1[1];
+      bilinear(levels, nch, n0, L0, p, v0);
+      bilinear(levels, nch, n0, L1, p, v1);
+      for (int c = 0; c < nch; ++c) sum[c] += (1.0 - fr) * v0[c] + fr * v1[c];
     }
-  *A = sa / (nmaj * nmin);
-  *B = sb / (nmaj * nmin);
+  for (int c = 0; c < nch; ++c) out[c] = sum[c] / (nmaj * nmin);
+}
+
+void orc_area_filter(const double* levels, int32_t n0, const double* d, const double* dw,
+                     const double* dh, double* A, double* B) {
+  double o[2];
+  filter_n(levels, 2, n0, d, dw, dh, o);
+  *A = o[0];
+  *B = o[1];
+}
+
+void orc_area_filter_bands(const double* levels, int32_t n0, const double* d, const double* dw,
+                           const double* dh, double out[3]) {
+  filter_n(levels, 3, n0, d, dw, dh, out);
 }
 
 /* ---- exact footprint mean ------------------------------------------------------------ */
@@ -231,9 +263,9 @@ static void comp(const double* d, const double* dw, const double* dh, int i, dou
   c[2] = dh[i];
 }
 
-void orc_area_exact(const double* levels, int32_t n0, const double* d, const double* dw,
-                    const double* dh, double* A, double* B) {
-  double sa = 0.0, sb = 0.0;
+static void exact_n(const double* levels, int nch, int32_t n0, const double* d,
+                    const double* dw, const double* dh, double* out) {
+  double sum[3] = {0.0, 0.0, 0.0};
   poly sq = {4, {-0.5, 0.5, 0.5, -0.5}, {-0.5, -0.5, 0.5, 0.5}};
   for (int f = 0; f < 6; ++f) {
     int k = f / 2, a = (k + 1) % 3, b = (k + 2) % 3;
@@ -269,7 +301,7 @@ void orc_area_exact(const double* levels, int32_t n0, const double* d, const dou
     if (j0 < 0) j0 = 0;
     if (i1 > n0 - 1) i1 = n0 - 1;
     if (j1 > n0 - 1) j1 = n0 - 1;
-    const double* tex = levels + 2 * (int64_t)f * n0 * n0;
+    const double* tex = levels + nch * (int64_t)f * n0 * n0;
     for (int32_t i = i0; i <= i1; ++i) {
       /* column i: (2i/n0 - 1) s p_k <= p_a <= (2(i+1)/n0 - 1) s p_k; the outermost columns
          reach the face edge, already enforced */
@@ -297,12 +329,23 @@ void orc_area_exact(const double* levels, int32_t n0, const double* d, const dou
         }
         if (R.n < 3) continue;
         double ar = area_of(&R);
-        const double* t = tex + 2 * ((int64_t)j * n0 + i);
-        sa += ar * t[0];
-        sb += ar * t[1];
+        const double* t = tex + nch * ((int64_t)j * n0 + i);
+        for (int c = 0; c < nch; ++c) sum[c] += ar * t[c];
       }
     }
   }
-  *A = sa;
-  *B = sb;
+  for (int c = 0; c < nch; ++c) out[c] = sum[c];
+}
+
+void orc_area_exact(const double* levels, int32_t n0, const double* d, const double* dw,
+                    const double* dh, double* A, double* B) {
+  double o[2];
+  exact_n(levels, 2, n0, d, dw, dh, o);
+  *A = o[0];
+  *B = o[1];
+}
+
+void orc_area_exact_bands(const double* levels, int32_t n0, const double* d, const double* dw,
+                          const double* dh, double out[3]) {
+  exact_n(levels, 3, n0, d, dw, dh, out);
 }

@@ -54,6 +54,12 @@ typedef struct {
   int32_t area_n0;
   int32_t area_exact;     /* 1: also compute the exact footprint mean (diagnostic) */
   double k_area;
+  /* 1: `area` is a band map (orc_area_build_bands), shifted with C(rg, D) (Section 3.4.2):
+     through the table `ctable` of ct_n[0] x ct_n[1] x ct_n[2] nodes (orc_cshift_table), or
+     exactly (orc_color_shift) if ctable is NULL */
+  int32_t area_bands;
+  int32_t ct_n[3];
+  const double* ctable;
 } orc_view;
 
 /* Result of tracing one ray in its orbital plane. */
@@ -99,6 +105,7 @@ typedef struct {
                              transmittance) */
   double area_A, area_T;  /* filtered radiance and colour temperature of the footprint */
   double area_exact_A, area_exact_T;  /* the exact footprint mean (if area_exact) */
+  double area_chroma[2];  /* band maps: the footprint's (r, g); area_A is its band sum */
 } orc_pixel;
 
 /* ---- geometry of rays (Section 3.3.1) --------------------------------------------- */
@@ -153,6 +160,23 @@ void orc_area_filter(const double* levels, int32_t n0, const double* d, const do
                      const double* dh, double* A, double* B);   /* the anisotropic filter */
 void orc_area_exact(const double* levels, int32_t n0, const double* d, const double* dw,
                     const double* dh, double* A, double* B);    /* the exact mean, level 0 */
+/* band maps: rgbx level-0 (R, G, B, unused) per texel; levels: orc_area_texels * 3 */
+int orc_area_build_bands(const float* rgbx, int32_t n0, double* levels);
+void orc_area_filter_bands(const double* levels, int32_t n0, const double* d, const double* dw,
+                           const double* dh, double out[3]);
+void orc_area_exact_bands(const double* levels, int32_t n0, const double* d, const double* dw,
+                          const double* dh, double out[3]);
+
+/* ---- light of any colour under the Doppler shift (Section 3.4.2, spectrum.c) --------- */
+double orc_absorption(int k, double lambda);         /* A1 (k = 0), A2 (k = 1) */
+void orc_chroma_project(double r, double g, double out[2]);
+double orc_band_cct(double r, double g);             /* correlated temperature (K) */
+void orc_spectrum_of(double r, double g, double out[3]);       /* (T, a1, a2) */
+void orc_color_shift(double r, double g, double D, double out[3]);  /* C_b(r, g, D) */
+/* table of log2 C_b, ((i ng + j) nd + k) * 3 doubles, and its trilinear lookup */
+void orc_cshift_table(int32_t nr, int32_t ng, int32_t nd, double* out, int nthreads);
+void orc_cshift_lookup(const double* tab, int32_t nr, int32_t ng, int32_t nd, double r,
+                       double g, double D, double out[3]);
 
 /* ---- whole pixels --------------------------------------------------------------------- */
 /* quads: (x0, y0) pairs with even coordinates; out: 4 pixels per quad in the order

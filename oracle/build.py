@@ -6,7 +6,7 @@ import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["quad.c", "geodesic.c", "tables.c", "emission.c", "render.c", "animate.c", "march.c", "bloom.c", "tonemap.c", "area.c"]
+SOURCES = ["quad.c", "geodesic.c", "tables.c", "emission.c", "render.c", "animate.c", "march.c", "bloom.c", "tonemap.c", "area.c", "spectrum.c"]
 LIB = os.path.join(HERE, "liboracle.so")
 
 

@@ -6,6 +6,9 @@ typedef double (*orc_fn)(double x, void* ctx);
 
 /* adaptive Gauss-Legendre integral of f over [a, b] to relative tolerance rel_tol */
 double orc_integrate(orc_fn f, void* ctx, double a, double b, double rel_tol);
+/* the same 12-point Gauss-Legendre rule on `panels` equal panels (no adaptivity: for
+   integrands that may cancel, where a relative tolerance has nothing to hold on to) */
+double orc_integrate_panels(orc_fn f, void* ctx, double a, double b, int panels);
 
 /* integrate the orbit equation from (u0, w0 = du/dphi) at phi = 0; shared by the
  * per-pixel trace and the deflection of rays from infinity */

@@ -71,6 +71,13 @@ double orc_integrate(orc_fn f, void* ctx, double a, double b, double rel_tol) {
   return adapt(f, ctx, a, b, whole, tol, 1e-15 * fabs(whole), 0);
 }
 
+double orc_integrate_panels(orc_fn f, void* ctx, double a, double b, int panels) {
+  pthread_once(&gl_once, gl_init);
+  double s = 0.0, h = (b - a) / panels;
+  for (int i = 0; i < panels; ++i) s += gl_rule(f, ctx, a + i * h, a + (i + 1) * h);
+  return s;
+}
+
 static double poly(double x, void* ctx) { return pow(x, *(int*)ctx); }
 
 double orc_quad_poly_check(int degree) {

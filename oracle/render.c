@@ -47,8 +47,11 @@
  *   term is zero for the whole quad.
  * Area sources (area.c): the same quad differences give the footprint; the filtered
  *   (A, B) = mean (I, I T) give area colour_b = k_area A L_b(D_cam T_pix) / sum_b L_b(T_pix),
- *   without Omega/Omega'; zero for a quad with a captured member, as for stars.  Both sky
- *   terms are seen through the disc's remaining transmittance.
+ *   without Omega/Omega'; zero for a quad with a captured member, as for stars.  Band maps
+ *   (spectrum.c) filter (R, G, B) instead; the footprint's band sum S and chromaticity
+ *   (r, g) = (R, G) / S give colour_b = k_area S C_b(r, g, D_cam), from the C table
+ *   (table mode) or computed exactly.  Both sky terms are seen through the disc's
+ *   remaining transmittance.
  */
 #include <math.h>
 #include <pthread.h>
@@ -349,21 +352,42 @@ static void shade_quad(const ctx_t* c, int32_t x0, int32_t y0, orc_pixel* out) {
         dw[i] = r[mw1].dprime[i] - r[mw0].dprime[i];
         dh[i] = r[mh1].dprime[i] - r[mh0].dprime[i];
       }
-      orc_area_filter(v->area, v->area_n0, o->dprime, dw, dh, &A, &B);
-      p->area_A = A;
-      if (A > 0.0) {
-        double Tpix = B / A, Lr[3], Ln[3];
-        p->area_T = Tpix;
-        orc_band_radiance(o->d_cam * Tpix, Lr);
-        orc_band_radiance(Tpix, Ln);
-        double norm = Ln[0] + Ln[1] + Ln[2];
-        if (norm > 0.0)
-          for (int b = 0; b < 3; ++b) p->area_rgb[b] = v->k_area * A * Lr[b] / norm;
-      }
-      if (v->area_exact) {
-        orc_area_exact(v->area, v->area_n0, o->dprime, dw, dh, &A, &B);
-        p->area_exact_A = A;
-        p->area_exact_T = A > 0.0 ? B / A : 0.0;
+      if (v->area_bands) {
+        double mb[3];
+        orc_area_filter_bands(v->area, v->area_n0, o->dprime, dw, dh, mb);
+        double S = mb[0] + mb[1] + mb[2], C[3];
+        p->area_A = S;
+        if (S > 0.0) {
+          p->area_chroma[0] = mb[0] / S;
+          p->area_chroma[1] = mb[1] / S;
+          if (v->ctable)
+            orc_cshift_lookup(v->ctable, v->ct_n[0], v->ct_n[1], v->ct_n[2], mb[0] / S,
+                              mb[1] / S, o->d_cam, C);
+          else
+            orc_color_shift(mb[0] / S, mb[1] / S, o->d_cam, C);
+          for (int b = 0; b < 3; ++b) p->area_rgb[b] = v->k_area * S * C[b];
+        }
+        if (v->area_exact) {
+          orc_area_exact_bands(v->area, v->area_n0, o->dprime, dw, dh, mb);
+          p->area_exact_A = mb[0] + mb[1] + mb[2];
+        }
+      } else {
+        orc_area_filter(v->area, v->area_n0, o->dprime, dw, dh, &A, &B);
+        p->area_A = A;
+        if (A > 0.0) {
+          double Tpix = B / A, Lr[3], Ln[3];
+          p->area_T = Tpix;
+          orc_band_radiance(o->d_cam * Tpix, Lr);
+          orc_band_radiance(Tpix, Ln);
+          double norm = Ln[0] + Ln[1] + Ln[2];
+          if (norm > 0.0)
+            for (int b = 0; b < 3; ++b) p->area_rgb[b] = v->k_area * A * Lr[b] / norm;
+        }
+        if (v->area_exact) {
+          orc_area_exact(v->area, v->area_n0, o->dprime, dw, dh, &A, &B);
+          p->area_exact_A = A;
+          p->area_exact_T = A > 0.0 ? B / A : 0.0;
+        }
       }
     }
     for (int b = 0; b < 3; ++b)

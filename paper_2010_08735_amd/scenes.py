@@ -146,6 +146,38 @@ def area_map(n0: int, seed: int, blobs: int = 24, sigma_lo: float = 0.10,
     return out
 
 
+def area_map_bands(n0: int, seed: int, blobs: int = 24, sigma_lo: float = 0.10,
+                   sigma_hi: float = 0.35) -> np.ndarray:
+    """Level-0 texels of a band-colour sky, float32 (6, n0, n0, 4) = (R, G, B, 0): the same
+    Gaussian patches as `area_map`, each with a colour of chromaticity r ~ U(0.2, 0.5),
+    g ~ U(0.22, 0.42), b = 1 - r - g (colours on and off the blackbody locus), over a
+    floor of 0.02 in each band."""
+    rng = np.random.default_rng(seed)
+    z = rng.uniform(-1.0, 1.0, blobs)
+    az = rng.uniform(0.0, 2.0 * math.pi, blobs)
+    sig = rng.uniform(sigma_lo, sigma_hi, blobs)
+    peak = 10.0 ** rng.uniform(-1.0, 0.0, blobs)
+    r = rng.uniform(0.2, 0.5, blobs)
+    g = rng.uniform(0.22, 0.42, blobs)
+    col = np.stack([r, g, 1.0 - r - g], axis=1)          # (blobs, 3)
+    s = np.sqrt(np.maximum(0.0, 1.0 - z * z))
+    centres = np.stack([s * np.cos(az), s * np.sin(az), z], axis=1)
+    c = (np.arange(n0) + 0.5) * (2.0 / n0) - 1.0
+    uu, vv = np.meshgrid(c, c, indexing="xy")          # [y, x]
+    out = np.zeros((6, n0, n0, 4), np.float32)
+    for f in range(6):
+        k, sgn = f // 2, (-1.0 if f % 2 else 1.0)
+        d = np.zeros((n0, n0, 3))
+        d[..., k] = sgn
+        d[..., (k + 1) % 3] = uu
+        d[..., (k + 2) % 3] = vv
+        d /= np.linalg.norm(d, axis=-1, keepdims=True)
+        ang = np.arccos(np.clip(d @ centres.T, -1.0, 1.0))  # (n0, n0, blobs)
+        gw = peak * np.exp(-0.5 * (ang / sig) ** 2)
+        out[f, ..., :3] = 0.02 + gw @ col
+    return out
+
+
 # ----------------------------------------------------------------------------------------
 # camera placement helpers (input recipe only)
 

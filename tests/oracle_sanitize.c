@@ -119,6 +119,30 @@ int main(void) {
   for (int i = 0; i < 4 * nq; ++i) FINITE(px[i].rgb[0] + px[i].area_exact_A);
   free(area);
 
+  /* band maps and the colour shift (exact and through a small table, several threads) */
+  float rgbx[6 * 8 * 8 * 4];
+  for (int i = 0; i < 6 * 8 * 8; ++i) {
+    rgbx[4 * i] = 0.2f + (float)(i % 7) * 0.03f;
+    rgbx[4 * i + 1] = 0.25f + (float)(i % 3) * 0.05f;
+    rgbx[4 * i + 2] = 0.15f + (float)(i % 11) * 0.02f;
+    rgbx[4 * i + 3] = 0.0f;
+  }
+  double* bands = calloc((size_t)orc_area_texels(8) * 3, sizeof(double));
+  if (orc_area_build_bands(rgbx, 8, bands)) bad = 1;
+  double cs[3];
+  orc_color_shift(0.3, 0.35, 1.7, cs);
+  FINITE(cs[0] + cs[1] + cs[2]);
+  double* ctab = calloc(5 * 5 * 5 * 3, sizeof(double));
+  orc_cshift_table(5, 5, 5, ctab, 3);
+  v.area = bands;
+  v.area_bands = 1;
+  v.ct_n[0] = v.ct_n[1] = v.ct_n[2] = 5;
+  v.ctable = ctab;
+  if (orc_render_quads(&v, cube, N0, D, dn, U, ne, nphi, quads, nq, px, 4)) bad = 1;
+  for (int i = 0; i < 4 * nq; ++i) FINITE(px[i].rgb[0] + px[i].area_exact_A);
+  free(bands);
+  free(ctab);
+
   /* post-process */
   double img[8 * 8 * 4], out[8 * 8 * 4], w[4] = {0.7, 0.2, 0.07, 0.03};
   for (int i = 0; i < 8 * 8 * 4; ++i) img[i] = (i % 7) * 0.1;

@@ -12,7 +12,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2010_08735_amd", "csrc")
 ORACLE = os.path.join(ROOT, "oracle")
 ORACLE_SOURCES = ["quad.c", "geodesic.c", "tables.c", "emission.c", "render.c", "animate.c",
-                  "march.c", "bloom.c", "tonemap.c", "area.c"]
+                  "march.c", "bloom.c", "tonemap.c", "area.c", "spectrum.c"]
 
 SCENARIOS = ["fifo_order", "continuous_batching", "admission_by_budget",
              "eagain_when_queue_full", "launch_failure_is_contained", "cancel_on_stop",

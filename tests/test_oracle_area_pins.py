@@ -262,3 +262,90 @@ def test_area_light_in_the_render(orc):
         ref = v.k_area * I * _band_ref(orc, p["d_cam"] * T) / norm
         assert np.allclose(p["area_rgb"], ref, rtol=1e-9, atol=0)
         assert np.allclose(p["rgb"], p["area_rgb"], rtol=1e-12)   # transparent disc, no stars
+
+
+# ---- band maps: (R, G, B) per texel, shifted with the colour-shift table (Section 3.4.2) ----
+
+def _random_band_map(n0, seed):
+    rng = np.random.default_rng(seed)
+    m = np.zeros((6, n0, n0, 4), np.float32)
+    m[..., :3] = rng.uniform(0.05, 1.5, (6, n0, n0, 3))
+    m[..., 3] = rng.uniform(-5.0, 5.0, (6, n0, n0))   # ignored
+    return m
+
+
+def test_band_map_mips_are_block_means(orc):
+    m = _random_band_map(8, 11)
+    lv = orc.area_levels_bands(m)
+    a = m[..., :3].astype(np.float64)
+    for L in range(4):
+        assert np.allclose(orc.area_level_bands(lv, 8, L), a, rtol=1e-12, atol=0)
+        n = a.shape[1] // 2
+        if n:
+            a = a.reshape(6, n, 2, n, 2, 3).mean(axis=(2, 4))
+
+
+def test_band_filter_and_exact_mean_act_on_each_band(orc):
+    """The band filter and exact mean are the same linear operators as on the (I, I T)
+    maps, applied to each band: a band map whose channels are copies of the radiance and
+    of I T channels gives the same numbers."""
+    n0 = 8
+    it = _random_map(n0, 12)
+    lv2 = orc.area_levels(it)
+    m = np.zeros((6, n0, n0, 4), np.float32)
+    m[..., 0] = it[..., 0]
+    m[..., 1] = it[..., 0] * it[..., 1] * 1e-4
+    m[..., 2] = it[..., 0]
+    lv3 = orc.area_levels_bands(m)
+    rng = np.random.default_rng(13)
+    for _ in range(20):
+        d, dw, dh = _footprint(rng, n0, 0.2, 8.0, 4.0)
+        A, B = orc.area_filter(lv2, n0, d, dw, dh)
+        f = orc.area_filter_bands(lv3, n0, d, dw, dh)
+        assert f[0] == pytest.approx(A, rel=1e-12) and f[2] == pytest.approx(A, rel=1e-12)
+        assert f[1] == pytest.approx(B * 1e-4, rel=1e-6)    # I T rounded to float32 in m
+        A, B = orc.area_exact(lv2, n0, d, dw, dh)
+        e = orc.area_exact_bands(lv3, n0, d, dw, dh)
+        assert e[0] == pytest.approx(A, rel=1e-12) and e[2] == pytest.approx(A, rel=1e-12)
+
+
+def test_band_sky_in_the_render(orc):
+    """A uniform band sky (R, G, B): every lit pixel reads its band sum and chromaticity
+    back and receives k_area S C(r, g, D_cam), exactly (no table) or from the table; a
+    blackbody-coloured sky receives what the temperature map gives."""
+    n0 = 16
+    rgb = np.array([0.3, 0.45, 0.25])
+    m = np.zeros((6, n0, n0, 4), np.float32)
+    m[..., :3] = rgb
+    lv = orc.area_levels_bands(m)
+    rgb = m[0, 0, 0, :3].astype(np.float64)
+    S = rgb.sum()
+    v = scenes.aimed_view(np.array([0.0, -15.0, 2.0]), np.array([0.3, 0.2, 0.0]), 32, 32,
+                          fov_y=math.radians(60), disc_opacity=0.0)
+    v.k_area = 2.0
+    q = scenes.all_quads(32, 32)
+    px = orc.render_quads(v, q, area=lv, area_n0=n0, area_bands=True)
+    lit = px["star_zeroed"] == 0
+    assert lit.sum() > 100 and (~lit).sum() > 10
+    assert np.allclose(px["area_A"][lit], S, rtol=1e-12)
+    assert np.allclose(px["area_chroma"][lit], rgb[:2] / S, rtol=1e-12)
+    assert np.all(px["area_rgb"][~lit] == 0)
+    for p in px[lit][::23]:
+        ref = v.k_area * S * orc.color_shift(rgb[0] / S, rgb[1] / S, p["d_cam"])
+        assert np.allclose(p["area_rgb"], ref, rtol=1e-12, atol=0)
+    tab = orc.cshift_table(9, 9, 9)
+    pt = orc.render_quads(v, q, area=lv, area_n0=n0, area_bands=True, ctable=tab)
+    for p in pt[lit][::23]:
+        ref = v.k_area * S * orc.cshift_lookup(tab, rgb[0] / S, rgb[1] / S, p["d_cam"])
+        assert np.allclose(p["area_rgb"], ref, rtol=1e-12, atol=0)
+    # a blackbody sky as a band map: the exact shift equals the temperature map's light
+    T = 5000.0
+    L = _band_ref(orc, T)
+    mb = np.zeros((6, n0, n0, 4), np.float32)
+    mb[..., :3] = (0.5 * L / L.sum()).astype(np.float32)
+    it = np.empty((6, n0, n0, 2), np.float32)
+    it[..., 0] = mb[0, 0, 0, :3].astype(np.float64).sum()
+    it[..., 1] = T
+    pb = orc.render_quads(v, q, area=orc.area_levels_bands(mb), area_n0=n0, area_bands=True)
+    pT = orc.render_quads(v, q, area=orc.area_levels(it), area_n0=n0)
+    assert np.allclose(pb["area_rgb"][lit], pT["area_rgb"][lit], rtol=2e-6, atol=0)
