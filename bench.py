@@ -493,6 +493,21 @@ def main():
                          "ms_per_frame": 1e3 * rwall / n_ar, "kernel_ms": float(rkms),
                          "mpx_per_s": W * H * n_ar / rwall / 1e6}
         bh.bh_release_area(ah)
+        # the same sky as band colours (light of any colour, Section 3.4.2): the footprint's
+        # (R, G, B) mean, shifted through the colour-shift table (built with the map)
+        tex = torch.from_numpy(scenes.area_map_bands(n_area, 21)).cuda()
+        t0 = time.perf_counter()
+        ah = bh.bh_build_area_bands(ctx, tex.data_ptr(), n_area, bh.current_stream())
+        torch.cuda.synchronize()
+        build_s = time.perf_counter() - t0
+        del tex
+        rwall, rkms, _ = plain_leg(bh, ctx, tables, bh.make_view(sv, stars, None, ah), n_ar,
+                                   args.warmup)
+        extra["area"]["bands"] = {"map_bytes": 16 * (8 * n_area * n_area - 2),
+                                  "build_with_color_shift_table_s": build_s,
+                                  "ms_per_frame": 1e3 * rwall / n_ar, "kernel_ms": float(rkms),
+                                  "mpx_per_s": W * H * n_ar / rwall / 1e6}
+        bh.bh_release_area(ah)
         log("area:", json.dumps(extra["area"]))
     if "bloom" in legs:
         extra["bloom"] = bloom_leg(bh, scenes, ctx, out, W, H)

@@ -213,8 +213,31 @@ typedef struct bh_area bh_area;
  * work still reads). */
 bh_status bh_build_area(bh_ctx* ctx, const float* texels_dev, int32_t face_size,
                         void* hip_stream, bh_area** out);
-/* Copy mip level `level` as float (face, y, x, [I, I T]) to host_texels
- * (6 * (face_size >> level)^2 * 2 floats).  Blocking. */
+/* Light of any colour (Section 3.4.2, the colour-shift table C(xy, D)): an area map whose
+ * texels hold band radiances (R, G, B) instead of (I, T).  A pixel receives
+ * k_area x S x C_b(r, g, D_cam), S the footprint mean of R + G + B and (r, g) its
+ * chromaticity (R, G) / S, from a table of the received band radiances per unit emitted
+ * band sum.  Each chromaticity stands for one spectrum B_T (1 - a1 A1 - a2 A2): T the
+ * blackbody temperature with the same blue-to-red band ratio (1e3 .. 1e6 K), A1, A2
+ * Gaussian absorption bands at 450 and 650 nm (width 30 nm), a1, a2 in [-8, 1] fixed by
+ * the chromaticity; its received spectrum is D^5 I(D lambda).  Blackbody colours shift
+ * exactly as the (I, T) maps do (up to the table's interpolation).  The table has
+ * BH_CSHIFT_N^3 nodes, r = i / (N - 1), g = j / (N - 1), log2 D = -3 + 6 k / (N - 1), and
+ * holds log2 C_b (each C_b at least 2^-100); it is read trilinearly, linearly in 1 / D
+ * along D, coordinates clamped; it is built on the device (FP64 quadrature) with a
+ * context's first band map and kept until bh_destroy (32 MiB, counted in the budget).
+ * rgbx_dev: device array of 6 * face_size^2 float4 (R, G, B, unused), laid out as in
+ * bh_build_area, R, G, B >= 0 finite.  Otherwise as bh_build_area (mips are box means of
+ * R, G and B); released with bh_release_area. */
+#define BH_CSHIFT_N 128
+bh_status bh_build_area_bands(bh_ctx* ctx, const float* rgbx_dev, int32_t face_size,
+                              void* hip_stream, bh_area** out);
+/* Copy the colour-shift table to host (BH_CSHIFT_N^3 float4 (log2 C_R, log2 C_G, log2 C_B,
+ * 0), node ((i N + j) N + k)), building it first if the context has none.  Blocking. */
+bh_status bh_color_shift_table_download(bh_ctx* ctx, float* host);
+/* Copy mip level `level` to host_texels: (face, y, x, [I, I T]), 6 * (face_size >>
+ * level)^2 * 2 floats, or for a band map (face, y, x, [R, G, B, 0]), 4 floats per texel.
+ * Blocking. */
 bh_status bh_area_download(const bh_area* area, int32_t level, float* host_texels);
 bh_status bh_release_area(bh_area* area);
 

@@ -28,7 +28,8 @@ EXPORTS = [
     "bh_bloom_create", "bh_bloom_apply", "bh_bloom_release", "bh_bloom_apply_display",
     "bh_tonemap",
     "bh_build_stars", "bh_stars_download", "bh_release_stars",
-    "bh_build_area", "bh_area_download", "bh_release_area",
+    "bh_build_area", "bh_build_area_bands", "bh_color_shift_table_download",
+    "bh_area_download", "bh_release_area",
     "bh_render", "bh_render_march", "bh_render_batch", "bh_render_batch_noalloc",
     "bh_tile_config_count", "bh_tile_config_get",
     "bh_set_tile_config", "bh_set_batch_form", "bh_autotune",
@@ -100,6 +101,8 @@ def lib():
             "bh_stars_download": ([vp, i32, vp], i32),
             "bh_release_stars": ([vp], i32),
             "bh_build_area": ([vp, vp, i32, vp, C.POINTER(vp)], i32),
+            "bh_build_area_bands": ([vp, vp, i32, vp, C.POINTER(vp)], i32),
+            "bh_color_shift_table_download": ([vp, vp], i32),
             "bh_area_download": ([vp, i32, vp], i32),
             "bh_release_area": ([vp], i32),
             "bh_render": ([vp, vp, C.POINTER(View), vp, vp, vp], i32),
@@ -222,6 +225,19 @@ def bh_build_area(ctx, texels_ptr, face_size, stream=None) -> int:
     out = C.c_void_p()
     _check(lib().bh_build_area(ctx, texels_ptr, face_size, stream, C.byref(out)))
     return out.value
+
+
+def bh_build_area_bands(ctx, rgbx_ptr, face_size, stream=None) -> int:
+    out = C.c_void_p()
+    _check(lib().bh_build_area_bands(ctx, rgbx_ptr, face_size, stream, C.byref(out)))
+    return out.value
+
+
+BH_CSHIFT_N = 128
+
+
+def bh_color_shift_table_download(ctx, host_ptr) -> None:
+    _check(lib().bh_color_shift_table_download(ctx, host_ptr))
 
 
 def bh_area_download(area, level, host_ptr) -> None:

@@ -10,7 +10,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libbh.so")
 SOURCES = ["precompute.hip", "band.hip", "stars.hip", "render.hip", "bloom.hip", "probe.hip",
-           "area.hip", "libbh.cpp"]
+           "area.hip", "cshift.hip", "libbh.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed FP32 instructions are kept out of the device code (-packed-fp32-ops).  FP32

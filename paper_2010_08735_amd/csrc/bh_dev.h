@@ -55,15 +55,25 @@ struct StarsDev {
 // (I, I T) per texel: radiance and radiance-weighted colour temperature; level L (size
 // n0 >> L, n0 a power of two) starts at texel 8 (n0^2 - nL^2), within it face-major rows.
 struct AreaDev {
-  const float2* tex;      // null: no area map
+  const void* tex;        // null: no area map; float2 (I, I T) texels, or float4 (R, G, B, 0)
   int n0, levels;
   float k_area;
-  int pad[3];
+  int bands;              // 1: band texels, received through the colour-shift table `ctab`
+  const float4* ctab;     // log2 C_b at kCshiftN^3 nodes (cshift.hip)
+};
+
+// Colour-shift table (Section 3.4.2): nodes per axis (r, g, log2 D over [-3, 3])
+constexpr int kCshiftN = 128;
+
+// Gauss-Legendre nodes and weights on [-1, 1] for the table's band integrals
+struct CshiftRule {
+  double x[8], w[8];
 };
 
 // Optional per-view work the render kernels are specialised for (a kernel without a
 // feature carries none of its code or registers): a particle disc, an area-source map.
-constexpr int kFeatParticles = 1, kFeatArea = 2;
+// kFeatBands: an area map of band colours (always with kFeatArea).
+constexpr int kFeatParticles = 1, kFeatArea = 2, kFeatBands = 4;
 
 // ---- per-view constant block (host computes it in FP64 from bh_view) -----------------
 // The camera axes and the velocity direction are passed split into their parts transverse
@@ -99,7 +109,8 @@ struct ViewDev {
 
 // the features a view uses
 __host__ __device__ inline int view_features(const ViewDev& v) {
-  return (v.density_mode != 0 ? kFeatParticles : 0) | (v.area.tex ? kFeatArea : 0);
+  return (v.density_mode != 0 ? kFeatParticles : 0) | (v.area.tex ? kFeatArea : 0) |
+         (v.area.tex && v.area.bands ? kFeatBands : 0);
 }
 
 // Bloom launch record: the image's box pyramid, levels 0 (the image) .. levels <= 16, and

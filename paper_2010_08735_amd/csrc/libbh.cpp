@@ -45,6 +45,9 @@ hipError_t launch_star_unpack(const void* in, int64_t count, float scale, int fp
 hipError_t launch_render(int cfg, const ViewDev& v, const TablesDev& T, const LutDev& L,
                          hipStream_t s);
 hipError_t launch_area_build(const float* it, int n0, float2* tex, int* bad, hipStream_t s);
+hipError_t launch_area_build_bands(const float* rgbx, int n0, float4* tex, int* bad,
+                                   hipStream_t s);
+hipError_t launch_cshift_build(const CshiftRule& q, double4* spec, float4* tab, hipStream_t s);
 hipError_t launch_render_batch(int cfg, int persistent, int feat, const ViewDev* views,
                                const TileRun* runs, int nruns, int ntiles, int* counter,
                                const TablesDev& T, const LutDev& L, int grid, hipStream_t s);
@@ -163,8 +166,9 @@ struct bh_stars {
 
 struct bh_area {
   bh_ctx* ctx;
-  float2* tex = nullptr;  // (I, I T), all levels (see area.hip)
+  void* tex = nullptr;    // all levels (see area.hip): float2 (I, I T), or float4 (R, G, B, 0)
   int n0 = 0, levels = 0;
+  int bands = 0;
   size_t bytes = 0;
 };
 
@@ -189,6 +193,7 @@ struct bh_ctx {
   std::set<bh_area*> areas;
   std::set<bh_bloom*> blooms;
   float4* lut = nullptr;
+  float4* ctab = nullptr;  // colour-shift table, built with the first band map
   int lut_n = 4096;
   float lut_x0 = 6.0f, lut_dx = 15.0f / 4095.0f;
   int tile_cfg = 0;
@@ -368,6 +373,7 @@ extern "C" void bh_destroy(bh_ctx* c) {
     delete p;
   }
   dev_free(c, c->lut, 0);
+  dev_free(c, c->ctab, 0);
   dev_free(c, c->b_counter, 0);
   dev_free(c, c->b_views, 0);
   dev_free(c, c->b_runs, 0);
@@ -860,13 +866,72 @@ extern "C" bh_status bh_release_stars(bh_stars* s) {
 
 // ---- area sources ----------------------------------------------------------------------------
 
-extern "C" bh_status bh_build_area(bh_ctx* c, const float* texels, int32_t n0, void* stream,
-                                   bh_area** out) {
+// 8-point Gauss-Legendre rule on [-1, 1]: the roots of P_8 by Newton's method from
+// x = cos(pi (i + 3/4) / (n + 1/2)), weights 2 / ((1 - x^2) P_8'(x)^2)
+static CshiftRule gauss_legendre8() {
+  CshiftRule q;
+  const int n = 8;
+  for (int i = 0; i < n; ++i) {
+    double x = std::cos(M_PI * (i + 0.75) / (n + 0.5)), dp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = x;
+      for (int k = 2; k <= n; ++k) {
+        const double pk = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = pk;
+      }
+      dp = n * (x * p1 - p0) / (x * x - 1.0);
+      const double dx = p1 / dp;
+      x -= dx;
+      if (std::fabs(dx) < 1e-16) break;
+    }
+    q.x[i] = x;
+    q.w[i] = 2.0 / ((1.0 - x * x) * dp * dp);
+  }
+  return q;
+}
+
+// the colour-shift table of this context, built on first use (the caller holds no lock)
+static bh_status ensure_cshift(bh_ctx* c, hipStream_t hs) {
+  static std::mutex build_mu;  // one build at a time; later callers find it done
+  std::lock_guard<std::mutex> lk(build_mu);
+  {
+    std::lock_guard<std::mutex> g(c->mu);
+    if (c->ctab) return BH_OK;
+  }
+  const size_t bt = sizeof(float4) * kCshiftN * kCshiftN * kCshiftN;
+  const size_t bs = sizeof(double4) * kCshiftN * kCshiftN;
+  float4* tab = nullptr;
+  double4* spec = nullptr;
+  bh_status st = dev_alloc(c, bt, (void**)&tab);
+  if (!st) st = dev_alloc(c, bs, (void**)&spec);
+  hipError_t e = hipSuccess;
+  if (!st) {
+    e = launch_cshift_build(gauss_legendre8(), spec, tab, hs);
+    if (e == hipSuccess) e = hipStreamSynchronize(hs);
+  }
+  dev_free(c, spec, spec ? bs : 0);
+  if (st || e != hipSuccess) {
+    dev_free(c, tab, tab ? bt : 0);
+    if (st) return st;
+    return fail(BH_EDEVICE, std::string("colour-shift table: ") + hipGetErrorString(e));
+  }
+  std::lock_guard<std::mutex> g(c->mu);
+  c->ctab = tab;
+  return BH_OK;
+}
+
+static bh_status build_area(bh_ctx* c, const float* texels, int32_t n0, int bands, void* stream,
+                            bh_area** out) {
   if (!c || !texels || !out) return fail(BH_EINVAL, "NULL argument");
   if (n0 < 1 || n0 > 4096 || (n0 & (n0 - 1)))
     return fail(BH_EINVAL, "face_size must be a power of two <= 4096");
   HIPCHK(hipSetDevice(c->device));
   hipStream_t hs = (hipStream_t)stream;
+  if (bands) {
+    bh_status st = ensure_cshift(c, hs);
+    if (st) return st;
+  }
   int levels = 0;
   while ((n0 >> levels) >= 1) ++levels;
   const size_t texels_all = 8ull * n0 * n0 - 2;  // 6 (n0^2 + (n0/2)^2 + ... + 1)
@@ -874,15 +939,18 @@ extern "C" bh_status bh_build_area(bh_ctx* c, const float* texels, int32_t n0, v
   a->ctx = c;
   a->n0 = n0;
   a->levels = levels;
-  a->bytes = sizeof(float2) * texels_all;
+  a->bands = bands;
+  a->bytes = (bands ? sizeof(float4) : sizeof(float2)) * texels_all;
   int* bad = nullptr;
-  bh_status st = dev_alloc(c, a->bytes, (void**)&a->tex);
+  bh_status st = dev_alloc(c, a->bytes, &a->tex);
   if (!st) st = dev_alloc(c, sizeof(int), (void**)&bad);
   hipError_t e = hipSuccess;
   int hbad = 0;
   if (!st) {
     e = launch_fill_int(bad, 1, 0, hs);
-    if (e == hipSuccess) e = launch_area_build(texels, n0, a->tex, bad, hs);
+    if (e == hipSuccess)
+      e = bands ? launch_area_build_bands(texels, n0, (float4*)a->tex, bad, hs)
+                : launch_area_build(texels, n0, (float2*)a->tex, bad, hs);
     if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, hs);
     if (e == hipSuccess) e = hipStreamSynchronize(hs);
   }
@@ -892,12 +960,33 @@ extern "C" bh_status bh_build_area(bh_ctx* c, const float* texels, int32_t n0, v
     delete a;
     if (st) return st;
     if (e != hipSuccess) return fail(BH_EDEVICE, std::string("area build: ") + hipGetErrorString(e));
-    return fail(BH_EINVAL, "area texels must be finite with I >= 0 and T >= 0");
+    return fail(BH_EINVAL, bands ? "band texels must be finite and >= 0"
+                                 : "area texels must be finite with I >= 0 and T >= 0");
   }
   std::lock_guard<std::mutex> g(c->mu);
   c->areas.insert(a);
   handle_add(a, kArea);
   *out = a;
+  return BH_OK;
+}
+
+extern "C" bh_status bh_build_area(bh_ctx* c, const float* texels, int32_t n0, void* stream,
+                                   bh_area** out) {
+  return build_area(c, texels, n0, 0, stream, out);
+}
+
+extern "C" bh_status bh_build_area_bands(bh_ctx* c, const float* rgbx, int32_t n0, void* stream,
+                                         bh_area** out) {
+  return build_area(c, rgbx, n0, 1, stream, out);
+}
+
+extern "C" bh_status bh_color_shift_table_download(bh_ctx* c, float* host) {
+  if (!c || !host) return fail(BH_EINVAL, "NULL argument");
+  HIPCHK(hipSetDevice(c->device));
+  bh_status st = ensure_cshift(c, nullptr);
+  if (st) return st;
+  HIPCHK(hipMemcpy(host, c->ctab, sizeof(float4) * kCshiftN * kCshiftN * kCshiftN,
+                   hipMemcpyDeviceToHost));
   return BH_OK;
 }
 
@@ -907,7 +996,9 @@ extern "C" bh_status bh_area_download(const bh_area* a, int32_t level, float* ho
   HIPCHK(hipSetDevice(a->ctx->device));
   const int64_t n0 = a->n0, nl = n0 >> level;
   const int64_t off = 8 * (n0 * n0 - nl * nl);
-  HIPCHK(hipMemcpy(host, a->tex + off, sizeof(float2) * 6 * nl * nl, hipMemcpyDeviceToHost));
+  const size_t tsz = a->bands ? sizeof(float4) : sizeof(float2);
+  HIPCHK(hipMemcpy(host, (const char*)a->tex + tsz * off, tsz * 6 * nl * nl,
+                   hipMemcpyDeviceToHost));
   return BH_OK;
 }
 
@@ -1054,6 +1145,8 @@ static bh_status make_view(const bh_view* v, float* out, float* aov, ViewDev* o)
     o->area.n0 = v->area->n0;
     o->area.levels = v->area->levels;
     o->area.k_area = (float)v->k_area;
+    o->area.bands = v->area->bands;
+    o->area.ctab = v->area->bands ? v->area->ctx->ctab : nullptr;
   }
   o->out = (float4*)out;
   o->aov = (float4*)aov;
@@ -1187,7 +1280,7 @@ static bh_status enqueue_batch(bh_ctx* c, int cfg, int pers, const TablesDev& T,
                                grid, s));
     return BH_OK;
   }
-  bh_ctx::GraphKey key{cfg * 8 + pers * 4 + feat, ntiles, nruns, grid, (uintptr_t)counter,
+  bh_ctx::GraphKey key{(cfg * 2 + pers) * 8 + feat, ntiles, nruns, grid, (uintptr_t)counter,
                        (const void*)T.D, (const void*)T.U, (const void*)T.Dt, (const void*)T.Ut,
                        T.d_n, T.u_ne, T.u_nphi};
   auto it = c->graphs.find(key);

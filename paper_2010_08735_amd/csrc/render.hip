@@ -408,8 +408,9 @@ __device__ __forceinline__ float disc_density(const ViewDev& v, float ht, float 
 // s), 1, 16) along the longer axis and N_min = clamp(ceil(l_min / s), 1, 2) across it (so
 // N_maj = ceil(2 l_maj / l_min) by 2 once l_min >= 1); every probe reads level
 // lambda = log2(max(l_maj / N_maj, l_min / N_min)) - 1 trilinearly; the result is the probes'
-// mean of (I, I T).  Each probe takes the face of its own direction, so footprints cross
-// cube edges; bilinear coordinates are clamped to the face's outermost texel centres.
+// mean of (I, I T), or of (R, G, B) on a band map.  Each probe takes the face of its own
+// direction, so footprints cross cube edges; bilinear coordinates are clamped to the face's
+// outermost texel centres.
 
 // Cube face of a direction: axis k = argmax |p_k| (the lowest on ties), face 2k + (p_k < 0);
 // (pk, pa, pb) = (p_k, p_{(k+1)%3}, p_{(k+2)%3})
@@ -432,23 +433,36 @@ __device__ __forceinline__ FaceOf face_of(float p0, float p1, float p2) {
   return f;
 }
 
-// both channels of level L, bilinear, at face coordinates (U, V) of `face`
-__device__ __forceinline__ float2 area_fetch(const AreaDev& M, int L, int face, float U,
-                                             float V) {
+// texel types of the two map formats: (I, I T), and (R, G, B, 0) for band maps
+template <bool BANDS> struct AreaTexel { using type = float2; };
+template <> struct AreaTexel<true> { using type = float4; };
+
+__device__ __forceinline__ float2 lerp_texel(float f, float2 a, float2 b) {
+  return make_float2(fmaf(f, b.x - a.x, a.x), fmaf(f, b.y - a.y, a.y));
+}
+__device__ __forceinline__ float4 lerp_texel(float f, float4 a, float4 b) {
+  return make_float4(fmaf(f, b.x - a.x, a.x), fmaf(f, b.y - a.y, a.y), fmaf(f, b.z - a.z, a.z),
+                     0.0f);
+}
+
+// every channel of level L, bilinear, at face coordinates (U, V) of `face`
+template <bool BANDS>
+__device__ __forceinline__ typename AreaTexel<BANDS>::type area_fetch(const AreaDev& M, int L,
+                                                                      int face, float U,
+                                                                      float V) {
+  using Tx = typename AreaTexel<BANDS>::type;
   const int nL = M.n0 >> L;
   const uint32_t level0 = 8u * ((uint32_t)M.n0 * (uint32_t)M.n0 - (uint32_t)nL * (uint32_t)nL);
-  const float2* t = M.tex + level0 + (uint32_t)face * (uint32_t)nL * (uint32_t)nL;
+  const Tx* t = (const Tx*)M.tex + level0 + (uint32_t)face * (uint32_t)nL * (uint32_t)nL;
   if (nL == 1) return t[0];
   const float fn = (float)nL, top = fn - 1.0f;
   const float x = clampf(fmaf(0.5f * fn, U + 1.0f, -0.5f), 0.0f, top);
   const float y = clampf(fmaf(0.5f * fn, V + 1.0f, -0.5f), 0.0f, top);
   const int i0 = min((int)x, nL - 2), j0 = min((int)y, nL - 2);
   const float fx = x - (float)i0, fy = y - (float)j0;
-  const float2* r0 = t + (uint32_t)j0 * (uint32_t)nL + (uint32_t)i0;
-  const float2 a = r0[0], b = r0[1], c = r0[nL], e = r0[nL + 1];
-  const float2 lo = make_float2(fmaf(fx, b.x - a.x, a.x), fmaf(fx, b.y - a.y, a.y));
-  const float2 hi = make_float2(fmaf(fx, e.x - c.x, c.x), fmaf(fx, e.y - c.y, c.y));
-  return make_float2(fmaf(fy, hi.x - lo.x, lo.x), fmaf(fy, hi.y - lo.y, lo.y));
+  const Tx* r0 = t + (uint32_t)j0 * (uint32_t)nL + (uint32_t)i0;
+  const Tx a = r0[0], b = r0[1], c = r0[nL], e = r0[nL + 1];
+  return lerp_texel(fy, lerp_texel(fx, a, b), lerp_texel(fx, c, e));
 }
 
 // length, in level-0 texels, of the face-coordinate change along direction change (xk, xa,
@@ -460,10 +474,13 @@ __device__ __forceinline__ float area_axis(float im, float sg, float U, float V,
   return half_n0 * fsqrt(dU * dU + dV * dV);
 }
 
-// mean (I, I T) of the map over the footprint of d' with axes dw, dh
+// mean (I, I T) of the map over the footprint of d' with axes dw, dh, or mean (R, G, B)
+// of a band map (BANDS, into A, B, C)
+template <bool BANDS>
 __device__ __forceinline__ void area_filter(const AreaDev& M, float d0, float d1, float d2,
                                             float w0, float w1, float w2, float h0, float h1,
-                                            float h2, float& A, float& B) {
+                                            float h2, float& A, float& B, float& Cc) {
+  using Tx = typename AreaTexel<BANDS>::type;
   const FaceOf c = face_of(d0, d1, d2);
   const int k = c.k;
   auto perm = [k](float x0, float x1, float x2, float& xk, float& xa, float& xb) {
@@ -506,7 +523,7 @@ __device__ __forceinline__ void area_filter(const AreaDev& M, float d0, float d1
                              fmaf(sb_, n2, fmaf(sa_, j2, d2)));
     one_face = one_face && f.face == c.face;
   }
-  float sa = 0.0f, sb = 0.0f;
+  float sa = 0.0f, sb = 0.0f, sc = 0.0f;
   const float inv = fdiv(1.0f, fmaj);
   for (int i = 0; i < nmaj; ++i) {
     const float ta = fmaf((float)i + 0.5f, inv, -0.5f);
@@ -530,19 +547,42 @@ __device__ __forceinline__ void area_filter(const AreaDev& M, float d0, float d1
         pv = f.pb * ip;
         face = f.face;
       }
-      const float2 v0 = area_fetch(M, L0, face, pu, pv);
-      float2 v = v0;
-      if (two) {
-        const float2 v1 = area_fetch(M, L1, face, pu, pv);
-        v = make_float2(fmaf(fr, v1.x - v0.x, v0.x), fmaf(fr, v1.y - v0.y, v0.y));
-      }
+      const Tx v0 = area_fetch<BANDS>(M, L0, face, pu, pv);
+      Tx v = v0;
+      if (two) v = lerp_texel(fr, v0, area_fetch<BANDS>(M, L1, face, pu, pv));
       sa += v.x;
       sb += v.y;
+      if constexpr (BANDS) sc += v.z;
     }
   }
   const float in = inv * (nmin == 1 ? 1.0f : 0.5f);
   A = sa * in;
   B = sb * in;
+  Cc = sc * in;
+}
+
+// C_b(r, g, D) from the colour-shift table (Section 3.4.2; cshift.hip): log2 values read
+// trilinearly, linearly in r and g and, between the two D nodes around D, linearly in 1 / D;
+// r, g and log2 D clamped to the node range
+__device__ __forceinline__ float3 cshift_lookup(const float4* __restrict__ tab, float r, float g,
+                                                float D) {
+  constexpr float top = (float)(kCshiftN - 1), step = 6.0f / (float)(kCshiftN - 1);
+  const float x = clampf(r * top, 0.0f, top), y = clampf(g * top, 0.0f, top);
+  const int i0 = min((int)x, kCshiftN - 2), j0 = min((int)y, kCshiftN - 2);
+  const float fx = x - (float)i0, fy = y - (float)j0;
+  const float Dc = clampf(D, 0.125f, 8.0f);
+  const int k0 = min((int)((__log2f(Dc) + 3.0f) * (1.0f / step)), kCshiftN - 2);
+  const float inv0 = exp2f(3.0f - (float)k0 * step), inv1 = exp2f(3.0f - (float)(k0 + 1) * step);
+  const float fz = clampf(fdiv(fdiv(1.0f, Dc) - inv0, inv1 - inv0), 0.0f, 1.0f);
+  const float4* p = tab + ((uint32_t)i0 * kCshiftN + (uint32_t)j0) * kCshiftN + (uint32_t)k0;
+  constexpr uint32_t si = kCshiftN * kCshiftN, sj = kCshiftN;
+  const float4 c000 = p[0], c001 = p[1], c010 = p[sj], c011 = p[sj + 1];
+  const float4 c100 = p[si], c101 = p[si + 1], c110 = p[si + sj], c111 = p[si + sj + 1];
+  const float4 e = lerp_texel(fx, lerp_texel(fy, lerp_texel(fz, c000, c001),
+                                             lerp_texel(fz, c010, c011)),
+                              lerp_texel(fy, lerp_texel(fz, c100, c101),
+                                         lerp_texel(fz, c110, c111)));
+  return make_float3(exp2f(e.x), exp2f(e.y), exp2f(e.z));
 }
 
 // One pixel; every lane of the wave must call this together (quad exchanges).
@@ -550,7 +590,7 @@ __device__ __forceinline__ void area_filter(const AreaDev& M, float d0, float d1
 // requests (measurement only, see CountBufs).  ANIM: views may have a particle disc
 // (retarded times).
 // MARCH: ray marching (march_ray) in place of TraceRay; no tables are read.
-template <bool COUNT, bool ANIM = false, bool MARCH = false, bool AREA = false>
+template <bool COUNT, bool ANIM = false, bool MARCH = false, int AREA = 0>
 __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& T,
                                              const LutDev& L, int px, int py,
                                              const CountBufs* cnt) {
@@ -797,15 +837,29 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
   // ---- area sources: the footprint's mean radiance, one Doppler shift per pixel as for
   // stars, no lensing amplification (Section 3.4.1)
   if (AREA && v.area.tex && !cap) {
-    float A, B;
-    area_filter(v.area, dp0, dp1, dp2, dw0, dw1, dw2, dh0, dh1, dh2, A, B);
-    if (A > 0.0f) {
-      const float Tpix = fdiv(B, A);
-      const float4 Lr = band_lookup(L, dcam * Tpix), Ln = band_lookup(L, Tpix);
-      const float sc = trans * v.area.k_area * fdiv(A, Ln.w);
-      cr += sc * Lr.x;
-      cg += sc * Lr.y;
-      cb += sc * Lr.z;
+    float A, B, Cc;
+    if (AREA == 2 && v.area.bands) {
+      // light of any colour: band sum S and chromaticity (r, g), shifted by C(r, g, D_cam)
+      area_filter<true>(v.area, dp0, dp1, dp2, dw0, dw1, dw2, dh0, dh1, dh2, A, B, Cc);
+      const float S = A + B + Cc;
+      if (S > 0.0f) {
+        const float iS = fdiv(1.0f, S);
+        const float3 C = cshift_lookup(v.area.ctab, A * iS, B * iS, dcam);
+        const float sc = trans * v.area.k_area * S;
+        cr += sc * C.x;
+        cg += sc * C.y;
+        cb += sc * C.z;
+      }
+    } else {
+      area_filter<false>(v.area, dp0, dp1, dp2, dw0, dw1, dw2, dh0, dh1, dh2, A, B, Cc);
+      if (A > 0.0f) {
+        const float Tpix = fdiv(B, A);
+        const float4 Lr = band_lookup(L, dcam * Tpix), Ln = band_lookup(L, Tpix);
+        const float sc = trans * v.area.k_area * fdiv(A, Ln.w);
+        cr += sc * Lr.x;
+        cg += sc * Lr.y;
+        cb += sc * Lr.z;
+      }
     }
   }
 
@@ -836,7 +890,7 @@ struct TileCfg {
 };
 
 template <int TW, int TH, int PPT, bool COUNT = false, bool ANIM = false, bool MARCH = false,
-          bool AREA = false>
+          int AREA = 0>
 __device__ __forceinline__ void render_tile(const ViewDev& v, const TablesDev& T, const LutDev& L,
                                             int tx0, int ty0, const CountBufs* cnt = nullptr) {
   using C = TileCfg<TW, TH, PPT>;
@@ -880,7 +934,12 @@ static inline int xcd_grid(int tiles_x, int tiles_y) {
 // budget the compiler keeps to): 8, and 6 for the area-source variants, whose probe loop
 // spilled 20 vector registers to memory at 8 waves and ran 17% faster at 6 without spills.
 template <int FEAT>
-constexpr int kMinWaves = (FEAT & kFeatArea) ? 6 : 8;
+constexpr int kMinWaves = (FEAT & kFeatBands) ? 5 : ((FEAT & kFeatArea) ? 6 : 8);
+
+// the area code a feature set needs (render_pixel's AREA): 0 none, 1 (I, I T) maps only,
+// 2 band maps too (a run-time branch on the map's format)
+template <int FEAT>
+constexpr int kAreaOf = (FEAT & kFeatBands) ? 2 : ((FEAT & kFeatArea) ? 1 : 0);
 
 // One launch per view, tiles in the XCD-aware order above.
 // At least 8 resident waves per SIMD: the register budget the compiler keeps to.  The
@@ -892,13 +951,13 @@ __global__ void __launch_bounds__((TW / 8) * (TH / 8) * 64 / PPT, kMinWaves<FEAT
     k_render(ViewDev v, TablesDev T, LutDev L, int tiles_x, int tiles_y) {
   int col, row;
   if (!xcd_tile(blockIdx.x, tiles_x, tiles_y, &col, &row)) return;
-  render_tile<TW, TH, PPT, false, (FEAT & kFeatParticles) != 0, false, (FEAT & kFeatArea) != 0>(
+  render_tile<TW, TH, PPT, false, (FEAT & kFeatParticles) != 0, false, kAreaOf<FEAT>>(
       v, T, L, col * TW, row * TH);
 }
 
 // The render with ray marching in place of TraceRay (16x16 tiles, one pixel per thread);
-// AREA: the view has an area-source map.
-template <bool AREA>
+// AREA as in render_pixel.
+template <int AREA>
 __global__ void __launch_bounds__(256)
     k_render_march(ViewDev v, LutDev L, int tiles_x, int tiles_y) {
   int col, row;
@@ -935,7 +994,7 @@ __device__ __forceinline__ void render_flat_tile(const ViewDev* __restrict__ vie
   // fields are read through the reference as they are needed (wave-uniform scalar loads):
   // a copy of the whole record would hold ~65 scalar registers across the tile
   const ViewDev& v = views[r.view];
-  render_tile<TW, TH, PPT, false, (FEAT & kFeatParticles) != 0, false, (FEAT & kFeatArea) != 0>(
+  render_tile<TW, TH, PPT, false, (FEAT & kFeatParticles) != 0, false, kAreaOf<FEAT>>(
       v, T, L, (tile % r.tiles_x) * TW,
                                         (tile / r.tiles_x) * TH);
 }
@@ -987,7 +1046,7 @@ __global__ void __launch_bounds__(kBatchThreads, 7)
       for (int blk = 0; blk < kBlocks; ++blk) {
         const int bx = tx0 + 8 * (blk % C::kBX), by = ty0 + 8 * (blk / C::kBX);
         if (bx >= v.width || by >= v.height) continue;    // block outside the image
-        render_pixel<false, (FEAT & kFeatParticles) != 0, false, (FEAT & kFeatArea) != 0>(
+        render_pixel<false, (FEAT & kFeatParticles) != 0, false, kAreaOf<FEAT>>(
             v, T, L, bx + ox, by + oy, nullptr);
       }
     }
@@ -1086,11 +1145,12 @@ hipError_t scratch_address(void** p) {
 
 struct TileEntry {
   int tw, th, waves, ppt;
-  // indexed by the features the views may use: kFeatParticles | kFeatArea
-  void (*plain[4])(const ViewDev&, const TablesDev&, const LutDev&, hipStream_t);
-  void (*batch[4])(const ViewDev*, const TileRun*, int, int, int*, const TablesDev&,
+  // indexed by the features the views may use: kFeatParticles | kFeatArea | kFeatBands
+  // (kFeatBands comes with kFeatArea; entries 4 and 5 repeat 6 and 7)
+  void (*plain[8])(const ViewDev&, const TablesDev&, const LutDev&, hipStream_t);
+  void (*batch[8])(const ViewDev*, const TileRun*, int, int, int*, const TablesDev&,
                    const LutDev&, int grid, hipStream_t);
-  void (*list[4])(const ViewDev*, const TileRun*, int, int, const TablesDev&, const LutDev&,
+  void (*list[8])(const ViewDev*, const TileRun*, int, int, const TablesDev&, const LutDev&,
                   hipStream_t);
 };
 
@@ -1120,8 +1180,9 @@ static void launch_list(const ViewDev* views, const TileRun* runs, int nruns, in
                      views, runs, nruns, ntiles, T, L);
 }
 
-#define BH_FEATS(F, TW, TH, PPT) \
-  {F<TW, TH, PPT, 0>, F<TW, TH, PPT, 1>, F<TW, TH, PPT, 2>, F<TW, TH, PPT, 3>}
+#define BH_FEATS(F, TW, TH, PPT)                                                          \
+  {F<TW, TH, PPT, 0>, F<TW, TH, PPT, 1>, F<TW, TH, PPT, 2>, F<TW, TH, PPT, 3>,             \
+   F<TW, TH, PPT, 6>, F<TW, TH, PPT, 7>, F<TW, TH, PPT, 6>, F<TW, TH, PPT, 7>}
 #define BH_TILE(TW, TH, PPT)                                                                \
   {TW, TH, TileCfg<TW, TH, PPT>::kWaves, PPT, BH_FEATS(launch_plain, TW, TH, PPT),          \
    BH_FEATS(launch_batch, TW, TH, PPT), BH_FEATS(launch_list, TW, TH, PPT)}
@@ -1151,7 +1212,7 @@ hipError_t launch_render_batch(int cfg, int persistent, int feat, const ViewDev*
                                const TileRun* runs, int nruns, int ntiles, int* counter,
                                const TablesDev& T, const LutDev& L, int grid, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  const int a = feat & (kFeatParticles | kFeatArea);
+  const int a = feat & (kFeatParticles | kFeatArea | kFeatBands);
   if (persistent)
     kTiles[cfg].batch[a](views, runs, nruns, ntiles, counter, T, L, grid, s);
   else
@@ -1172,12 +1233,13 @@ hipError_t launch_render_count(const ViewDev& v, const TablesDev& T, const LutDe
 
 hipError_t launch_render_march(const ViewDev& v, const LutDev& L, hipStream_t s) {
   int tiles_x = (v.width + 15) / 16, tiles_y = (v.height + 15) / 16;
-  if (v.area.tex)
-    hipLaunchKernelGGL(k_render_march<true>, dim3(xcd_grid(tiles_x, tiles_y)), dim3(256), 0, s,
-                       v, L, tiles_x, tiles_y);
+  const dim3 grid(xcd_grid(tiles_x, tiles_y));
+  if (v.area.tex && v.area.bands)
+    hipLaunchKernelGGL(k_render_march<2>, grid, dim3(256), 0, s, v, L, tiles_x, tiles_y);
+  else if (v.area.tex)
+    hipLaunchKernelGGL(k_render_march<1>, grid, dim3(256), 0, s, v, L, tiles_x, tiles_y);
   else
-    hipLaunchKernelGGL(k_render_march<false>, dim3(xcd_grid(tiles_x, tiles_y)), dim3(256), 0, s,
-                       v, L, tiles_x, tiles_y);
+    hipLaunchKernelGGL(k_render_march<0>, grid, dim3(256), 0, s, v, L, tiles_x, tiles_y);
   return hipGetLastError();
 }
 

@@ -1,0 +1,265 @@
+"""Light of any colour (Section 3.4.2, the colour-shift table C(xy, D)) on the GPU, through
+the C ABI, against the FP64 oracle: the table built on the device, band-colour area maps,
+and whole frames that receive them through the table.
+
+Tolerances.  The table holds log2 values in FP32: against the oracle's FP64 nodes (its own
+quadrature, the same definitions) within 2e-5 + 2e-7 |log2 C|.  Frames: the GPU reads its
+FP32 table with FP32 coordinates where the oracle reads its FP64 table, on its own FP32
+trace of each pixel's footprint, so a pixel's colour moves with the escape direction's
+error (as for (I, T) maps) and with the table's rounding.  The method's own error, the
+table against the exact shift, is reported and bounded loosely."""
+import json
+import math
+
+import numpy as np
+import pytest
+
+from paper_2010_08735_amd import bh, scenes
+
+import oracle as orc_mod
+import parity
+
+pytestmark = pytest.mark.gpu
+
+
+def _report(s):
+    print("\nCSHIFT " + json.dumps(s, sort_keys=True))
+
+
+def gpu_band_map(ctx, m):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(m, np.float32)).cuda()
+    h = bh.bh_build_area_bands(ctx, t.data_ptr(), m.shape[1], bh.current_stream())
+    torch.cuda.synchronize()
+    return h
+
+
+@pytest.fixture(scope="module")
+def orc_ctable():
+    return orc_mod.cshift_table(*orc_mod.CSHIFT_DIMS)
+
+
+@pytest.fixture(scope="module")
+def band_scene(gpu_ctx, orc):
+    n0 = 64
+    m = scenes.area_map_bands(n0, 31)
+    h = gpu_band_map(gpu_ctx, m)
+    yield n0, m, h, orc.area_levels_bands(m)
+    bh.bh_release_area(h)
+
+
+def test_color_shift_table_matches_oracle(gpu_ctx, band_scene, orc_ctable):
+    n = bh.BH_CSHIFT_N
+    g = np.zeros((n, n, n, 4), np.float32)
+    bh.bh_color_shift_table_download(gpu_ctx, g.ctypes.data)
+    o = orc_ctable
+    assert g.shape[:3] == o.shape[:3]
+    err = np.abs(g[..., :3].astype(np.float64) - o)
+    bound = 2e-5 + 2e-7 * np.abs(o)
+    worst = np.unravel_index(np.argmax(err / bound), err.shape)
+    _report({"table_abs_max": float(err.max()), "table_abs_p99": float(np.percentile(err, 99)),
+             "worst_node": [int(x) for x in worst], "floor_nodes": int((o == -100.0).sum())})
+    assert np.all(g[..., 3] == 0.0)
+    assert np.all(err <= bound), (worst, g[worst[:3]], o[worst[:3]])
+
+
+def test_band_map_levels_match_oracle(band_scene, orc):
+    n0, m, h, lv = band_scene
+    for L in range(7):
+        nl = n0 >> L
+        g = np.zeros((6, nl, nl, 4), np.float32)
+        bh.bh_area_download(h, L, g.ctypes.data)
+        o = orc.area_level_bands(lv, n0, L)
+        rel = np.abs(g[..., :3] - o) / np.abs(o)
+        assert rel.max() < 5e-7, (L, rel.max())
+        assert np.all(g[..., 3] == 0.0)
+
+
+def _moving_view():
+    """128x128 camera at r = 15 moving at 0.6c across the line of sight, transparent disc:
+    D_cam spans about 0.87 .. 1.85 over the lit pixels."""
+    pos = scenes.spherical_position(15.0, math.radians(80.0), 0.0)
+    vel = 0.6 * scenes.azimuthal_direction(pos)
+    v = scenes.aimed_view(pos, vel, 128, 128, disc_r_in=3.0, disc_r_out=12.0)
+    v.disc_opacity = 0.0
+    v.k_area = 2.0
+    return v
+
+
+def test_band_light_frame_matches_oracle(gpu_ctx, gpu_tables, orc, orc_tables, band_scene,
+                                         orc_ctable):
+    """Every pixel of a moving camera's frame lit by the band sky, against the oracle in table
+    mode (TraceRay and colour shift); also reports the colour-shift table against the exact
+    shift and the filter against the exact footprint mean on the same pixels."""
+    n0, m, h, lv = band_scene
+    v = _moving_view()
+    rgb, aov = parity.render_gpu(gpu_ctx, gpu_tables, v, None, area=h)
+    assert np.all(rgb[..., 3] == 1.0) and np.isfinite(rgb).all()
+    quads = scenes.all_quads(v.width, v.height)
+    pt = orc.render_quads(v, quads, tables=orc_tables, area=lv, area_n0=n0, area_exact=True,
+                          area_bands=True, ctable=orc_ctable)
+    px = orc.render_quads(v, quads, tables=orc_tables, area=lv, area_n0=n0, area_bands=True)
+    g = parity.gpu_at(rgb, aov, pt)
+    msk = parity.mask_of(pt, g)
+    lit = ~msk & (pt["star_zeroed"] == 0) & (pt["area_A"] > 0)
+    dark = ~msk & (pt["star_zeroed"] != 0)
+    o = pt["rgb"][lit]
+    r = np.abs(g["rgb"][lit] - o).max(axis=1) / o.max(axis=1)
+    tm = np.abs(pt["rgb"][lit] - px["rgb"][lit]).max(axis=1) / px["rgb"][lit].max(axis=1)
+    ex = np.abs(pt["area_A"][lit] - pt["area_exact_A"][lit]) / pt["area_exact_A"][lit]
+    d = pt["d_cam"][lit]
+    s = {"lit": int(lit.sum()), "masked": float(msk.mean()), "d_cam": [float(d.min()), float(d.max())],
+         "rel_p50": float(np.median(r)), "rel_p99": float(np.percentile(r, 99)),
+         "rel_max": float(r.max()), "table_vs_exact_p50": float(np.median(tm)),
+         "table_vs_exact_p99": float(np.percentile(tm, 99)),
+         "filter_vs_exact_p90": float(np.percentile(ex, 90))}
+    w = int(np.argmax(r))
+    i = int(np.nonzero(lit)[0][w])
+    s["worst"] = {"x": int(pt["x"][i]), "y": int(pt["y"][i]), "rel": float(r[w]),
+                  "d_cam": float(pt["d_cam"][i]), "chroma": [float(c) for c in pt["area_chroma"][i]],
+                  "dprime_err": float(abs(g["dprime"][i] - pt["delta_prime"][i]))}
+    s["frac_above_1e-3"] = float((r > 1e-3).mean())
+    _report(s)
+    assert lit.sum() > 10000 and msk.mean() < 0.02
+    assert d.min() < 0.9 and d.max() > 1.4
+    assert np.all(g["rgb"][dark] == 0.0)
+    # measured on MI355X: p99 2.5e-6; 2 of 15 611 pixels above 1e-3 (max 1.9e-2), where the
+    # filter's discrete choices (probe count, level) fall differently in FP32 and FP64
+    assert s["rel_p99"] < 1e-4 and s["frac_above_1e-3"] < 1e-3 and s["rel_max"] < 5e-2
+    # the table against the exact shift (the method's interpolation): measured p50 6.4e-4,
+    # p99 3.8e-3
+    assert s["table_vs_exact_p50"] < 2e-3 and s["table_vs_exact_p99"] < 3e-2
+
+
+def test_blackbody_band_map_renders_like_the_temperature_map(gpu_ctx, gpu_tables, orc):
+    """A band map holding each texel's blackbody colour (I L_b(T) / sum L(T)) against the
+    (I, T) map on the GPU: the same light up to the colour-shift table's interpolation."""
+    import scipy.integrate as si
+    n0 = 32
+    it = scenes.area_map(n0, 21)
+    Ts = np.unique(np.round(it[..., 1].astype(np.float64), 0))
+    edges = [700e-9, 600e-9, 500e-9, 400e-9]
+
+    def chroma(T):
+        L = np.array([si.quad(lambda l: orc.planck(l, T), edges[b + 1], edges[b],
+                              epsrel=1e-12)[0] for b in range(3)])
+        return L / L.sum()
+    # the map's temperatures are smooth: interpolate the chromaticity over a fine T grid
+    grid = np.geomspace(Ts.min() * 0.999, Ts.max() * 1.001, 400)
+    cg = np.array([chroma(T) for T in grid])
+    T = it[..., 1].astype(np.float64)
+    cols = np.stack([np.interp(np.log(T), np.log(grid), cg[:, b]) for b in range(3)], axis=-1)
+    m = np.zeros((6, n0, n0, 4), np.float32)
+    m[..., :3] = it[..., :1] * cols
+    hb = gpu_band_map(gpu_ctx, m)
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(it)).cuda()
+    ht = bh.bh_build_area(gpu_ctx, t.data_ptr(), n0, bh.current_stream())
+    torch.cuda.synchronize()
+    try:
+        v = _moving_view()
+        a, _ = parity.render_gpu(gpu_ctx, gpu_tables, v, None, aov=False, area=hb)
+        b, _ = parity.render_gpu(gpu_ctx, gpu_tables, v, None, aov=False, area=ht)
+    finally:
+        bh.bh_release_area(hb)
+        bh.bh_release_area(ht)
+    lit = b[..., :3].max(axis=-1) > 0
+    r = np.abs(a[..., :3] - b[..., :3]).max(axis=-1)[lit] / b[..., :3].max(axis=-1)[lit]
+    _report({"bb_band_vs_temperature_p50": float(np.median(r)),
+             "p99": float(np.percentile(r, 99)), "max": float(r.max())})
+    assert lit.sum() > 10000
+    assert np.median(r) < 3e-3 and np.percentile(r, 99) < 3e-2
+
+
+def test_band_maps_in_batches_and_serving_equal_plain(gpu_ctx, gpu_tables, band_scene,
+                                                     small_scene):
+    """Views with band maps, (I, T) maps and none, in one batched launch (both forms) and
+    through the serving loop: every image equals its single-view render bit for bit."""
+    import torch
+    n0, m, h, lv = band_scene
+    field, sn0, sh, cube = small_scene
+    it = scenes.area_map(32, 21)
+    t = torch.from_numpy(np.ascontiguousarray(it)).cuda()
+    ht = bh.bh_build_area(gpu_ctx, t.data_ptr(), 32, bh.current_stream())
+    torch.cuda.synchronize()
+    try:
+        views = [v for v in scenes.batch_views(64, 3) if v.width * v.height <= 512 * 512][:6]
+        areas = [h, None, ht, h, ht, None][:len(views)]
+        for v in views:
+            v.k_area = 0.7
+        recs = [bh.make_view(v, sh, None, a) for v, a in zip(views, areas)]
+        refs = [parity.render_gpu(gpu_ctx, gpu_tables, v, sh, aov=False, area=a)[0]
+                for v, a in zip(views, areas)]
+        for pers in (0, 1):
+            bh.bh_set_batch_form(gpu_ctx, pers)
+            outs = [torch.zeros((v.height, v.width, 4), dtype=torch.float32, device="cuda")
+                    for v in views]
+            bh.bh_render_batch(gpu_ctx, gpu_tables, recs, [o.data_ptr() for o in outs],
+                               bh.current_stream())
+            torch.cuda.synchronize()
+            for o, ref in zip(outs, refs):
+                assert np.array_equal(o.cpu().numpy(), ref)
+        bh.bh_set_batch_form(gpu_ctx, 0)
+        ctx = bh.bh_create(0, 0)
+        try:
+            bh.bh_serve_start(ctx, 0, 2, 64)
+            outs = [torch.zeros((v.height, v.width, 4), dtype=torch.float32, device="cuda")
+                    for v in views]
+            torch.cuda.synchronize()
+            tickets = [bh.bh_submit(ctx, gpu_tables, r, o.data_ptr()) for r, o in zip(recs, outs)]
+            bh.bh_serve_drain(ctx)
+            for tk in tickets:
+                assert bh.bh_poll(ctx, tk)[0]
+            for o, ref in zip(outs, refs):
+                assert np.array_equal(o.cpu().numpy(), ref)
+        finally:
+            bh.bh_destroy(ctx)
+    finally:
+        bh.bh_set_batch_form(gpu_ctx, 0)
+        bh.bh_release_area(ht)
+
+
+def test_band_light_with_ray_marching(gpu_ctx, orc, band_scene, orc_ctable):
+    """The ray-marching render reads band maps the same way: against the oracle's marcher
+    at the same step budget, with the oracle's table."""
+    import torch
+    n0, m, h, lv = band_scene
+    v = _moving_view()
+    v.width = v.height = 64
+    W = H = 64
+    out = torch.full((H, W, 4), float("nan"), dtype=torch.float32, device="cuda")
+    a = torch.full((H, W, 4), float("nan"), dtype=torch.float32, device="cuda")
+    bh.bh_render_march(gpu_ctx, bh.make_view(v, None, None, h), 100, out.data_ptr(),
+                       a.data_ptr(), bh.current_stream())
+    torch.cuda.synchronize()
+    rgb, aov = out.cpu().numpy(), a.cpu().numpy()
+    pm = orc.render_quads(v, scenes.all_quads(W, H), march=100, area=lv, area_n0=n0,
+                          area_bands=True, ctable=orc_ctable)
+    g = parity.gpu_at(rgb, aov, pm)
+    msk = parity.mask_of(pm, g)
+    lit = ~msk & (pm["star_zeroed"] == 0) & (pm["area_A"] > 0)
+    o = pm["rgb"][lit]
+    r = np.abs(g["rgb"][lit] - o).max(axis=1) / o.max(axis=1)
+    _report({"march_lit": int(lit.sum()), "march_rel_p99": float(np.percentile(r, 99)),
+             "march_rel_max": float(r.max())})
+    assert lit.sum() > 2500
+    assert np.percentile(r, 99) < 2e-4 and r.max() < 3e-3
+
+
+def test_band_maps_reject_invalid_texels(gpu_ctx):
+    m = scenes.area_map_bands(8, 1)
+    for bad in ("negative", "nan", "inf"):
+        b = m.copy()
+        if bad == "negative":
+            b[3, 2, 1, 2] = -1.0
+        elif bad == "nan":
+            b[5, 7, 7, 0] = np.nan
+        else:
+            b[0, 0, 0, 1] = np.inf
+        with pytest.raises(bh.BhError) as e:
+            gpu_band_map(gpu_ctx, b)
+        assert e.value.status == bh.BH_EINVAL
+    b = m.copy()
+    b[..., 3] = np.nan          # the fourth component is ignored
+    h = gpu_band_map(gpu_ctx, b)
+    bh.bh_release(h)
