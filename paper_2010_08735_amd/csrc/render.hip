@@ -59,12 +59,24 @@ template <bool FP16, bool COUNT>
 __device__ __forceinline__ void gather(const void* tex, const Footprint& F, const CountBufs* cnt,
                                        uint32_t& req, float& A, float& B) {
   uint32_t w0 = 0, w1 = 0, hi = 0;  // lo = w0 + 2^32 w1
-  uint32_t off = 0;
-  for (int r = 0; r <= F.ny; ++r, off += (uint32_t)F.wpr) {
-    const uint32_t* orow = F.occ + off;
-    if (COUNT) req += 8;  // two occupancy words
+  // Every row's two occupancy words are loaded before any is used, so a lane waits once for
+  // its rows instead of once per row (rows past the footprint stay zero and load nothing).
+  uint32_t ra[9], rb[9];
+#pragma unroll
+  for (int r = 0; r < 9; ++r) {
+    ra[r] = 0u;
+    rb[r] = 0u;
+    if (r <= F.ny) {
+      const uint32_t* orow = F.occ + (uint32_t)r * (uint32_t)F.wpr;
+      ra[r] = orow[0];
+      rb[r] = orow[1];
+    }
+  }
+  if (COUNT) req += 8 * (F.ny + 1);  // two occupancy words per row
+#pragma unroll
+  for (int r = 0; r < 9; ++r) {
     // the row's 9 columns from bit x0 & 31 of two consecutive words (a funnel shift)
-    uint32_t b = __builtin_amdgcn_alignbit(orow[1], orow[0], (uint32_t)F.sh) & F.span;
+    uint32_t b = __builtin_amdgcn_alignbit(rb[r], ra[r], (uint32_t)F.sh) & F.span;
     if (r < 3) {
       w0 |= b << (9 * r);
     } else if (r == 3) {
