@@ -263,3 +263,35 @@ def test_band_maps_reject_invalid_texels(gpu_ctx):
     b[..., 3] = np.nan          # the fourth component is ignored
     h = gpu_band_map(gpu_ctx, b)
     bh.bh_release(h)
+
+
+def test_boosted_frame_under_a_band_sky_sampled(gpu_ctx, gpu_tables, orc, orc_tables,
+                                                big_field_scene, orc_ctable):
+    """The 1920x1080 frame of a camera at r = 6 moving at 0.9c (D_cam from 0.64 to 4.8)
+    with the disc, the 1M-star map and a 6 x 256^2 band sky: a seeded 1% of the quads against
+    the oracle in table mode (TraceRay tables and colour-shift table), with the full-frame
+    disc and colour tolerances of the star parity."""
+    field, n0, h, cube = big_field_scene
+    na = 256
+    m = scenes.area_map_bands(na, 33)
+    ah = gpu_band_map(gpu_ctx, m)
+    try:
+        v = scenes.boosted_orbit_view()
+        v.k_area = 0.3
+        rgb, aov = parity.render_gpu(gpu_ctx, gpu_tables, v, h, area=ah)
+    finally:
+        bh.bh_release_area(ah)
+    quads = scenes.sample_quads(v.width, v.height, 0.01, 14)
+    pt = orc.render_quads(v, quads, cube=cube, n0=n0, tables=orc_tables,
+                          area=orc.area_levels_bands(m), area_n0=na, area_bands=True,
+                          ctable=orc_ctable)
+    g = parity.gpu_at(rgb, aov, pt)
+    st = parity.compare(pt, g, "table")
+    sky = (pt["star_zeroed"] == 0) & (pt["area_A"] > 0)
+    d = pt["d_cam"][sky]
+    _report({"boosted_band_sky": st, "d_cam": [float(d.min()), float(d.max())],
+             "sky_pixels": int(sky.sum())})
+    assert np.isfinite(rgb).all() and st["masked_fraction"] < 0.02
+    assert d.min() < 0.7 and d.max() > 4.0
+    assert parity.frac_within(pt, g, 1e-3, "disc") > 0.995
+    assert parity.frac_within(pt, g, 2e-2, "all") > 0.995
