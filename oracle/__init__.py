@@ -29,7 +29,8 @@ class OrcView(C.Structure):
                 ("area", C.POINTER(C.c_double)), ("area_n0", C.c_int32),
                 ("area_exact", C.c_int32), ("k_area", C.c_double),
                 ("area_bands", C.c_int32), ("ct_n", C.c_int32 * 3),
-                ("ctable", C.POINTER(C.c_double))]
+                ("ctable", C.POINTER(C.c_double)), ("star_bands", C.c_int32),
+                ("pad1", C.c_int32)]
 
 
 class OrcRay(C.Structure):
@@ -87,6 +88,7 @@ def lib():
         L.orc_cubemap_texels.argtypes = [C.c_int32]
         fp = C.POINTER(C.c_float)
         L.orc_cubemap_build.argtypes = [fp, fp, fp, C.c_int64, C.c_int32, dp]
+        L.orc_cubemap_build_bands.argtypes = [fp, fp, C.c_int64, C.c_int32, dp]
         L.orc_render_quads.argtypes = [C.POINTER(OrcView), dp, C.c_int32, dp, C.c_int32, dp,
                                        C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.c_int64,
                                        C.c_void_p, C.c_int]
@@ -300,6 +302,27 @@ def planck(lam: float, T: float) -> float:
     return lib().orc_planck(lam, T)
 
 
+def cubemap_bands(dirs: np.ndarray, rgb: np.ndarray, n0: int) -> np.ndarray:
+    """FP64 band-colour cubemap texels (all mip levels), shape (texels, 5) = (R, G, B, p_u,
+    p_v), from star directions (n, 3) and band intensities (n, 3)."""
+    d = np.ascontiguousarray(dirs, np.float32).reshape(-1, 3)
+    c = np.ascontiguousarray(rgb, np.float32).reshape(-1, 3)
+    tex = np.zeros((lib().orc_cubemap_texels(n0), 5), np.float64)
+    fp = C.POINTER(C.c_float)
+    rc = lib().orc_cubemap_build_bands(d.ctypes.data_as(fp), c.ctypes.data_as(fp), len(d), n0,
+                                       _dp(tex))
+    if rc:
+        raise ValueError("orc_cubemap_build_bands rejected the stars (%d)" % rc)
+    return tex
+
+
+def cubemap_level_bands(tex: np.ndarray, n0: int, level: int) -> np.ndarray:
+    """View of one band-map mip level as (6, nL, nL, 5)."""
+    off = sum(6 * (n0 >> l) ** 2 for l in range(level))
+    nl = n0 >> level
+    return tex[off:off + 6 * nl * nl].reshape(6, nl, nl, 5)
+
+
 def cubemap(field, n0: int) -> np.ndarray:
     """FP64 cubemap texels (all mip levels concatenated), shape (texels, 4)."""
     n = len(field)
@@ -466,7 +489,8 @@ def to_orc_view(v) -> OrcView:
 def render_quads(view, quads: np.ndarray, cube: np.ndarray = None, n0: int = 0,
                  tables: Tables = None, nthreads: int = None, march: int = 0,
                  area: np.ndarray = None, area_n0: int = 0, area_exact: bool = False,
-                 area_bands: bool = False, ctable: np.ndarray = None) -> np.ndarray:
+                 area_bands: bool = False, ctable: np.ndarray = None,
+                 star_bands: bool = False) -> np.ndarray:
     """Render the 4 pixels of every quad (x0, y0); returns a PIXEL_DTYPE array (4 per quad).
     march > 0 replaces TraceRay by ray marching with at most that many steps.  area: levels
     from area_levels (area_exact also fills the exact footprint means), or from
@@ -476,6 +500,11 @@ def render_quads(view, quads: np.ndarray, cube: np.ndarray = None, n0: int = 0,
     nq = q.shape[0]
     out = np.zeros(4 * nq, PIXEL_DTYPE)
     ov = to_orc_view(view)
+    ov.star_bands = 1 if star_bands else 0
+    if ctable is not None and area is None:
+        ov._ct = np.ascontiguousarray(ctable, np.float64)
+        ov.ct_n[:] = list(ov._ct.shape[:3])
+        ov.ctable = _dp(ov._ct)
     if area is not None:
         ov._area = np.ascontiguousarray(area, np.float64)
         ov.area = _dp(ov._area)
@@ -483,7 +512,7 @@ def render_quads(view, quads: np.ndarray, cube: np.ndarray = None, n0: int = 0,
         ov.area_exact = 1 if area_exact else 0
         ov.k_area = getattr(view, "k_area", 1.0)
         ov.area_bands = 1 if area_bands else 0
-        if area_bands and ctable is not None:
+        if ctable is not None:
             ov._ct = np.ascontiguousarray(ctable, np.float64)
             ov.ct_n[:] = list(ov._ct.shape[:3])
             ov.ctable = _dp(ov._ct)

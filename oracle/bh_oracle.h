@@ -60,6 +60,9 @@ typedef struct {
   int32_t area_bands;
   int32_t ct_n[3];
   const double* ctable;
+  /* 1: the star map is a band map (orc_cubemap_build_bands), received as S C(r, g, D) */
+  int32_t star_bands;
+  int32_t pad1;
 } orc_view;
 
 /* Result of tracing one ray in its orbital plane. */
@@ -150,6 +153,9 @@ double orc_planck(double lambda, double T);          /* spectral radiance B_lamb
 int64_t orc_cubemap_texels(int32_t n0);              /* texel count over all mip levels */
 int orc_cubemap_build(const float* dirs, const float* inten, const float* temp, int64_t n,
                       int32_t n0, double* texels);   /* texels: orc_cubemap_texels * 4 */
+/* band colours: rgb 3 floats per star; texels: orc_cubemap_texels * 5 (R, G, B, p_u, p_v) */
+int orc_cubemap_build_bands(const float* dirs, const float* rgb, int64_t n, int32_t n0,
+                            double* texels);
 
 /* ---- area sources (Section 3.3.2 "Emitted light", Section 3.4.1 closing note) -------- */
 int64_t orc_area_texels(int32_t n0);                 /* texel count over all mip levels */

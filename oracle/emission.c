@@ -63,6 +63,96 @@ int64_t orc_cubemap_texels(int32_t n0) {
   return t;
 }
 
+/* level-0 texel of direction d: face, column, row and the position inside the texel in
+   [0, 1)^2; 0 for the zero vector */
+static int star_texel(const double* d, int32_t n0, int64_t* t, double* fu, double* fv) {
+  int k = 0;
+  if (fabs(d[1]) > fabs(d[k])) k = 1;
+  if (fabs(d[2]) > fabs(d[k])) k = 2;
+  double m = fabs(d[k]);
+  if (!(m > 0.0)) return 0;
+  int face = 2 * k + (d[k] < 0.0);
+  double U = d[(k + 1) % 3] / m, V = d[(k + 2) % 3] / m;
+  double gx = 0.5 * (U + 1.0) * n0, gy = 0.5 * (V + 1.0) * n0;
+  int64_t ix = (int64_t)floor(gx), iy = (int64_t)floor(gy);
+  if (ix < 0) ix = 0;
+  if (ix > n0 - 1) ix = n0 - 1;
+  if (iy < 0) iy = 0;
+  if (iy > n0 - 1) iy = n0 - 1;
+  *t = ((int64_t)face * n0 + iy) * n0 + ix;
+  *fu = gx - ix;
+  *fv = gy - iy;
+  return 1;
+}
+
+/* Band-colour star map (light of any colour, spectrum.c): each texel holds the band sums
+ * (R, G, B) of its stars and their position inside the texel weighted by S = R + G + B;
+ * mips combine the four children by the same rule.  Layout as the (I, T) map with 5
+ * doubles per texel: (R, G, B, p_u, p_v).  Stars with S = 0 are left out; a negative or
+ * non-finite band returns 2. */
+int orc_cubemap_build_bands(const float* dirs, const float* rgb, int64_t n, int32_t n0,
+                            double* tex) {
+  if (n0 < 1 || (n0 & (n0 - 1))) return 1;
+  for (int64_t s = 0; s < 3 * n; ++s)
+    if (!(rgb[s] >= 0.0f) || isinf(rgb[s])) return 2;
+  int nl = levels_of(n0);
+  int64_t total = orc_cubemap_texels(n0);
+  memset(tex, 0, sizeof(double) * 5 * total);
+  double* acc = (double*)calloc((size_t)6 * n0 * n0 * 5, sizeof(double));
+  if (!acc) return 3;
+  for (int64_t s = 0; s < n; ++s) {
+    double d[3] = {dirs[3 * s], dirs[3 * s + 1], dirs[3 * s + 2]};
+    double c[3] = {rgb[3 * s], rgb[3 * s + 1], rgb[3 * s + 2]};
+    double S = c[0] + c[1] + c[2];
+    int64_t t;
+    double fu, fv;
+    if (!(S > 0.0) || !star_texel(d, n0, &t, &fu, &fv)) continue;
+    double* a = acc + t * 5;
+    for (int b = 0; b < 3; ++b) a[b] += c[b];
+    a[3] += S * fu;
+    a[4] += S * fv;
+  }
+  for (int64_t t = 0; t < 6LL * n0 * n0; ++t) {
+    const double* a = acc + t * 5;
+    double* o = tex + t * 5;
+    double S = a[0] + a[1] + a[2];
+    if (S > 0.0) {
+      for (int b = 0; b < 3; ++b) o[b] = a[b];
+      o[3] = a[3] / S;
+      o[4] = a[4] / S;
+    }
+  }
+  free(acc);
+  int64_t off_prev = 0;
+  for (int l = 1; l < nl; ++l) {
+    int32_t np = n0 >> (l - 1), nc = n0 >> l;
+    int64_t off = off_prev + 6LL * np * np;
+    for (int f = 0; f < 6; ++f)
+      for (int32_t y = 0; y < nc; ++y)
+        for (int32_t x = 0; x < nc; ++x) {
+          double sc[3] = {0, 0, 0}, su = 0, sv = 0;
+          for (int c = 0; c < 4; ++c) {
+            int cx = 2 * x + (c & 1), cy = 2 * y + (c >> 1);
+            const double* ch = tex + (off_prev + ((int64_t)f * np + cy) * np + cx) * 5;
+            double S = ch[0] + ch[1] + ch[2];
+            if (!(S > 0.0)) continue;
+            for (int b = 0; b < 3; ++b) sc[b] += ch[b];
+            su += S * 0.5 * ((c & 1) + ch[3]);
+            sv += S * 0.5 * ((c >> 1) + ch[4]);
+          }
+          double S = sc[0] + sc[1] + sc[2];
+          double* o = tex + (off + ((int64_t)f * nc + y) * nc + x) * 5;
+          if (S > 0.0) {
+            for (int b = 0; b < 3; ++b) o[b] = sc[b];
+            o[3] = su / S;
+            o[4] = sv / S;
+          }
+        }
+    off_prev = off;
+  }
+  return 0;
+}
+
 int orc_cubemap_build(const float* dirs, const float* inten, const float* temp, int64_t n,
                       int32_t n0, double* tex) {
   if (n0 < 1 || (n0 & (n0 - 1))) return 1;
@@ -75,25 +165,14 @@ int orc_cubemap_build(const float* dirs, const float* inten, const float* temp, 
   for (int64_t s = 0; s < n; ++s) {
     double d[3] = {dirs[3 * s], dirs[3 * s + 1], dirs[3 * s + 2]};
     double I = inten[s], T = temp[s];
-    if (!(I > 0.0)) continue;
-    int k = 0;
-    if (fabs(d[1]) > fabs(d[k])) k = 1;
-    if (fabs(d[2]) > fabs(d[k])) k = 2;
-    double m = fabs(d[k]);
-    if (!(m > 0.0)) continue;
-    int face = 2 * k + (d[k] < 0.0);
-    double U = d[(k + 1) % 3] / m, V = d[(k + 2) % 3] / m;
-    double gx = 0.5 * (U + 1.0) * n0, gy = 0.5 * (V + 1.0) * n0;
-    int64_t ix = (int64_t)floor(gx), iy = (int64_t)floor(gy);
-    if (ix < 0) ix = 0;
-    if (ix > n0 - 1) ix = n0 - 1;
-    if (iy < 0) iy = 0;
-    if (iy > n0 - 1) iy = n0 - 1;
-    double* a = acc + (((size_t)face * n0 + iy) * n0 + ix) * 4;
+    int64_t t;
+    double fu, fv;
+    if (!(I > 0.0) || !star_texel(d, n0, &t, &fu, &fv)) continue;
+    double* a = acc + t * 4;
     a[0] += I;
     a[1] += I * T;
-    a[2] += I * (gx - ix);
-    a[3] += I * (gy - iy);
+    a[2] += I * fu;
+    a[3] += I * fv;
   }
   for (int64_t t = 0; t < 6LL * n0 * n0; ++t) {
     double* a = acc + t * 4;

@@ -44,7 +44,9 @@
  *   exactly 1 wherever d' is a rotation of q (flat space, static camera);
  *   star colour_b = k_star (Omega/Omega') A L_b(D_cam T_pix) / sum_b L_b(T_pix), T_pix = B/A
  *   (static stars: k' = [1, 0, 0, 0]).  If any member of the quad is captured the star
- *   term is zero for the whole quad.
+ *   term is zero for the whole quad.  A band-colour star map (emission.c) gathers the
+ *   weighted band sums instead; their sum S and chromaticity (r, g) give
+ *   colour_b = k_star (Omega/Omega') S C_b(r, g, D_cam) (spectrum.c).
  * Area sources (area.c): the same quad differences give the footprint; the filtered
  *   (A, B) = mean (I, I T) give area colour_b = k_area A L_b(D_cam T_pix) / sum_b L_b(T_pix),
  *   without Omega/Omega'; zero for a quad with a captured member, as for stars.  Band maps
@@ -217,9 +219,13 @@ static void face_coords(const double* d, int* face, int* k, double* U, double* V
 }
 
 /* footprint gather; returns the mip level, fills A and B */
+/* A, B: the tent-weighted sums of I and I T; for a band map (the view's star_bands) the
+   weighted sums of R, G, B go to A[0..2] */
 static int gather(const ctx_t* c, const double* dp, const double* dw, const double* dh,
                   double* A, double* B) {
-  *A = 0.0;
+  const int bands = c->v->star_bands, stride = bands ? 5 : 4;
+  A[0] = 0.0;
+  if (bands) A[1] = A[2] = 0.0;
   *B = 0.0;
   int face, k;
   double U, V;
@@ -245,15 +251,20 @@ static int gather(const ctx_t* c, const double* dp, const double* dw, const doub
   if (y1 > nL - 1) y1 = nL - 1;
   for (int32_t ty = y0; ty <= y1; ++ty)
     for (int32_t tx = x0; tx <= x1; ++tx) {
-      const double* tex = c->cube + (off + ((int64_t)face * nL + ty) * nL + tx) * 4;
-      if (!(tex[0] > 0.0)) continue;
-      double su = 2.0 * (tx + tex[2]) / nL - 1.0, sv = 2.0 * (ty + tex[3]) / nL - 1.0;
+      const double* tex = c->cube + (off + ((int64_t)face * nL + ty) * nL + tx) * stride;
+      const double* pos = tex + (bands ? 3 : 2);
+      if (!((bands ? tex[0] + tex[1] + tex[2] : tex[0]) > 0.0)) continue;
+      double su = 2.0 * (tx + pos[0]) / nL - 1.0, sv = 2.0 * (ty + pos[1]) / nL - 1.0;
       double du = su - U, dv = sv - V;
       double w = (J11 * du - J01 * dv) / det;
       double h = (-J10 * du + J00 * dv) / det;
       double wt = fmax(1.0 - fabs(w), 0.0) * fmax(1.0 - fabs(h), 0.0);
-      *A += wt * tex[0];
-      *B += wt * tex[0] * tex[1];
+      if (bands) {
+        for (int b = 0; b < 3; ++b) A[b] += wt * tex[b];
+      } else {
+        A[0] += wt * tex[0];
+        *B += wt * tex[0] * tex[1];
+      }
     }
   return L;
 }
@@ -329,10 +340,22 @@ static void shade_quad(const ctx_t* c, int32_t x0, int32_t y0, orc_pixel* out) {
       cross3(qw, qh, cq);
       double om = norm3(cq), omp = norm3(cd);
       p->omega_ratio = omp > 0.0 ? om / omp : 0.0;
-      double A, B;
-      p->mip_level = gather(c, o->dprime, dw, dh, &A, &B);
+      double A, B, Ab[3];
+      p->mip_level = gather(c, o->dprime, dw, dh, Ab, &B);
+      A = v->star_bands ? Ab[0] + Ab[1] + Ab[2] : Ab[0];
       p->star_A = A;
-      if (A > 0.0 && omp > 0.0) {
+      if (v->star_bands) {
+        /* band colours: S C(r, g, D_cam) (spectrum.c), from the table or exactly */
+        if (A > 0.0 && omp > 0.0) {
+          double C[3];
+          if (v->ctable)
+            orc_cshift_lookup(v->ctable, v->ct_n[0], v->ct_n[1], v->ct_n[2], Ab[0] / A,
+                              Ab[1] / A, o->d_cam, C);
+          else
+            orc_color_shift(Ab[0] / A, Ab[1] / A, o->d_cam, C);
+          for (int b = 0; b < 3; ++b) p->star_rgb[b] = v->k_star * p->omega_ratio * A * C[b];
+        }
+      } else if (A > 0.0 && omp > 0.0) {
         double Tpix = B / A;
         p->star_T = Tpix;
         double Lr[3], Ln[3];

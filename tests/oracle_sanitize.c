@@ -140,6 +140,16 @@ int main(void) {
   v.ctable = ctab;
   if (orc_render_quads(&v, cube, N0, D, dn, U, ne, nphi, quads, nq, px, 4)) bad = 1;
   for (int i = 0; i < 4 * nq; ++i) FINITE(px[i].rgb[0] + px[i].area_exact_A);
+  /* a band-colour star map through the same table */
+  float srgb[3 * 40];
+  for (int i = 0; i < 3 * 40; ++i) srgb[i] = 0.01f + (float)(i % 9) * 0.02f;
+  double* bcube = calloc((size_t)orc_cubemap_texels(N0) * 5, sizeof(double));
+  if (orc_cubemap_build_bands(dirs, srgb, 40, N0, bcube)) bad = 1;
+  v.star_bands = 1;
+  if (orc_render_quads(&v, bcube, N0, D, dn, U, ne, nphi, quads, nq, px, 4)) bad = 1;
+  for (int i = 0; i < 4 * nq; ++i) FINITE(px[i].rgb[0] + px[i].star_A);
+  v.star_bands = 0;
+  free(bcube);
   free(bands);
   free(ctab);
 
