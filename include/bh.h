@@ -183,8 +183,27 @@ bh_status bh_bloom_apply_display(bh_bloom* b, const float* weights, float exposu
 bh_status bh_build_stars(bh_ctx* ctx, const float* dir_xyz_dev, const float* intensity_dev,
                          const float* temperature_dev, int64_t n, int32_t face_size,
                          int32_t texel_format, void* hip_stream, bh_stars** out);
+/* Stars of any colour (Section 3.4.2: the emitted colour of the star gather received as
+ * (X + Y + Z) C(xy, D), here in the band basis of bh_build_area_bands).  rgb_dev: n x 3
+ * band intensities (R, G, B) per star, each finite and >= 0 (a star with R + G + B = 0 is
+ * left out), device array; dir_xyz_dev, face_size, texel_format as bh_build_stars.  A
+ * texel holds the band sums of its stars and their position inside the texel weighted by
+ * S = R + G + B; mips combine the four children by the same rule.  FP16 texels store
+ * (R, G, B) / scale_L (the per-level power of two of the (I, T) format, from the level's
+ * largest band value), p_u, p_v and three zero halves (16 bytes); FP32 texels the same
+ * eight values (32 bytes).  A pixel receives k_star x (Omega / Omega') x S x
+ * C_b(r, g, D_cam), S the footprint's tent-weighted band sum and (r, g) = (R, G) / S its
+ * chromaticity, through the context's colour-shift table (built with the first band map,
+ * as for bh_build_area_bands).  Shared by content like bh_build_stars (a band map never
+ * shares a key with an (I, T) map); BH_EINVAL for an invalid band value (the check runs on
+ * the device); released with bh_release_stars.  Synchronises hip_stream. */
+bh_status bh_build_star_bands(bh_ctx* ctx, const float* dir_xyz_dev, const float* rgb_dev,
+                              int64_t n, int32_t face_size, int32_t texel_format,
+                              void* hip_stream, bh_stars** out);
+
 /* Copy mip level `level` as float (face, y, x, [I, T, p_u, p_v]) to host_texels
- * (6 * (face_size >> level)^2 * 4 floats).  Blocking. */
+ * (6 * (face_size >> level)^2 * 4 floats); for a band map as float (face, y, x,
+ * [R, G, B, p_u, p_v, 0, 0, 0]) (8 floats per texel).  Blocking. */
 bh_status bh_stars_download(const bh_stars* s, int32_t level, float* host_texels);
 bh_status bh_release_stars(bh_stars* s);
 

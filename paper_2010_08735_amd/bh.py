@@ -27,7 +27,7 @@ EXPORTS = [
     "bh_create_particles", "bh_release_particles",
     "bh_bloom_create", "bh_bloom_apply", "bh_bloom_release", "bh_bloom_apply_display",
     "bh_tonemap",
-    "bh_build_stars", "bh_stars_download", "bh_release_stars",
+    "bh_build_stars", "bh_build_star_bands", "bh_stars_download", "bh_release_stars",
     "bh_build_area", "bh_build_area_bands", "bh_color_shift_table_download",
     "bh_area_download", "bh_release_area",
     "bh_render", "bh_render_march", "bh_render_batch", "bh_render_batch_noalloc",
@@ -98,6 +98,7 @@ def lib():
             "bh_release_particles": ([vp], i32),
             "bh_release_tables": ([vp], i32),
             "bh_build_stars": ([vp, vp, vp, vp, i64, i32, i32, vp, C.POINTER(vp)], i32),
+            "bh_build_star_bands": ([vp, vp, vp, i64, i32, i32, vp, C.POINTER(vp)], i32),
             "bh_stars_download": ([vp, i32, vp], i32),
             "bh_release_stars": ([vp], i32),
             "bh_build_area": ([vp, vp, i32, vp, C.POINTER(vp)], i32),
@@ -210,6 +211,14 @@ def bh_build_stars(ctx, dir_ptr, inten_ptr, temp_ptr, n, face_size, texel_format
     out = C.c_void_p()
     _check(lib().bh_build_stars(ctx, dir_ptr, inten_ptr, temp_ptr, n, face_size, texel_format,
                                 stream, C.byref(out)))
+    return out.value
+
+
+def bh_build_star_bands(ctx, dir_ptr, rgb_ptr, n, face_size, texel_format=BH_TEXEL_FP16,
+                        stream=None) -> int:
+    out = C.c_void_p()
+    _check(lib().bh_build_star_bands(ctx, dir_ptr, rgb_ptr, n, face_size, texel_format, stream,
+                                     C.byref(out)))
     return out.value
 
 

@@ -48,8 +48,10 @@ struct StarsDev {
   int n0, levels, fp16;
   float one;              // 1.0 (a run-time constant, see the gather)
   float tw0;              // 2 / n0: width of a level-0 texel in face coordinates (n0 = 2^k)
-  int pad[3];
+  int bands;              // 1: band-colour texels (R, G, B, p_u, p_v), received through `ctab`
+  const float4* ctab;     // colour-shift table of the context (band maps), else null
 };
+static_assert(sizeof(StarsDev) == 72, "the star-map record keeps the view record's layout");
 
 // ---- area-source map (nebulae, galaxies) ----------------------------------------------
 // (I, I T) per texel: radiance and radiance-weighted colour temperature; level L (size
@@ -72,7 +74,8 @@ struct CshiftRule {
 
 // Optional per-view work the render kernels are specialised for (a kernel without a
 // feature carries none of its code or registers): a particle disc, an area-source map.
-// kFeatBands: an area map of band colours (always with kFeatArea).
+// kFeatBands: band colours received through the colour-shift table, from an area map (then
+// with kFeatArea) or a star map.
 constexpr int kFeatParticles = 1, kFeatArea = 2, kFeatBands = 4;
 
 // ---- per-view constant block (host computes it in FP64 from bh_view) -----------------
@@ -110,7 +113,7 @@ struct ViewDev {
 // the features a view uses
 __host__ __device__ inline int view_features(const ViewDev& v) {
   return (v.density_mode != 0 ? kFeatParticles : 0) | (v.area.tex ? kFeatArea : 0) |
-         (v.area.tex && v.area.bands ? kFeatBands : 0);
+         ((v.area.tex && v.area.bands) || (v.has_stars && v.stars.bands) ? kFeatBands : 0);
 }
 
 // Bloom launch record: the image's box pyramid, levels 0 (the image) .. levels <= 16, and

@@ -42,6 +42,17 @@ hipError_t launch_star_occupancy(const void* tex, int n0, int levels, const uint
                                  hipStream_t s);
 hipError_t launch_star_unpack(const void* in, int64_t count, float scale, int fp16, float4* out,
                               hipStream_t s);
+hipError_t launch_star_build_bands(const float* dirs, const float* rgb, int64_t n, int n0,
+                                   int levels, const uint32_t* level_off_host, int* head,
+                                   int* next, float2* pos, float4* master, unsigned* maxbits,
+                                   float* scale, int fp16, void* out, int* bad, hipStream_t s);
+hipError_t launch_star_hash_bands(const float* dirs, const float* rgb, int64_t n,
+                                  unsigned long long* acc, hipStream_t s);
+hipError_t launch_star_occupancy_bands(const void* tex, int n0, int levels,
+                                       const uint32_t* level_off, const uint32_t* occ_off,
+                                       int fp16, uint32_t* occ, hipStream_t s);
+hipError_t launch_star_unpack_bands(const void* in, int64_t count, float scale, int fp16,
+                                    float4* out, hipStream_t s);
 hipError_t launch_render(int cfg, const ViewDev& v, const TablesDev& T, const LutDev& L,
                          hipStream_t s);
 hipError_t launch_area_build(const float* it, int n0, float2* tex, int* bad, hipStream_t s);
@@ -146,13 +157,14 @@ struct bh_bloom {
 };
 
 // Star maps are shared by content: (hash of the star arrays, star count, face size,
-// texel format).
-using StarKey = std::tuple<uint64_t, int64_t, int, int>;
+// texel format, band colours).
+using StarKey = std::tuple<uint64_t, int64_t, int, int, int>;
 
 struct bh_stars {
   bh_ctx* ctx;
   StarKey key;
   int n0, levels, fp16;
+  int bands = 0;          // 1: band-colour texels (R, G, B, p_u, p_v), see stars.hip
   void* tex = nullptr;
   float* scale = nullptr;
   uint32_t* level_off_dev = nullptr;
@@ -706,12 +718,15 @@ extern "C" bh_status bh_bloom_release(bh_bloom* b) {
 
 // ---- stars ---------------------------------------------------------------------------------
 
-extern "C" bh_status bh_build_stars(bh_ctx* c, const float* dir_xyz_dev,
-                                    const float* intensity_dev, const float* temperature_dev,
-                                    int64_t n, int32_t face_size, int32_t texel_format,
-                                    void* stream, bh_stars** out) {
+static bh_status ensure_cshift(bh_ctx* c, hipStream_t hs);
+
+// (I, T) maps (bands = 0: intensity_dev and temperature_dev) or band-colour maps (bands = 1:
+// rgb in intensity_dev, three floats per star, temperature_dev unused)
+static bh_status build_stars(bh_ctx* c, const float* dir_xyz_dev, const float* intensity_dev,
+                             const float* temperature_dev, int64_t n, int32_t face_size,
+                             int32_t texel_format, int bands, void* stream, bh_stars** out) {
   if (!c || !out) return fail(BH_EINVAL, "NULL argument");
-  if (n < 0 || (n > 0 && (!dir_xyz_dev || !intensity_dev || !temperature_dev)))
+  if (n < 0 || (n > 0 && (!dir_xyz_dev || !intensity_dev || (!bands && !temperature_dev))))
     return fail(BH_EINVAL, "bad star arrays");
   if (n >= (int64_t)1 << 31) return fail(BH_EINVAL, "at most 2^31 - 1 stars");
   int n0 = face_size;
@@ -720,7 +735,11 @@ extern "C" bh_status bh_build_stars(bh_ctx* c, const float* dir_xyz_dev,
     return fail(BH_EINVAL, "bad texel_format");
   HIPCHK(hipSetDevice(c->device));
   hipStream_t hs = (hipStream_t)stream;
-  // content hash of the three arrays (ordered after the caller's work on the stream)
+  if (bands) {
+    bh_status st = ensure_cshift(c, hs);  // band maps are received through the table
+    if (st) return st;
+  }
+  // content hash of the arrays (ordered after the caller's work on the stream)
   uint64_t hash = 0;
   {
     unsigned long long* acc = nullptr;
@@ -728,7 +747,8 @@ extern "C" bh_status bh_build_stars(bh_ctx* c, const float* dir_xyz_dev,
     if (hst) return hst;
     hipError_t e = hipMemsetAsync(acc, 0, sizeof(unsigned long long), hs);
     if (e == hipSuccess)
-      e = launch_star_hash(dir_xyz_dev, intensity_dev, temperature_dev, n, acc, hs);
+      e = bands ? launch_star_hash_bands(dir_xyz_dev, intensity_dev, n, acc, hs)
+                : launch_star_hash(dir_xyz_dev, intensity_dev, temperature_dev, n, acc, hs);
     unsigned long long h = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&h, acc, sizeof(h), hipMemcpyDeviceToHost, hs);
     if (e == hipSuccess) e = hipStreamSynchronize(hs);
@@ -737,7 +757,7 @@ extern "C" bh_status bh_build_stars(bh_ctx* c, const float* dir_xyz_dev,
     hash = h;
   }
   std::lock_guard<std::mutex> g(c->mu);
-  StarKey key{hash, n, n0, texel_format};
+  StarKey key{hash, n, n0, texel_format, bands};
   auto found = c->stars.find(key);
   if (found != c->stars.end()) {
     found->second->refs++;
@@ -755,13 +775,14 @@ extern "C" bh_status bh_build_stars(bh_ctx* c, const float* dir_xyz_dev,
     owords += 6ull * (n0 >> l) * ((((n0 >> l) + 31) >> 5) + 1);
   }
   int fp16 = texel_format == BH_TEXEL_FP16;
-  size_t tsz = fp16 ? 8 : 16;
+  const size_t tsz = (fp16 ? 8 : 16) * (bands ? 2 : 1);
   auto* s = new bh_stars;
   s->ctx = c;
   s->key = key;
   s->n0 = n0;
   s->levels = levels;
   s->fp16 = fp16;
+  s->bands = bands;
   s->level_off = off;
   s->occ_off = ooff;
   size_t btex = tsz * total, bsc = sizeof(float) * levels, boff = sizeof(uint32_t) * levels;
@@ -775,31 +796,43 @@ extern "C" bh_status bh_build_stars(bh_ctx* c, const float* dir_xyz_dev,
   // build scratch (freed below)
   int64_t ntex0 = 6ll * n0 * n0;
   size_t bhead = sizeof(int) * ntex0, bnext = sizeof(int) * std::max<int64_t>(n, 1),
-         bpos = sizeof(float2) * std::max<int64_t>(n, 1), bmaster = sizeof(float4) * total,
-         bmax = sizeof(unsigned) * 64;
+         bpos = sizeof(float2) * std::max<int64_t>(n, 1),
+         bmaster = sizeof(float4) * total * (bands ? 2 : 1), bmax = sizeof(unsigned) * 64;
   int* head = nullptr;
   int* next = nullptr;
   float2* pos = nullptr;
   float4* master = nullptr;
   unsigned* maxbits = nullptr;
+  int* bad = nullptr;
   if (!st) st = dev_alloc(c, bhead, (void**)&head);
   if (!st) st = dev_alloc(c, bnext, (void**)&next);
   if (!st) st = dev_alloc(c, bpos, (void**)&pos);
   if (!st) st = dev_alloc(c, bmaster, (void**)&master);
   if (!st) st = dev_alloc(c, bmax, (void**)&maxbits);
+  if (!st && bands) st = dev_alloc(c, sizeof(int), (void**)&bad);
   hipError_t e = hipSuccess;
+  int hbad = 0;
   if (!st) {
     e = hipMemcpyAsync(s->level_off_dev, off.data(), boff, hipMemcpyHostToDevice, hs);
     if (e == hipSuccess)
       e = hipMemcpyAsync(s->occ_off_dev, ooff.data(), boff, hipMemcpyHostToDevice, hs);
     if (e == hipSuccess) e = launch_fill_int(head, ntex0, -1, hs);
     if (e == hipSuccess) e = launch_fill_int((int*)maxbits, 64, 0, hs);
+    if (e == hipSuccess && bands) e = launch_fill_int(bad, 1, 0, hs);
     if (e == hipSuccess)
-      e = launch_star_build(dir_xyz_dev, intensity_dev, temperature_dev, n, n0, levels,
-                            off.data(), head, next, pos, master, maxbits, s->scale, fp16, s->tex,
-                            hs);
+      e = bands ? launch_star_build_bands(dir_xyz_dev, intensity_dev, n, n0, levels, off.data(),
+                                          head, next, pos, master, maxbits, s->scale, fp16,
+                                          s->tex, bad, hs)
+                : launch_star_build(dir_xyz_dev, intensity_dev, temperature_dev, n, n0, levels,
+                                    off.data(), head, next, pos, master, maxbits, s->scale, fp16,
+                                    s->tex, hs);
     if (e == hipSuccess)
-      e = launch_star_occupancy(s->tex, n0, levels, off.data(), ooff.data(), fp16, s->occ, hs);
+      e = bands ? launch_star_occupancy_bands(s->tex, n0, levels, off.data(), ooff.data(), fp16,
+                                              s->occ, hs)
+                : launch_star_occupancy(s->tex, n0, levels, off.data(), ooff.data(), fp16,
+                                        s->occ, hs);
+    if (e == hipSuccess && bands)
+      e = hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, hs);
     if (e == hipSuccess) e = hipStreamSynchronize(hs);
   }
   dev_free(c, head, head ? bhead : 0);
@@ -807,7 +840,8 @@ extern "C" bh_status bh_build_stars(bh_ctx* c, const float* dir_xyz_dev,
   dev_free(c, pos, pos ? bpos : 0);
   dev_free(c, master, master ? bmaster : 0);
   dev_free(c, maxbits, maxbits ? bmax : 0);
-  if (st || e != hipSuccess) {
+  dev_free(c, bad, bad ? sizeof(int) : 0);
+  if (st || e != hipSuccess || hbad) {
     dev_free(c, s->tex, s->tex ? btex : 0);
     dev_free(c, s->scale, s->scale ? bsc : 0);
     dev_free(c, s->level_off_dev, s->level_off_dev ? boff : 0);
@@ -815,13 +849,30 @@ extern "C" bh_status bh_build_stars(bh_ctx* c, const float* dir_xyz_dev,
     dev_free(c, s->occ_off_dev, s->occ_off_dev ? boff : 0);
     delete s;
     if (st) return st;
-    return fail(BH_EDEVICE, std::string("star build: ") + hipGetErrorString(e));
+    if (e != hipSuccess)
+      return fail(BH_EDEVICE, std::string("star build: ") + hipGetErrorString(e));
+    return fail(BH_EINVAL, "star band values must be finite and >= 0");
   }
   s->bytes = btex + bsc + 2 * boff + bocc;
   c->stars[key] = s;
   handle_add(s, kStars);
   *out = s;
   return BH_OK;
+}
+
+extern "C" bh_status bh_build_stars(bh_ctx* c, const float* dir_xyz_dev,
+                                    const float* intensity_dev, const float* temperature_dev,
+                                    int64_t n, int32_t face_size, int32_t texel_format,
+                                    void* stream, bh_stars** out) {
+  return build_stars(c, dir_xyz_dev, intensity_dev, temperature_dev, n, face_size, texel_format,
+                     0, stream, out);
+}
+
+extern "C" bh_status bh_build_star_bands(bh_ctx* c, const float* dir_xyz_dev,
+                                         const float* rgb_dev, int64_t n, int32_t face_size,
+                                         int32_t texel_format, void* stream, bh_stars** out) {
+  return build_stars(c, dir_xyz_dev, rgb_dev, nullptr, n, face_size, texel_format, 1, stream,
+                     out);
 }
 
 extern "C" bh_status bh_stars_download(const bh_stars* s, int32_t level, float* host) {
@@ -833,11 +884,14 @@ extern "C" bh_status bh_stars_download(const bh_stars* s, int32_t level, float* 
   float scale = 1.0f;
   HIPCHK(hipMemcpy(&scale, s->scale + level, sizeof(float), hipMemcpyDeviceToHost));
   float4* tmp = nullptr;
-  HIPCHK(hipMalloc(&tmp, sizeof(float4) * cnt));
-  size_t tsz = s->fp16 ? 8 : 16;
-  hipError_t e = launch_star_unpack((const char*)s->tex + tsz * s->level_off[level], cnt, scale,
-                                    s->fp16, tmp, nullptr);
-  if (e == hipSuccess) e = hipMemcpy(host, tmp, sizeof(float4) * cnt, hipMemcpyDeviceToHost);
+  const int per = s->bands ? 2 : 1;  // float4 records per texel
+  HIPCHK(hipMalloc(&tmp, sizeof(float4) * cnt * per));
+  const size_t tsz = (s->fp16 ? 8 : 16) * per;
+  const void* lvl = (const char*)s->tex + tsz * s->level_off[level];
+  hipError_t e = s->bands ? launch_star_unpack_bands(lvl, cnt, scale, s->fp16, tmp, nullptr)
+                          : launch_star_unpack(lvl, cnt, scale, s->fp16, tmp, nullptr);
+  if (e == hipSuccess)
+    e = hipMemcpy(host, tmp, sizeof(float4) * cnt * per, hipMemcpyDeviceToHost);
   (void)hipFree(tmp);
   if (e != hipSuccess) return fail(BH_EDEVICE, hipGetErrorString(e));
   return BH_OK;
@@ -851,7 +905,7 @@ extern "C" bh_status bh_release_stars(bh_stars* s) {
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
   c->stars.erase(s->key);
-  size_t tsz = s->fp16 ? 8 : 16;
+  const size_t tsz = (s->fp16 ? 8 : 16) * (s->bands ? 2 : 1);
   uint64_t total = 0;
   for (int l = 0; l < s->levels; ++l) total += 6ull * (s->n0 >> l) * (s->n0 >> l);
   dev_free(c, s->tex, tsz * total);
@@ -1139,6 +1193,8 @@ static bh_status make_view(const bh_view* v, float* out, float* aov, ViewDev* o)
     o->stars.fp16 = s->fp16;
     o->stars.one = 1.0f;
     o->stars.tw0 = 2.0f / (float)s->n0;
+    o->stars.bands = s->bands;
+    o->stars.ctab = s->bands ? s->ctx->ctab : nullptr;
   }
   if (v->area) {
     o->area.tex = v->area->tex;

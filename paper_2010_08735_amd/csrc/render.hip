@@ -27,15 +27,21 @@ namespace bh {
 struct __align__(8) Half4r {
   _Float16 x, y, z, w;
 };
+struct __align__(16) Half8r {
+  _Float16 v[8];
+};
 
 // Stored texels are (I, T, p_u, p_v); the FP16 format keeps I / scale_L and T / 1024, and
-// the caller applies both factors once to the footprint sums.
+// the caller applies both factors once to the footprint sums.  Band-colour maps store
+// (R, G, B, p_u, p_v, 0, 0, 0), FP16 bands divided by scale_L.
+enum { kTexIT16 = 0, kTexIT32 = 1, kTexBand16 = 2, kTexBand32 = 3 };
 
 // Footprint of one pixel on one star-map level: texel columns x0 .. x0 + 8 and rows
 // y0 .. y0 + ny at most, read from the occupancy bits into one 81-bit mask (bit 9 r + c for
 // row y0 + r, column x0 + c; rows 0-6 in `lo`, rows 7-8 in `hi`), then one pass over the set
 // bits.  A single loop over occupied texels keeps the lanes of a wave in step far better
-// than a loop per row.  Adds the tent-weighted sums of I and I T, in stored units, to A, B.
+// than a loop per row.  Adds the tent-weighted sums of I and I T, in stored units, to A, B
+// (FMT kTexIT16, kTexIT32), or of R, G, B to A, B, C (kTexBand16, kTexBand32).
 struct Footprint {
   uint32_t texel0;       // texel index of (x0, y0)
   const uint32_t* occ;   // occupancy word holding (x0, y0)
@@ -55,9 +61,9 @@ struct CountBufs {
   unsigned long long* l2_bytes;
 };
 
-template <bool FP16, bool COUNT>
+template <int FMT, bool COUNT>
 __device__ __forceinline__ void gather(const void* tex, const Footprint& F, const CountBufs* cnt,
-                                       uint32_t& req, float& A, float& B) {
+                                       uint32_t& req, float& A, float& B, float& C) {
   uint32_t w0 = 0, w1 = 0, hi = 0;  // lo = w0 + 2^32 w1
   // Every row's two occupancy words are loaded before any is used, so a lane waits once for
   // its rows instead of once per row (rows past the footprint stay zero and load nothing).
@@ -93,6 +99,8 @@ __device__ __forceinline__ void gather(const void* tex, const Footprint& F, cons
   // texels on (nL - 9 >= -8: a signed 24-bit product)
   const Half4r* tex16 = (const Half4r*)tex + F.texel0;
   const float4* tex32 = (const float4*)tex + F.texel0;
+  const Half8r* texb16 = (const Half8r*)tex + F.texel0;
+  const float4* texb32 = (const float4*)tex + 2 * (size_t)F.texel0;
   const int nLm9 = F.nL - 9;
   auto tap = [&](int idx) {
     int r = (idx * 57) >> 9;  // idx / 9 for idx < 81
@@ -101,10 +109,30 @@ __device__ __forceinline__ void gather(const void* tex, const Footprint& F, cons
     if (COUNT) {
       uint32_t ta = F.texel0 + t;
       atomicOr(&cnt->touched[ta >> 5], 1u << (ta & 31));
-      req += FP16 ? 8 : 16;
+      req += FMT == kTexIT16 ? 8 : (FMT == kTexBand32 ? 32 : 16);
     }
     const float fc = (float)c, fr = (float)r;
-    if (FP16) {
+    if constexpr (FMT == kTexBand16) {
+      const Half8r hx = texb16[t];
+      float a = fmaf((float)hx.v[3], F.one, fc), b = fmaf((float)hx.v[4], F.one, fr);
+      float w = fmaf(F.Wc, a, fmaf(F.Wr, b, F.W0));
+      float h = fmaf(F.Hc, a, fmaf(F.Hr, b, F.H0));
+      float wt = __builtin_amdgcn_fmed3f(1.0f - fabsf(w), 0.0f, 1.0f) *
+                 __builtin_amdgcn_fmed3f(1.0f - fabsf(h), 0.0f, 1.0f);
+      A = fmaf(wt, (float)hx.v[0], A);
+      B = fmaf(wt, (float)hx.v[1], B);
+      C = fmaf(wt, (float)hx.v[2], C);
+    } else if constexpr (FMT == kTexBand32) {
+      const float4 x = texb32[2 * t], y = texb32[2 * t + 1];
+      float a = fc + x.w, b = fr + y.x;
+      float w = fmaf(F.Wc, a, fmaf(F.Wr, b, F.W0));
+      float h = fmaf(F.Hc, a, fmaf(F.Hr, b, F.H0));
+      float wt = __builtin_amdgcn_fmed3f(1.0f - fabsf(w), 0.0f, 1.0f) *
+                 __builtin_amdgcn_fmed3f(1.0f - fabsf(h), 0.0f, 1.0f);
+      A = fmaf(wt, x.x, A);
+      B = fmaf(wt, x.y, B);
+      C = fmaf(wt, x.z, C);
+    } else if constexpr (FMT == kTexIT16) {
       // half operands go straight into mixed-precision multiply-adds
       Half4r hx = tex16[t];
       float a = fmaf((float)hx.z, F.one, fc), b = fmaf((float)hx.w, F.one, fr);
@@ -777,7 +805,9 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
     }
     mip = Lv;
     float det = J00 * J11 - J01 * J10;
-    float A = 0.0f, B = 0.0f;
+    // band-colour star maps are read only by the band variant (AREA == 2)
+    const bool bands = AREA == 2 && S.bands;
+    float A = 0.0f, B = 0.0f, Cb = 0.0f;
     if (fabsf(det) >= 1e-20f) {
       float idet = fdiv(1.0f, det);
       Footprint F;
@@ -814,13 +844,24 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
       F.H0 = fmaf(i10, cu, i11 * cv);
       F.one = S.one;
       if (COUNT) req += 12;  // level offsets and scale
-      if (S.fp16)
-        gather<true, COUNT>(S.tex, F, cnt, req, A, B);
-      else
-        gather<false, COUNT>(S.tex, F, cnt, req, A, B);
+      if constexpr (AREA == 2) {
+        if (bands) {
+          if (S.fp16)
+            gather<kTexBand16, COUNT>(S.tex, F, cnt, req, A, B, Cb);
+          else
+            gather<kTexBand32, COUNT>(S.tex, F, cnt, req, A, B, Cb);
+        }
+      }
+      if (!bands) {
+        if (S.fp16)
+          gather<kTexIT16, COUNT>(S.tex, F, cnt, req, A, B, Cb);
+        else
+          gather<kTexIT32, COUNT>(S.tex, F, cnt, req, A, B, Cb);
+      }
       const float iscale = S.scale[Lv];
       A *= iscale;
-      B *= S.fp16 ? iscale * 1024.0f : iscale;
+      B *= S.fp16 && !bands ? iscale * 1024.0f : iscale;
+      Cb *= iscale;
     }
     float cdx = dw1 * dh2 - dw2 * dh1, cdy = dw2 * dh0 - dw0 * dh2, cdz = dw0 * dh1 - dw1 * dh0;
     // Omega / Omega' = |q_w x q_h| / |d'_w x d'_h| with the same quad differences of the
@@ -834,7 +875,18 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
     const float cq2 = dq0 * dq1 - (qw * qh) * (qa * qb);
     const float om2 = cq0 * cq0 + cq1 * cq1 + cq2 * cq2;
     const float omp2 = cdx * cdx + cdy * cdy + cdz * cdz;
-    if (A > 0.0f && omp2 > 0.0f) {
+    if (bands) {
+      // light of any colour: band sum and chromaticity, shifted by C(r, g, D_cam)
+      const float Ssum = A + B + Cb;
+      if (Ssum > 0.0f && omp2 > 0.0f) {
+        const float iS = fdiv(1.0f, Ssum);
+        const float3 C = cshift_lookup(S.ctab, A * iS, B * iS, dcam);
+        const float sc = trans * v.k_star * fsqrt(om2) * __builtin_amdgcn_rsqf(omp2) * Ssum;
+        cr += sc * C.x;
+        cg += sc * C.y;
+        cb += sc * C.z;
+      }
+    } else if (A > 0.0f && omp2 > 0.0f) {
       float Tpix = fdiv(B, A);
       float4 Lr = band_lookup(L, dcam * Tpix);
       float4 Ln = band_lookup(L, Tpix);
@@ -1246,7 +1298,7 @@ hipError_t launch_render_count(const ViewDev& v, const TablesDev& T, const LutDe
 hipError_t launch_render_march(const ViewDev& v, const LutDev& L, hipStream_t s) {
   int tiles_x = (v.width + 15) / 16, tiles_y = (v.height + 15) / 16;
   const dim3 grid(xcd_grid(tiles_x, tiles_y));
-  if (v.area.tex && v.area.bands)
+  if ((v.area.tex && v.area.bands) || (v.has_stars && v.stars.bands))
     hipLaunchKernelGGL(k_render_march<2>, grid, dim3(256), 0, s, v, L, tiles_x, tiles_y);
   else if (v.area.tex)
     hipLaunchKernelGGL(k_render_march<1>, grid, dim3(256), 0, s, v, L, tiles_x, tiles_y);

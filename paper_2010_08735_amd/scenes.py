@@ -116,6 +116,23 @@ def star_field(n: int, seed: int) -> StarField:
                      temp.astype(np.float32), seed)
 
 
+def star_field_bands(n: int, seed: int):
+    """A seeded field of stars of any colour: directions (n, 3) and band intensities (n, 3),
+    float32.  Directions and the 4-decade log-uniform brightness as `star_field`; each
+    star's colour has chromaticity r ~ U(0.2, 0.5), g ~ U(0.22, 0.42), b = 1 - r - g (on
+    and off the blackbody locus), so its bands are I (r, g, b)."""
+    rng = np.random.default_rng(seed)
+    z = rng.uniform(-1.0, 1.0, n)
+    az = rng.uniform(0.0, 2.0 * math.pi, n)
+    inten = 10.0 ** rng.uniform(-4.0, 0.0, n)
+    r = rng.uniform(0.2, 0.5, n)
+    g = rng.uniform(0.22, 0.42, n)
+    s = np.sqrt(np.maximum(0.0, 1.0 - z * z))
+    dirs = np.stack([s * np.cos(az), s * np.sin(az), z], axis=1)
+    rgb = inten[:, None] * np.stack([r, g, 1.0 - r - g], axis=1)
+    return dirs.astype(np.float32), rgb.astype(np.float32)
+
+
 def area_map(n0: int, seed: int, blobs: int = 24, sigma_lo: float = 0.10,
              sigma_hi: float = 0.35) -> np.ndarray:
     """Level-0 texels of an area-source cube map, float32 (6, n0, n0, 2) = (I, T)."""

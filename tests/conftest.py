@@ -53,6 +53,12 @@ def orc_tables(orc):
 
 
 @pytest.fixture(scope="session")
+def orc_ctable(orc):
+    """The oracle's colour-shift table at the library's node counts (FP64)."""
+    return orc.cshift_table(*orc.CSHIFT_DIMS)
+
+
+@pytest.fixture(scope="session")
 def small_scene(gpu_ctx, orc):
     """20 000 seeded stars in a 6 x 256^2 FP16 map (GPU) and the oracle's map."""
     from paper_2010_08735_amd import bh, scenes

@@ -16,7 +16,6 @@ import pytest
 
 from paper_2010_08735_amd import bh, scenes
 
-import oracle as orc_mod
 import parity
 
 pytestmark = pytest.mark.gpu
@@ -32,11 +31,6 @@ def gpu_band_map(ctx, m):
     h = bh.bh_build_area_bands(ctx, t.data_ptr(), m.shape[1], bh.current_stream())
     torch.cuda.synchronize()
     return h
-
-
-@pytest.fixture(scope="module")
-def orc_ctable():
-    return orc_mod.cshift_table(*orc_mod.CSHIFT_DIMS)
 
 
 @pytest.fixture(scope="module")
