@@ -509,6 +509,22 @@ def main():
                                   "mpx_per_s": W * H * n_ar / rwall / 1e6}
         bh.bh_release_area(ah)
         log("area:", json.dumps(extra["area"]))
+        # the 1M-star field as stars of any colour (Section 3.4.2): a band-colour star map of
+        # the same size, gathered and received through the colour-shift table
+        bd, brgb = scenes.star_field_bands(1_000_000, 1)
+        d_t, c_t = torch.from_numpy(bd).cuda(), torch.from_numpy(brgb).cuda()
+        t0 = time.perf_counter()
+        bsh = bh.bh_build_star_bands(ctx, d_t.data_ptr(), c_t.data_ptr(), len(bd), 2048,
+                                     bh.BH_TEXEL_FP16, bh.current_stream())
+        torch.cuda.synchronize()
+        build_s = time.perf_counter() - t0
+        del d_t, c_t
+        rwall, rkms, _ = plain_leg(bh, ctx, tables, bh.make_view(sv, bsh), n_ar, args.warmup)
+        extra["star_bands"] = {"stars": len(bd), "star_map": "6x2048x2048, 16-byte FP16 band texels",
+                               "build_s": build_s, "ms_per_frame": 1e3 * rwall / n_ar,
+                               "kernel_ms": float(rkms), "mpx_per_s": W * H * n_ar / rwall / 1e6}
+        bh.bh_release_stars(bsh)
+        log("star bands:", json.dumps(extra["star_bands"]))
     if "bloom" in legs:
         extra["bloom"] = bloom_leg(bh, scenes, ctx, out, W, H)
         log("bloom:", json.dumps(extra["bloom"]))
