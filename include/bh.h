@@ -430,7 +430,8 @@ bh_status bh_march_rays(bh_ctx* ctx, const float* rays_dev, int64_t n, int32_t m
  * visited (the star-map bytes one frame must read at least once) and, if req_bytes is not
  * NULL, the bytes all pixels request through the caches (table and band-table fetches,
  * occupancy words, texels, level records, image and AOV stores).  The frame is rendered
- * without the view's area-source map (none of its light, texels or bytes).  Blocking. */
+ * without the view's area-source map (none of its light, texels or bytes).  The view's star
+ * map must be an (I, T) map (BH_EINVAL for a band-colour map).  Blocking. */
 bh_status bh_footprint_texels(bh_ctx* ctx, const bh_tables* t, const bh_view* v,
                               float* out_rgba_dev, uint64_t* texels, uint64_t* req_bytes);
 /* Measurement: the read bandwidth of data held in the L2 caches.  Every workgroup (8 per

@@ -772,7 +772,8 @@ static bh_status build_stars(bh_ctx* c, const float* dir_xyz_dev, const float* i
     off[l] = (uint32_t)total;
     total += 6ull * (n0 >> l) * (n0 >> l);
     ooff[l] = (uint32_t)owords;
-    owords += 6ull * (n0 >> l) * ((((n0 >> l) + 31) >> 5) + 1);
+    const uint64_t nl = (uint64_t)(n0 >> l);
+    owords += 12ull * nl * (((nl + 31) >> 5) + 1);  // every row paired with the next (stars.hip)
   }
   int fp16 = texel_format == BH_TEXEL_FP16;
   const size_t tsz = (fp16 ? 8 : 16) * (bands ? 2 : 1);
@@ -1573,6 +1574,7 @@ extern "C" bh_status bh_footprint_texels(bh_ctx* c, const bh_tables* t, const bh
                                          float* out, uint64_t* texels, uint64_t* req_bytes) {
   if (!c || !t || !texels) return fail(BH_EINVAL, "NULL argument");
   if (!v || !v->stars) return fail(BH_EINVAL, "view without a star map");
+  if (v->stars->bands) return fail(BH_EINVAL, "footprint counting reads (I, T) star maps only");
   ViewDev vd;
   bh_status st = make_view(v, out, nullptr, &vd);
   if (st) return st;

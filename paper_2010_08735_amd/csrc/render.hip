@@ -30,6 +30,9 @@ struct __align__(8) Half4r {
 struct __align__(16) Half8r {
   _Float16 v[8];
 };
+struct __align__(8) OccPair {  // two words of two consecutive occupancy rows (stars.hip)
+  uint32_t a0, a1, b0, b1;      // row r word k, row r + 1 word k, row r word k + 1, row r + 1 word k + 1
+};
 
 // Stored texels are (I, T, p_u, p_v); the FP16 format keeps I / scale_L and T / 1024, and
 // the caller applies both factors once to the footprint sums.  Band-colour maps store
@@ -44,8 +47,8 @@ enum { kTexIT16 = 0, kTexIT32 = 1, kTexBand16 = 2, kTexBand32 = 3 };
 // (FMT kTexIT16, kTexIT32), or of R, G, B to A, B, C (kTexBand16, kTexBand32).
 struct Footprint {
   uint32_t texel0;       // texel index of (x0, y0)
-  const uint32_t* occ;   // occupancy word holding (x0, y0)
-  int nL, wpr, sh, ny;
+  const uint32_t* occ;   // occupancy word of (x0, y0) in the row pair starting at y0
+  int nL, wpr4, sh, ny;  // wpr4: occupancy words from one row pair to the pair two rows down
   uint32_t span;         // bit mask of the footprint's columns, shifted to bit 0
   // screen-space coordinates (w, h) of a star at (c + p_u, r + p_v) texels from the
   // footprint's corner: w = W0 + Wc (c + p_u) + Wr (r + p_v), h = H0 + Hc (..) + Hr (..)
@@ -66,23 +69,27 @@ __device__ __forceinline__ void gather(const void* tex, const Footprint& F, cons
                                        uint32_t& req, float& A, float& B, float& C) {
   uint32_t w0 = 0, w1 = 0, hi = 0;  // lo = w0 + 2^32 w1
   // Every row's two occupancy words are loaded before any is used, so a lane waits once for
-  // its rows instead of once per row (rows past the footprint stay zero and load nothing).
-  uint32_t ra[9], rb[9];
+  // its rows instead of once per row.  Rows come in pairs (r, r + 1), one 16-byte load each
+  // (the occupancy layout of stars.hip); pairs past the footprint load nothing, and the
+  // second row of the last pair is dropped when it lies past the footprint.
+  uint32_t ra[10], rb[10];
 #pragma unroll
-  for (int r = 0; r < 9; ++r) {
-    ra[r] = 0u;
-    rb[r] = 0u;
-    if (r <= F.ny) {
-      const uint32_t* orow = F.occ + (uint32_t)r * (uint32_t)F.wpr;
-      ra[r] = orow[0];
-      rb[r] = orow[1];
+  for (int p = 0; p < 5; ++p) {
+    ra[2 * p] = rb[2 * p] = ra[2 * p + 1] = rb[2 * p + 1] = 0u;
+    if (2 * p <= F.ny) {
+      const OccPair q = *(const OccPair*)(F.occ + (uint32_t)p * (uint32_t)F.wpr4);
+      ra[2 * p] = q.a0;
+      ra[2 * p + 1] = q.a1;
+      rb[2 * p] = q.b0;
+      rb[2 * p + 1] = q.b1;
     }
   }
-  if (COUNT) req += 8 * (F.ny + 1);  // two occupancy words per row
+  if (COUNT) req += 16 * (F.ny / 2 + 1);  // one 16-byte load per row pair
 #pragma unroll
   for (int r = 0; r < 9; ++r) {
     // the row's 9 columns from bit x0 & 31 of two consecutive words (a funnel shift)
     uint32_t b = __builtin_amdgcn_alignbit(rb[r], ra[r], (uint32_t)F.sh) & F.span;
+    if ((r & 1) && r > F.ny) b = 0u;
     if (r < 3) {
       w0 |= b << (9 * r);
     } else if (r == 3) {
@@ -824,14 +831,16 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
       x1 = min(x1, x0 + 8);
       y1 = min(y1, y0 + 8);
       F.nL = nL;
-      F.wpr = ((nL + 31) >> 5) + 1;
+      const int wpr = ((nL + 31) >> 5) + 1;
+      F.wpr4 = 4 * wpr;
       F.sh = x0 & 31;
       F.ny = y1 - y0;
       F.span = (1u << (x1 - x0 + 1)) - 1u;  // x1 - x0 <= 8
       F.texel0 = S.level_off[Lv] + ((uint32_t)face * (uint32_t)nL + (uint32_t)y0) * (uint32_t)nL +
                  (uint32_t)x0;
       F.occ = S.occ + S.occ_off[Lv] +
-              ((uint32_t)face * (uint32_t)nL + (uint32_t)y0) * (uint32_t)F.wpr + (uint32_t)(x0 >> 5);
+              2u * (((uint32_t)face * (uint32_t)nL + (uint32_t)y0) * (uint32_t)wpr +
+                    (uint32_t)(x0 >> 5));
       // a level-L texel is tw = 2 / nL wide in face coordinates; the corner (x0, y0) lies at
       // (cu, cv) from the centre direction (U, V)
       const float tw = __builtin_ldexpf(S.tw0, Lv);  // nL = n0 / 2^L: 2 / nL exactly

@@ -163,22 +163,38 @@ __global__ void k_star_scales(const unsigned* __restrict__ maxbits, int levels, 
 
 // Occupancy bits of one level: one bit per texel (stored intensity > 0), each texel row
 // padded to whole 32-bit words plus one guard word, so a footprint row of at most 9
-// texels is read with two consecutive word loads that never leave the row's storage.
+// texels is read from two consecutive words of its row that never leave the row's storage.
+// Every row is stored paired with the next row of its face (the last row with an empty
+// one), the two rows' words interleaved: word wi of the pair starting at row R = face nl + y
+// is at 2 (R wpr + wi) for row y and 2 (R wpr + wi) + 1 for row y + 1, so one 16-byte load
+// returns two consecutive words of two consecutive rows, from any starting row.
+__device__ __forceinline__ bool occ_word_row(int64_t w, int nl, int wpr, int* wi, int64_t* row) {
+  const int h = (int)(w & 1);
+  const int64_t q = w >> 1;
+  *wi = (int)(q % wpr);
+  const int64_t R = q / wpr;                    // face * nl + y: the pair's first row
+  const int y = (int)(R % nl) + h;
+  *row = R + h;
+  return y < nl;
+}
+
 __global__ void k_star_occupancy(const void* __restrict__ tex, int nl, int fp16,
                                  uint32_t* __restrict__ occ) {
   const int wpr = ((nl + 31) >> 5) + 1;
   int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  int64_t total = 6LL * nl * wpr;
+  int64_t total = 6LL * 2 * nl * wpr;
   if (w >= total) return;
-  int wi = (int)(w % wpr);
-  int64_t row = w / wpr;  // face * nl + y
+  int wi;
+  int64_t row;
   uint32_t bits = 0;
-  for (int b = 0; b < 32; ++b) {
-    int x = wi * 32 + b;
-    if (x >= nl) break;
-    int64_t t = row * nl + x;
-    float I = fp16 ? (float)((const Half4*)tex)[t].x : ((const float4*)tex)[t].x;
-    if (I > 0.0f) bits |= 1u << b;
+  if (occ_word_row(w, nl, wpr, &wi, &row)) {
+    for (int b = 0; b < 32; ++b) {
+      int x = wi * 32 + b;
+      if (x >= nl) break;
+      int64_t t = row * nl + x;
+      float I = fp16 ? (float)((const Half4*)tex)[t].x : ((const float4*)tex)[t].x;
+      if (I > 0.0f) bits |= 1u << b;
+    }
   }
   occ[w] = bits;
 }
@@ -191,7 +207,7 @@ hipError_t launch_star_occupancy(const void* tex, int n0, int levels, const uint
   size_t tsz = fp16 ? 8 : 16;
   for (int l = 0; l < levels; ++l) {
     int nl = n0 >> l;
-    int64_t words = 6LL * nl * (((nl + 31) >> 5) + 1);
+    int64_t words = 6LL * 2 * nl * (((nl + 31) >> 5) + 1);
     hipLaunchKernelGGL(k_star_occupancy, dim3(blocks_for(words, 256)), dim3(256), 0, s,
                        (const void*)((const char*)tex + tsz * level_off[l]), nl, fp16,
                        occ + occ_off[l]);
@@ -407,24 +423,26 @@ __global__ void k_star_occupancy_bands(const void* __restrict__ tex, int nl, int
                                        uint32_t* __restrict__ occ) {
   const int wpr = ((nl + 31) >> 5) + 1;
   int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  int64_t total = 6LL * nl * wpr;
+  int64_t total = 6LL * 2 * nl * wpr;
   if (w >= total) return;
-  int wi = (int)(w % wpr);
-  int64_t row = w / wpr;
+  int wi;
+  int64_t row;
   uint32_t bits = 0;
-  for (int b = 0; b < 32; ++b) {
-    int x = wi * 32 + b;
-    if (x >= nl) break;
-    int64_t t = row * nl + x;
-    bool lit;
-    if (fp16) {
-      const Half8 h = ((const Half8*)tex)[t];
-      lit = (float)h.v[0] > 0.0f || (float)h.v[1] > 0.0f || (float)h.v[2] > 0.0f;
-    } else {
-      const float4 a = ((const float4*)tex)[2 * t];
-      lit = a.x > 0.0f || a.y > 0.0f || a.z > 0.0f;
+  if (occ_word_row(w, nl, wpr, &wi, &row)) {
+    for (int b = 0; b < 32; ++b) {
+      int x = wi * 32 + b;
+      if (x >= nl) break;
+      int64_t t = row * nl + x;
+      bool lit;
+      if (fp16) {
+        const Half8 h = ((const Half8*)tex)[t];
+        lit = (float)h.v[0] > 0.0f || (float)h.v[1] > 0.0f || (float)h.v[2] > 0.0f;
+      } else {
+        const float4 a = ((const float4*)tex)[2 * t];
+        lit = a.x > 0.0f || a.y > 0.0f || a.z > 0.0f;
+      }
+      if (lit) bits |= 1u << b;
     }
-    if (lit) bits |= 1u << b;
   }
   occ[w] = bits;
 }
@@ -471,7 +489,7 @@ hipError_t launch_star_occupancy_bands(const void* tex, int n0, int levels,
   const size_t tsz = fp16 ? 16 : 32;
   for (int l = 0; l < levels; ++l) {
     int nl = n0 >> l;
-    int64_t words = 6LL * nl * (((nl + 31) >> 5) + 1);
+    int64_t words = 6LL * 2 * nl * (((nl + 31) >> 5) + 1);
     hipLaunchKernelGGL(k_star_occupancy_bands, dim3(blocks_for(words, 256)), dim3(256), 0, s,
                        (const void*)((const char*)tex + tsz * level_off[l]), nl, fp16,
                        occ + occ_off[l]);

@@ -219,7 +219,7 @@ def test_band_stars_with_ray_marching(gpu_ctx, orc, band_stars, orc_ctable):
     assert parity.frac_within(pm, g, 2e-2, "star") > 0.99
 
 
-def test_band_star_maps_shared_by_content_and_validated(gpu_ctx, small_scene):
+def test_band_star_maps_shared_by_content_and_validated(gpu_ctx, gpu_tables, small_scene):
     field, n0, hs, cube = small_scene
     dirs, rgb = scenes.star_field_bands(500, 7)
     h1 = gpu_band_stars(gpu_ctx, dirs, rgb, 64)
@@ -231,6 +231,13 @@ def test_band_star_maps_shared_by_content_and_validated(gpu_ctx, small_scene):
     assert h3 != h1                      # one band of one star differs
     h4 = gpu_band_stars(gpu_ctx, dirs, rgb, 64, bh.BH_TEXEL_FP32)
     assert h4 not in (h1, h3)
+    # the footprint-counting measurement reads (I, T) maps only
+    import torch
+    v = _moving_view(16, 16)
+    out = torch.zeros((16, 16, 4), dtype=torch.float32, device="cuda")
+    with pytest.raises(bh.BhError) as e:
+        bh.bh_footprint_texels(gpu_ctx, gpu_tables, bh.make_view(v, h1), out.data_ptr())
+    assert e.value.status == bh.BH_EINVAL
     for h in (h1, h2, h3, h4):
         bh.bh_release_stars(h)
     for bad in ("negative", "nan", "inf"):
