@@ -812,8 +812,8 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
     }
     mip = Lv;
     float det = J00 * J11 - J01 * J10;
-    // band-colour star maps are read only by the band variant (AREA == 2)
-    const bool bands = AREA == 2 && S.bands;
+    // band-colour star maps are read only by the band variants (AREA 2 and 3)
+    const bool bands = AREA >= 2 && S.bands;
     float A = 0.0f, B = 0.0f, Cb = 0.0f;
     if (fabsf(det) >= 1e-20f) {
       float idet = fdiv(1.0f, det);
@@ -853,7 +853,7 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
       F.H0 = fmaf(i10, cu, i11 * cv);
       F.one = S.one;
       if (COUNT) req += 12;  // level offsets and scale
-      if constexpr (AREA == 2) {
+      if constexpr (AREA >= 2) {
         if (bands) {
           if (S.fp16)
             gather<kTexBand16, COUNT>(S.tex, F, cnt, req, A, B, Cb);
@@ -909,7 +909,7 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
 
   // ---- area sources: the footprint's mean radiance, one Doppler shift per pixel as for
   // stars, no lensing amplification (Section 3.4.1)
-  if (AREA && v.area.tex && !cap) {
+  if ((AREA == 1 || AREA == 2) && v.area.tex && !cap) {
     float A, B, Cc;
     if (AREA == 2 && v.area.bands) {
       // light of any colour: band sum S and chromaticity (r, g), shifted by C(r, g, D_cam)
@@ -1005,14 +1005,17 @@ static inline int xcd_grid(int tiles_x, int tiles_y) {
 
 // Resident waves per SIMD the one-launch and per-tile kernels are held to (the register
 // budget the compiler keeps to): 8, and 6 for the area-source variants, whose probe loop
-// spilled 20 vector registers to memory at 8 waves and ran 17% faster at 6 without spills.
+// spilled 20 vector registers to memory at 8 waves and ran 17% faster at 6 without spills,
+// 5 when they also read band colours.  Band star maps without area maps fit 8 (64 VGPRs).
 template <int FEAT>
-constexpr int kMinWaves = (FEAT & kFeatBands) ? 5 : ((FEAT & kFeatArea) ? 6 : 8);
+constexpr int kMinWaves = (FEAT & kFeatArea) ? ((FEAT & kFeatBands) ? 5 : 6) : 8;
 
-// the area code a feature set needs (render_pixel's AREA): 0 none, 1 (I, I T) maps only,
-// 2 band maps too (a run-time branch on the map's format)
+// the area and band code a feature set needs (render_pixel's AREA): 0 none, 1 (I, I T) area
+// maps, 2 area maps of either format and band star maps (run-time branches on the maps'
+// formats), 3 band star maps without area maps
 template <int FEAT>
-constexpr int kAreaOf = (FEAT & kFeatBands) ? 2 : ((FEAT & kFeatArea) ? 1 : 0);
+constexpr int kAreaOf =
+    (FEAT & kFeatBands) ? ((FEAT & kFeatArea) ? 2 : 3) : ((FEAT & kFeatArea) ? 1 : 0);
 
 // One launch per view, tiles in the XCD-aware order above.
 // At least 8 resident waves per SIMD: the register budget the compiler keeps to.  The
@@ -1219,7 +1222,7 @@ hipError_t scratch_address(void** p) {
 struct TileEntry {
   int tw, th, waves, ppt;
   // indexed by the features the views may use: kFeatParticles | kFeatArea | kFeatBands
-  // (kFeatBands comes with kFeatArea; entries 4 and 5 repeat 6 and 7)
+  // (kFeatBands alone: band star maps without area maps)
   void (*plain[8])(const ViewDev&, const TablesDev&, const LutDev&, hipStream_t);
   void (*batch[8])(const ViewDev*, const TileRun*, int, int, int*, const TablesDev&,
                    const LutDev&, int grid, hipStream_t);
@@ -1255,7 +1258,7 @@ static void launch_list(const ViewDev* views, const TileRun* runs, int nruns, in
 
 #define BH_FEATS(F, TW, TH, PPT)                                                          \
   {F<TW, TH, PPT, 0>, F<TW, TH, PPT, 1>, F<TW, TH, PPT, 2>, F<TW, TH, PPT, 3>,             \
-   F<TW, TH, PPT, 6>, F<TW, TH, PPT, 7>, F<TW, TH, PPT, 6>, F<TW, TH, PPT, 7>}
+   F<TW, TH, PPT, 4>, F<TW, TH, PPT, 5>, F<TW, TH, PPT, 6>, F<TW, TH, PPT, 7>}
 #define BH_TILE(TW, TH, PPT)                                                                \
   {TW, TH, TileCfg<TW, TH, PPT>::kWaves, PPT, BH_FEATS(launch_plain, TW, TH, PPT),          \
    BH_FEATS(launch_batch, TW, TH, PPT), BH_FEATS(launch_list, TW, TH, PPT)}

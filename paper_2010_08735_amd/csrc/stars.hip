@@ -270,7 +270,8 @@ __global__ void k_star_link_bands(const float* __restrict__ dirs, const float* _
   float d0 = dirs[3 * s], d1 = dirs[3 * s + 1], d2 = dirs[3 * s + 2];
   const float r = rgb[3 * s], g = rgb[3 * s + 1], b = rgb[3 * s + 2];
   // a negative, infinite or NaN band fails the whole build (the host reads `bad`)
-  if (!(r >= 0.0f && g >= 0.0f && b >= 0.0f) || isinf(r) || isinf(g) || isinf(b)) *bad = 1;
+  if (!(r >= 0.0f && g >= 0.0f && b >= 0.0f) || isinf(r) || isinf(g) || isinf(b))
+    atomicOr(bad, 1);
   // S > 0 exactly when a band is positive
   const bool lit = r > 0.0f || g > 0.0f || b > 0.0f;
   float a0 = fabsf(d0), a1 = fabsf(d1), a2 = fabsf(d2);
