@@ -263,3 +263,34 @@ def test_band_star_maps_shared_by_content_and_validated(gpu_ctx, gpu_tables, sma
     bh.bh_release_stars(hz)
     bh.bh_release_stars(hr)
     assert np.array_equal(ga, gb)
+
+
+def test_boosted_frame_band_stars_sampled(gpu_ctx, gpu_tables, orc, orc_tables, orc_ctable):
+    """The 1920x1080 frame of the camera at r = 6 moving at 0.9c under the one-million-star
+    field as band colours in a 6 x 2048^2 FP16 band map (the benchmark's configuration): a
+    seeded 1% of the quads against the oracle in table mode, with the full-frame tolerances
+    of the (I, T) star parity."""
+    dirs, rgb = scenes.star_field_bands(1_000_000, 1)
+    n0 = 2048
+    h = gpu_band_stars(gpu_ctx, dirs, rgb, n0)
+    try:
+        v = scenes.boosted_orbit_view()
+        out, aov = parity.render_gpu(gpu_ctx, gpu_tables, v, h)
+    finally:
+        bh.bh_release_stars(h)
+    cube = orc.cubemap_bands(dirs, rgb, n0)
+    quads = scenes.sample_quads(v.width, v.height, 0.01, 15)
+    pt = orc.render_quads(v, quads, cube=cube, n0=n0, tables=orc_tables, star_bands=True,
+                          ctable=orc_ctable)
+    del cube
+    g = parity.gpu_at(out, aov, pt)
+    st = parity.compare(pt, g, "table")
+    lit = (pt["n_cross"] == 0) & (pt["star_A"] > 0)
+    d = pt["d_cam"][lit]
+    _report({"boosted_band_stars": st, "d_cam": [float(d.min()), float(d.max())]})
+    assert np.isfinite(out).all() and st["masked_fraction"] < 0.02
+    assert d.min() < 0.7 and d.max() > 4.0
+    assert st["dprime_max"] < 1e-3 and st["dprime_p99"] < 1e-5 and st["u_max"] < 2e-4
+    assert parity.frac_within(pt, g, 1e-3, "disc") > 0.995
+    assert parity.frac_within(pt, g, 2e-2, "star") > 0.99
+    assert parity.frac_within(pt, g, 2e-2, "all") > 0.995
