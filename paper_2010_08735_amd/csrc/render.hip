@@ -735,7 +735,8 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
     if (anim) az0 = fatan2_any(t1, t0);
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-      if (k >= tr.ncross) break;
+      // a crossing behind an opaque one (transmittance exactly 0) adds nothing
+      if (k >= tr.ncross || !(trans > 0.0f)) break;
       float uk = k == 0 ? tr.ucr[0] : tr.ucr[1];
       float Tp = disc_temperature(v, uk);
       // 1 / k'^t = sqrt(1 - 3u/2) and Omega' = sqrt(u^3 / 2) on the circular orbit at u
@@ -815,7 +816,9 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
     // band-colour star maps are read only by the band variants (AREA 2 and 3)
     const bool bands = AREA >= 2 && S.bands;
     float A = 0.0f, B = 0.0f, Cb = 0.0f;
-    if (fabsf(det) >= 1e-20f) {
+    // behind an opaque disc crossing (transmittance exactly 0) the stars add nothing: their
+    // light is scaled by trans below, so the gather is skipped (the level above is kept)
+    if (fabsf(det) >= 1e-20f && trans > 0.0f) {
       float idet = fdiv(1.0f, det);
       Footprint F;
       // inverse face Jacobian
@@ -909,7 +912,7 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
 
   // ---- area sources: the footprint's mean radiance, one Doppler shift per pixel as for
   // stars, no lensing amplification (Section 3.4.1)
-  if ((AREA == 1 || AREA == 2) && v.area.tex && !cap) {
+  if ((AREA == 1 || AREA == 2) && v.area.tex && !cap && trans > 0.0f) {
     float A, B, Cc;
     if (AREA == 2 && v.area.bands) {
       // light of any colour: band sum S and chromaticity (r, g), shifted by C(r, g, D_cam)
