@@ -134,3 +134,33 @@ def test_generic_release_frees_every_handle_type(gpu_ctx):
             assert e.value.status == bh.BH_EINVAL
     finally:
         bh.bh_destroy(ctx)
+
+
+def test_opaque_disc_hides_stars_and_area_exactly(gpu_ctx, gpu_tables, small_scene):
+    """Behind an opaque disc crossing (transmittance exactly 0) star and area light are
+    multiplied by 0, which lets the kernel skip their gather and filter: every pixel with a
+    crossing has the same bits with and without the star map and area sky, pixels without
+    one do not; a semi-transparent disc lets star light through, so there the two differ."""
+    import torch
+    field, n0, h, cube = small_scene
+    it = scenes.area_map(32, 21)
+    t = torch.from_numpy(np.ascontiguousarray(it)).cuda()
+    ah = bh.bh_build_area(gpu_ctx, t.data_ptr(), 32, bh.current_stream())
+    torch.cuda.synchronize()
+    try:
+        v = scenes.boosted_orbit_view(256, 144)
+        v.k_area = 0.5
+        with_sky, aov = parity.render_gpu(gpu_ctx, gpu_tables, v, h, area=ah)
+        bare, _ = parity.render_gpu(gpu_ctx, gpu_tables, v, None)
+        bits = aov[..., 3].copy().view(np.uint32)
+        cross = (bits & 6) != 0
+        assert cross.mean() > 0.3 and (~cross).mean() > 0.2
+        assert np.array_equal(with_sky[cross].view(np.uint32), bare[cross].view(np.uint32))
+        assert (with_sky[~cross, :3] != bare[~cross, :3]).any(axis=1).mean() > 0.9
+        v.disc_opacity = 0.5
+        half_sky, _ = parity.render_gpu(gpu_ctx, gpu_tables, v, h, area=ah)
+        half_bare, _ = parity.render_gpu(gpu_ctx, gpu_tables, v, None)
+        seen = (half_sky[cross, :3] != half_bare[cross, :3]).any(axis=1)
+        assert seen.mean() > 0.9
+    finally:
+        bh.bh_release_area(ah)
