@@ -64,7 +64,7 @@ struct CountBufs {
   unsigned long long* l2_bytes;
 };
 
-template <int FMT, bool COUNT>
+template <int FMT, bool COUNT, bool PAIR = true>
 __device__ __forceinline__ void gather(const void* tex, const Footprint& F, const CountBufs* cnt,
                                        uint32_t& req, float& A, float& B, float& C) {
   uint32_t w0 = 0, w1 = 0, hi = 0;  // lo = w0 + 2^32 w1
@@ -109,68 +109,126 @@ __device__ __forceinline__ void gather(const void* tex, const Footprint& F, cons
   const Half8r* texb16 = (const Half8r*)tex + F.texel0;
   const float4* texb32 = (const float4*)tex + 2 * (size_t)F.texel0;
   const int nLm9 = F.nL - 9;
-  auto tap = [&](int idx) {
-    int r = (idx * 57) >> 9;  // idx / 9 for idx < 81
-    int c = idx - 9 * r;
-    uint32_t t = (uint32_t)(__mul24(r, nLm9) + idx);  // r nL + c, nL < 2^23
-    if (COUNT) {
-      uint32_t ta = F.texel0 + t;
-      atomicOr(&cnt->touched[ta >> 5], 1u << (ta & 31));
-      req += FMT == kTexIT16 ? 8 : (FMT == kTexBand32 ? 32 : 16);
+  // the texel of mask bit idx (row r, column c lies r nL + c = idx + r (nL - 9) texels from
+  // the footprint's corner)
+  auto at = [&](int idx) {
+    const int r = (idx * 57) >> 9;  // idx / 9 for idx < 81
+    return (uint32_t)(__mul24(r, nLm9) + idx);
+  };
+  struct Tx {  // one stored texel of any format
+    Half4r h4;
+    Half8r h8;
+    float4 f0, f1;
+  };
+  auto load = [&](uint32_t t) {
+    Tx x;
+    if constexpr (FMT == kTexIT16) x.h4 = tex16[t];
+    if constexpr (FMT == kTexIT32) x.f0 = tex32[t];
+    if constexpr (FMT == kTexBand16) x.h8 = texb16[t];
+    if constexpr (FMT == kTexBand32) {
+      x.f0 = texb32[2 * t];
+      x.f1 = texb32[2 * t + 1];
     }
+    return x;
+  };
+  // tent weight f(w) f(h) of the star of texel x at bit idx, 0 unless `use`, then the sums
+  auto weigh = [&](const Tx& x, int idx, bool use) {
+    const int r = (idx * 57) >> 9, c = idx - 9 * r;
     const float fc = (float)c, fr = (float)r;
-    if constexpr (FMT == kTexBand16) {
-      const Half8r hx = texb16[t];
-      float a = fmaf((float)hx.v[3], F.one, fc), b = fmaf((float)hx.v[4], F.one, fr);
-      float w = fmaf(F.Wc, a, fmaf(F.Wr, b, F.W0));
-      float h = fmaf(F.Hc, a, fmaf(F.Hr, b, F.H0));
-      float wt = __builtin_amdgcn_fmed3f(1.0f - fabsf(w), 0.0f, 1.0f) *
-                 __builtin_amdgcn_fmed3f(1.0f - fabsf(h), 0.0f, 1.0f);
-      A = fmaf(wt, (float)hx.v[0], A);
-      B = fmaf(wt, (float)hx.v[1], B);
-      C = fmaf(wt, (float)hx.v[2], C);
-    } else if constexpr (FMT == kTexBand32) {
-      const float4 x = texb32[2 * t], y = texb32[2 * t + 1];
-      float a = fc + x.w, b = fr + y.x;
-      float w = fmaf(F.Wc, a, fmaf(F.Wr, b, F.W0));
-      float h = fmaf(F.Hc, a, fmaf(F.Hr, b, F.H0));
-      float wt = __builtin_amdgcn_fmed3f(1.0f - fabsf(w), 0.0f, 1.0f) *
-                 __builtin_amdgcn_fmed3f(1.0f - fabsf(h), 0.0f, 1.0f);
-      A = fmaf(wt, x.x, A);
-      B = fmaf(wt, x.y, B);
-      C = fmaf(wt, x.z, C);
-    } else if constexpr (FMT == kTexIT16) {
+    float a, b;
+    if constexpr (FMT == kTexIT16) {
       // half operands go straight into mixed-precision multiply-adds
-      Half4r hx = tex16[t];
-      float a = fmaf((float)hx.z, F.one, fc), b = fmaf((float)hx.w, F.one, fr);
-      float w = fmaf(F.Wc, a, fmaf(F.Wr, b, F.W0));
-      float h = fmaf(F.Hc, a, fmaf(F.Hr, b, F.H0));
-      float wt = __builtin_amdgcn_fmed3f(1.0f - fabsf(w), 0.0f, 1.0f) *
-                 __builtin_amdgcn_fmed3f(1.0f - fabsf(h), 0.0f, 1.0f);  // max(1 - |x|, 0)
-      float wi = fmaf(wt, (float)hx.x, 0.0f);
-      A += wi;
-      B = fmaf(wi, (float)hx.y, B);
+      a = fmaf((float)x.h4.z, F.one, fc);
+      b = fmaf((float)x.h4.w, F.one, fr);
+    } else if constexpr (FMT == kTexIT32) {
+      a = fc + x.f0.z;
+      b = fr + x.f0.w;
+    } else if constexpr (FMT == kTexBand16) {
+      a = fmaf((float)x.h8.v[3], F.one, fc);
+      b = fmaf((float)x.h8.v[4], F.one, fr);
     } else {
-      float4 x = tex32[t];
-      float a = fc + x.z, b = fr + x.w;
-      float w = fmaf(F.Wc, a, fmaf(F.Wr, b, F.W0));
-      float h = fmaf(F.Hc, a, fmaf(F.Hr, b, F.H0));
-      float wt = __builtin_amdgcn_fmed3f(1.0f - fabsf(w), 0.0f, 1.0f) *
-                 __builtin_amdgcn_fmed3f(1.0f - fabsf(h), 0.0f, 1.0f);  // max(1 - |x|, 0)
-      float wi = wt * x.x;
+      a = fc + x.f0.w;
+      b = fr + x.f1.x;
+    }
+    const float w = fmaf(F.Wc, a, fmaf(F.Wr, b, F.W0));
+    const float h = fmaf(F.Hc, a, fmaf(F.Hr, b, F.H0));
+    float wt = __builtin_amdgcn_fmed3f(1.0f - fabsf(w), 0.0f, 1.0f) *
+               __builtin_amdgcn_fmed3f(1.0f - fabsf(h), 0.0f, 1.0f);  // max(1 - |x|, 0)
+    wt = use ? wt : 0.0f;
+    if constexpr (FMT == kTexIT16) {
+      const float wi = fmaf(wt, (float)x.h4.x, 0.0f);
       A += wi;
-      B = fmaf(wi, x.y, B);
+      B = fmaf(wi, (float)x.h4.y, B);
+    } else if constexpr (FMT == kTexIT32) {
+      const float wi = wt * x.f0.x;
+      A += wi;
+      B = fmaf(wi, x.f0.y, B);
+    } else if constexpr (FMT == kTexBand16) {
+      A = fmaf(wt, (float)x.h8.v[0], A);
+      B = fmaf(wt, (float)x.h8.v[1], B);
+      C = fmaf(wt, (float)x.h8.v[2], C);
+    } else {
+      A = fmaf(wt, x.f0.x, A);
+      B = fmaf(wt, x.f0.y, B);
+      C = fmaf(wt, x.f0.z, C);
     }
   };
-  while (lo) {
-    int idx = __builtin_ctzll(lo);
-    lo &= lo - 1u;
-    tap(idx);
-  }
-  while (hi) {
-    int idx = 63 + __builtin_ctz(hi);
-    hi &= hi - 1u;
-    tap(idx);
+  // Two taps per iteration, both texel loads in flight before either is weighed, so a lane
+  // waits on its scattered loads half as often.  With one tap left the second repeats the
+  // first texel with weight 0 and adds nothing: the sums take the taps in bit order.  Only
+  // the bit indices stay live across the loads (row and column are recomputed after).
+  auto two_taps = [&](int i0, int i1, bool two) {
+    if (COUNT) {
+      for (int k = 0; k < 2; ++k) {
+        if (k == 1 && !two) break;
+        const uint32_t ta = F.texel0 + at(k == 0 ? i0 : i1);
+        atomicOr(&cnt->touched[ta >> 5], 1u << (ta & 31));
+        req += FMT == kTexIT16 ? 8 : (FMT == kTexBand32 ? 32 : 16);
+      }
+    }
+    const Tx x0 = load(at(i0)), x1 = load(at(i1));
+    weigh(x0, i0, true);
+    weigh(x1, i1, two);
+  };
+  if constexpr (PAIR && (FMT == kTexIT16 || FMT == kTexIT32)) {
+    while (lo) {
+      const int i0 = __builtin_ctzll(lo);
+      lo &= lo - 1u;
+      const bool two = lo != 0;
+      const int i1 = two ? __builtin_ctzll(lo) : i0;
+      lo &= lo - 1u;  // 0 stays 0
+      two_taps(i0, i1, two);
+    }
+    while (hi) {
+      const int i0 = 63 + __builtin_ctz(hi);
+      hi &= hi - 1u;
+      const bool two = hi != 0;
+      const int i1 = two ? 63 + __builtin_ctz(hi) : i0;
+      hi &= hi - 1u;
+      two_taps(i0, i1, two);
+    }
+  } else {
+    // band texels are twice as wide: one tap per iteration keeps the band kernels' register
+    // budget (two in flight spilled 19 registers at 8 waves per SIMD), and the kernel for
+    // band star maps without area maps takes (I, T) maps one tap at a time too (PAIR)
+    auto one_tap = [&](int i) {
+      if (COUNT) {
+        const uint32_t ta = F.texel0 + at(i);
+        atomicOr(&cnt->touched[ta >> 5], 1u << (ta & 31));
+        req += FMT == kTexBand32 ? 32 : 16;
+      }
+      weigh(load(at(i)), i, true);
+    };
+    while (lo) {
+      const int i = __builtin_ctzll(lo);
+      lo &= lo - 1u;
+      one_tap(i);
+    }
+    while (hi) {
+      const int i = 63 + __builtin_ctz(hi);
+      hi &= hi - 1u;
+      one_tap(i);
+    }
   }
 }
 
@@ -866,9 +924,9 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
       }
       if (!bands) {
         if (S.fp16)
-          gather<kTexIT16, COUNT>(S.tex, F, cnt, req, A, B, Cb);
+          gather<kTexIT16, COUNT, AREA != 3>(S.tex, F, cnt, req, A, B, Cb);
         else
-          gather<kTexIT32, COUNT>(S.tex, F, cnt, req, A, B, Cb);
+          gather<kTexIT32, COUNT, AREA != 3>(S.tex, F, cnt, req, A, B, Cb);
       }
       const float iscale = S.scale[Lv];
       A *= iscale;
