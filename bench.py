@@ -363,7 +363,8 @@ def main():
     ap.add_argument("--serve-inflight", type=int, default=6,
                     help="serving launches kept in flight")
     ap.add_argument("--serve-tile-config", type=int, default=0,
-                    help="tile configuration index of the serving launches")
+                    help="tile configuration index of the serving launches (0: 16x16 "
+                         "tiles, the fastest for the mixed stream; -1: the library's default)")
     ap.add_argument("--serve-orbits", choices=("circular", "freefall"), default="circular",
                     help="serve leg cameras: circular orbits, or free fall (Appendix C)")
     args = ap.parse_args()
@@ -437,7 +438,7 @@ def main():
             "peak": (l2 if t_l2 > t_hbm else hbm)["peak"], "unit": "GB/s",
             "frac": t_roof / t_k, "t_roof_us": 1e6 * t_roof, "kernel_us": 1e6 * t_k,
             "traffic": prof["fetch_bytes"] + prof["write_bytes"] if prof else None,
-            "kernel": "k_render<16,16,1,0>", "kernel_ms": kernel_ms, "hbm": hbm, "l2": l2}
+            "kernel": "k_render<8,8,1,0>", "kernel_ms": kernel_ms, "hbm": hbm, "l2": l2}
     if prof is not None:
         flops = prof["fp32_flops_per_pixel"] * W * H
         tf = flops / t_k / 1e12

@@ -363,7 +363,8 @@ typedef struct {
 } bh_tile_config;
 int32_t bh_tile_config_count(void);
 bh_status bh_tile_config_get(int32_t index, bh_tile_config* out);
-/* Select the tile configuration used by bh_render / bh_render_batch (-1: built-in default) */
+/* Select the tile configuration used by bh_render / bh_render_batch and a later
+ * bh_serve_start (-1: the built-in default, 8x8 tiles of one pixel per thread, index 3) */
 bh_status bh_set_tile_config(bh_ctx* ctx, int32_t index);
 /* Select the launch form of the batched calls: 1 = persistent workgroups claiming tiles
  * from an atomic counter, 0 = one workgroup per tile (the default). */

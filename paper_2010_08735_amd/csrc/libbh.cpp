@@ -76,6 +76,9 @@ hipError_t launch_render_count(const ViewDev& v, const TablesDev& T, const LutDe
                                unsigned long long* l2_bytes, hipStream_t s);
 int tile_config_count();
 void tile_config(int i, int* tw, int* th, int* waves, int* ppt);
+// The tile configuration a context starts with: 8x8 tiles of one pixel per thread (index 3
+// of render.hip's table), the fastest for the 1080p frame and for uneven batches.
+constexpr int kDefaultTileCfg = 3;
 hipError_t scratch_address(void** p);
 hipError_t launch_l2_read(const float4* buf, int64_t n4, int per_wg, int grid, float* sink,
                           hipStream_t s);
@@ -208,7 +211,7 @@ struct bh_ctx {
   float4* ctab = nullptr;  // colour-shift table, built with the first band map
   int lut_n = 4096;
   float lut_x0 = 6.0f, lut_dx = 15.0f / 4095.0f;
-  int tile_cfg = 0;
+  int tile_cfg = kDefaultTileCfg;
   int persistent = 0;  // batched launches: 1 = persistent workgroups, 0 = one per tile
   // batched launches
   ViewDev* b_views = nullptr;
@@ -1281,7 +1284,7 @@ extern "C" bh_status bh_tile_config_get(int32_t i, bh_tile_config* o) {
 extern "C" bh_status bh_set_tile_config(bh_ctx* c, int32_t i) {
   if (!c || i < -1 || i >= tile_config_count()) return fail(BH_EINVAL, "bad tile config index");
   std::lock_guard<std::mutex> g(c->mu);
-  c->tile_cfg = i < 0 ? 0 : i;
+  c->tile_cfg = i < 0 ? kDefaultTileCfg : i;
   return BH_OK;
 }
 
