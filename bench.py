@@ -36,7 +36,7 @@ VALU_ISSUE_REF_G = 256 * 2.4
 WAVE_PIXELS = 64
 PROFILE = os.path.join(ROOT, "profiles", "k_render_1080p_summary.txt")
 KERNEL_SOURCES = ("paper_2010_08735_amd/csrc/render.hip", "paper_2010_08735_amd/csrc/bh_dev.h",
-                  "paper_2010_08735_amd/build.py")
+                  "paper_2010_08735_amd/csrc/libbh.cpp", "paper_2010_08735_amd/build.py")
 
 
 def kernel_profile():
