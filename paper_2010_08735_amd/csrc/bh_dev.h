@@ -138,6 +138,17 @@ __device__ __forceinline__ float clampf(float x, float lo, float hi) {
   return fminf(fmaxf(x, lo), hi);
 }
 
+// Streaming stores of results the kernel never reads back (images): marked non-temporal, so
+// they do not evict the tables and star-map lines the other waves still read from L2.
+__device__ __forceinline__ void store_stream(float4* p, float4 v) {
+  typedef float f4v __attribute__((ext_vector_type(4)));
+  const f4v x = {v.x, v.y, v.z, v.w};
+  __builtin_nontemporal_store(x, reinterpret_cast<f4v*>(p));
+}
+__device__ __forceinline__ void store_stream(uint32_t* p, uint32_t v) {
+  __builtin_nontemporal_store(v, p);
+}
+
 // ---- short math for the render path ----------------------------------------------------
 // Hardware square root and reciprocal (about 1 ulp each), for values whose rounding is not
 // amplified afterwards.

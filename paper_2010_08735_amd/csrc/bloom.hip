@@ -89,8 +89,8 @@ __global__ void __launch_bounds__(256)
   const int64_t i0 = (int64_t)blockIdx.x * 256 + threadIdx.x, i1 = i0 + step;
   const float4 a = i0 < n ? in[i0] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   const float4 b = i1 < n ? in[i1] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-  if (i0 < n) out[i0] = display_pixel(a, exposure);
-  if (i1 < n) out[i1] = display_pixel(b, exposure);
+  if (i0 < n) store_stream(&out[i0], display_pixel(a, exposure));
+  if (i1 < n) store_stream(&out[i1], display_pixel(b, exposure));
 }
 
 // ---- level building inside one 64 x 64 tile --------------------------------------------------
@@ -429,9 +429,9 @@ __global__ void __launch_bounds__(256)
     }
     const float4 o = f4_fma(w0, im[j], v);
     if constexpr (DISPLAY)
-      static_cast<uint32_t*>(out)[i] = display_pixel(o, exposure);
+      store_stream(&static_cast<uint32_t*>(out)[i], display_pixel(o, exposure));
     else
-      static_cast<float4*>(out)[i] = o;
+      store_stream(&static_cast<float4*>(out)[i], o);
   }
 }
 

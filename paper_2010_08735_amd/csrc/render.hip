@@ -1005,11 +1005,11 @@ __device__ __forceinline__ void render_pixel(const ViewDev& v, const TablesDev& 
   }
   if (px < v.width && py < v.height) {
     size_t idx = (size_t)py * v.width + px;
-    v.out[idx] = make_float4(cr, cg, cb, 1.0f);
+    store_stream(&v.out[idx], make_float4(cr, cg, cb, 1.0f));
     if (v.aov) {
       bits |= (unsigned)mip << 8;
-      v.aov[idx] = make_float4(captured ? __builtin_inff() : tr.dprime, tr.ucr[0], tr.ucr[1],
-                               __uint_as_float(bits));
+      store_stream(&v.aov[idx], make_float4(captured ? __builtin_inff() : tr.dprime, tr.ucr[0],
+                                             tr.ucr[1], __uint_as_float(bits)));
     }
   }
 }
